@@ -1,0 +1,211 @@
+/*
+ * localgs.h -- C ABI of the MI355X (gfx950) tile-based Gaussian-splatting
+ * rasterizer with the Local-GS render stages (arXiv 2606.16566).
+ *
+ * Pipeline (Sec. II-A, Fig. 2 of the paper):
+ *   lgs_project      -> projected 2D splats, depth keys, touched-tile rectangles
+ *   lgs_sort         -> (tile, Gaussian) pairs ordered by tile, then depth
+ *   lgs_tile_ranges  -> [start, end) of every tile's list
+ *   lgs_render       -> RGB image, final transmittance, last-contributor index
+ * plus the gradient path (lgs_render_backward, lgs_project_backward,
+ * lgs_l1_loss), which the paper does not cover.
+ *
+ * Conventions shared by every entry point
+ *  - Pointer arguments named as device buffers are device pointers owned by the
+ *    caller; the library never allocates or frees device memory.  Workspace
+ *    sizes come from the *_workspace_size queries.
+ *  - Arrays are row-major and contiguous, float32 / int32 / uint32 as typed.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work on that stream; none synchronises the host.
+ *  - Arguments are validated on the host before anything is enqueued; a failed
+ *    check returns LGS_ERR_INVALID_ARG and enqueues nothing.  A HIP launch
+ *    failure returns LGS_ERR_HIP.  lgs_last_error() then holds a message
+ *    (per host thread).  No C++ exception crosses this interface.
+ *  - Calls on different streams may run concurrently when their output
+ *    buffers are disjoint.
+ */
+#ifndef LOCALGS_H
+#define LOCALGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LGS_TILE 16
+
+typedef enum {
+    LGS_OK = 0,
+    LGS_ERR_INVALID_ARG = 1,
+    LGS_ERR_CAPACITY = 2,
+    LGS_ERR_HIP = 3,
+    LGS_ERR_UNSUPPORTED = 4
+} lgs_status;
+
+/*
+ * Pinhole camera, OpenCV axes (x right, y down, z forward).  Host struct,
+ * passed by pointer and copied at the call.
+ *   viewmat   world->camera [R | t], row-major 3x4
+ *   campos    camera centre in world space (direction of the SH colour)
+ *   fx, fy    focal lengths in pixels; cx, cy principal point in pixels.
+ *             Pixel (i, j) has its centre at image coordinates (i, j).
+ *   tan_fovx, tan_fovy   tangent of half the field of view; the projection
+ *             Jacobian is evaluated at points clamped to 1.3x these.
+ *   width, height        image size in pixels (>= 1)
+ *   znear     Gaussians with camera-space z <= znear are culled
+ *   bg        background colour blended behind the last Gaussian
+ */
+typedef struct lgs_camera {
+    float viewmat[12];
+    float campos[3];
+    float fx, fy, cx, cy;
+    float tan_fovx, tan_fovy;
+    int32_t width, height;
+    float znear;
+    float bg[3];
+} lgs_camera;
+
+/* Render-kernel variants: the cumulative ablation ladder of the paper
+ * (Table "ablation", Sec. IV-C).  OR with LGS_RENDER_FP32 for single-precision
+ * exponent and transmittance arithmetic (the paper's own precision); the
+ * default evaluates the exponent and the transmittance in double, which the
+ * gfx950 vector ALU issues at the same rate as single precision. */
+typedef enum {
+    LGS_RENDER_PLAIN = 0,       /* baseline per-pixel loop (Alg. 1, baseline column) */
+    LGS_RENDER_HOIST = 1,       /* + tile-local hoisted dot product (Sec. III-B) */
+    LGS_RENDER_HOIST_CULL = 2,  /* + wavefront-level tight-box culling (Sec. III-C) */
+    LGS_RENDER_LOCAL = 3,       /* + uniform blend, wave-wide termination vote (Sec. III-D) */
+    LGS_RENDER_FP32 = 0x10
+} lgs_render_variant;
+
+/* Message for the last non-OK status on the calling host thread. */
+const char *lgs_last_error(void);
+/* Library version string. */
+const char *lgs_version(void);
+
+/*
+ * lgs_project -- preprocessing of n 3D Gaussians for one camera (Sec. II-A,
+ * Fig. 2: projection to a 2D mean and covariance, footprint for tile culling).
+ *
+ * Inputs (device, raw parameters):
+ *   means3d [n,3], log_scales [n,3] (natural log of the per-axis standard
+ *   deviation), quats [n,4] (w, x, y, z; normalised inside), opacity_logits
+ *   [n] (opacity = sigmoid), sh [n,(sh_degree+1)^2,3] real SH coefficients.
+ *   sh_degree in 0..3.
+ * Outputs (device):
+ *   means2d [n,2]         projected mean in pixels
+ *   conic_opacity [n,4]   (a, b, c, o): inverse 2D covariance (with a 0.3 px^2
+ *                         low-pass added to the covariance) and opacity
+ *   rgb [n,3]             view-dependent colour, clamped at 0
+ *   depth [n]             depth key: the float32 rounding of camera-space z
+ *   rect [n,4]            touched tiles [tx0, ty0, tx1, ty1): the tiles
+ *                         holding a pixel centre of the alpha >= 1/255 ellipse;
+ *                         all zero for culled Gaussians
+ * Culled (rect empty, depth = +inf): z <= znear, opacity < 1/255, singular
+ * covariance, footprint outside the image, non-finite parameters.
+ */
+lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
+                       const float *means3d, const float *log_scales, const float *quats,
+                       const float *opacity_logits, const float *sh,
+                       float *means2d, float *conic_opacity, float *rgb, float *depth,
+                       int32_t *rect, void *stream);
+
+/*
+ * lgs_sort -- duplication of every visible Gaussian into one (tile, id) pair
+ * per touched tile and a stable sort so that each tile's pairs are in
+ * ascending (depth, id) order (Sec. II-A: prefix scan, key duplication,
+ * radix sort).  Implemented as a stable depth sort of the visible Gaussians,
+ * a scan of their tile counts, duplication in depth order and a stable radix
+ * sort on the tile id; the result equals a stable sort of 64-bit
+ * (tile << 32 | depth bits) keys emitted in id order.
+ *
+ * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
+ * Outputs (device):
+ *   tile_keys [capacity_pairs]  tile id of each pair, ascending
+ *   values    [capacity_pairs]  Gaussian id of each pair
+ *   num_pairs (device int64)    total pair count P (also when P > capacity)
+ *   overflow  (device int32)    set to 1 if P > capacity_pairs, else 0; then
+ *                               nothing past capacity_pairs is written and the
+ *                               pair lists are invalid (lgs_tile_ranges then
+ *                               yields empty tiles).  Grow and call again.
+ * workspace: device scratch of at least lgs_sort_workspace_size(...) bytes.
+ */
+size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int32_t num_tiles);
+lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
+                    uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                    int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
+                    void *stream);
+
+/*
+ * lgs_tile_ranges -- [start, end) of every tile's run in the sorted pairs
+ * (Sec. II-A, "tile ranges").  ranges [num_tiles,2] uint32 (device); tiles
+ * without pairs get (0, 0), and so do all tiles if *overflow != 0.
+ */
+lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, const int32_t *overflow,
+                           int64_t capacity_pairs, int32_t num_tiles, uint32_t *ranges, void *stream);
+
+/*
+ * lgs_render -- front-to-back alpha blending of every 16x16 tile (Sec. II-A
+ * render kernel; Local-GS stages of Sec. III).  For each pixel p, over its
+ * tile's list in order: alpha = min(0.99, o * exp(-q/2)) with
+ * q = a dx^2 + 2 b dx dy + c dy^2, d = p - mean; Gaussians with
+ * alpha < 1/255 are skipped; blending stops before the first Gaussian that
+ * would take the transmittance T below 1e-4; C += rgb * alpha * T.
+ * Inputs: ranges from lgs_tile_ranges, values from lgs_sort, projected
+ * attributes from lgs_project.  `variant` is an lgs_render_variant.
+ * Outputs (device): out_rgb [3,H,W] = C + T * bg; out_T [H,W] final T;
+ *   out_ncontrib [H,W] 1-based position, in the tile's list, of the last
+ *   blended Gaussian (0 if none).
+ * stats: NULL, or device uint64[8] that receives (added) counters:
+ *   [0] (wavefront, Gaussian) steps met by live wavefronts,
+ *   [1] of those, steps evaluated (not culled), [2] Gaussians staged,
+ *   [3] lane evaluations.  Counting runs a separate, slower instantiation.
+ */
+lgs_status lgs_render(int32_t variant, const lgs_camera *cam, const uint32_t *ranges, const uint32_t *values,
+                      const float *means2d, const float *conic_opacity, const float *rgb,
+                      float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats, void *stream);
+
+/*
+ * lgs_render_backward -- gradient of L through the blending, given
+ * grad_rgb = dL/d out_rgb [3,H,W] and optionally grad_T = dL/d out_T [H,W]
+ * (NULL = 0).  Replays each pixel back to front from its last contributor,
+ * recovering T from the stored final T.  Writes (overwrites) dL/d means2d
+ * [n,2], dL/d conic (a, b, c) [n,3], dL/d opacity [n], dL/d rgb [n,3];
+ * the clamp at 0.99 and all skip / stop decisions are held fixed.
+ * `variant` is LGS_RENDER_PLAIN or LGS_RENDER_LOCAL (hoisted, culled).
+ */
+lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam, int64_t n, const uint32_t *ranges,
+                               const uint32_t *values, const float *means2d, const float *conic_opacity,
+                               const float *rgb, const float *out_T, const int32_t *out_ncontrib,
+                               const float *grad_rgb, const float *grad_T,
+                               float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
+                               void *stream);
+
+/*
+ * lgs_project_backward -- chain rule from the projected attributes back to
+ * the raw parameters of lgs_project (same inputs, plus its rect output to
+ * know which Gaussians were culled).  Writes (overwrites) d_means3d [n,3],
+ * d_log_scales [n,3], d_quats [n,4], d_opacity_logits [n],
+ * d_sh [n,(deg+1)^2,3]; culled Gaussians get zero.
+ */
+lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_degree,
+                                const float *means3d, const float *log_scales, const float *quats,
+                                const float *opacity_logits, const float *sh, const int32_t *rect,
+                                const float *g_means2d, const float *g_conic, const float *g_opacity,
+                                const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
+
+/*
+ * lgs_l1_loss -- L = mean |image - target| over `count` floats and
+ * grad = dL/d image = sign(image - target) / count (0 where equal).
+ * loss: device float (overwritten); grad: device [count].
+ */
+lgs_status lgs_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOCALGS_H */

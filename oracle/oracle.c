@@ -454,6 +454,10 @@ static void blend_pixel(const splats_t *S, const int32_t *list, int64_t len, dou
         if (m1 < mmin) mmin = m1;
         double alpha = a_raw < ALPHA_MAX ? a_raw : ALPHA_MAX;
         if (alpha < ALPHA_MIN) continue;
+        /* the clamp at 0.99 does not change the colour continuously, but its
+           derivative switches there */
+        double m3 = fabs(la - log(ALPHA_MAX));
+        if (m3 < mmin) mmin = m3;
         double test = T * (1.0 - alpha);
         double m2 = fabs(log(test) - log(T_MIN));
         if (m2 < mmin) mmin = m2;
@@ -610,4 +614,36 @@ void oracle_render_backward(int W, int H, const int64_t *offsets, const int32_t 
             }
         }
     free(cid); free(ca); free(cT); free(cq); free(cclamp); free(suffix);
+}
+
+/*
+ * oracle_footprint: tile rectangle of splats given directly in screen space
+ * (mean, conic, opacity), with the same footprint rule as oracle_project:
+ * pixel centres of the ellipse q <= tau = 2 ln(255 o), clipped to the image.
+ */
+void oracle_footprint(int W, int H, int64_t n, const double *means2d, const double *conic, const double *opacity,
+                      int32_t *visible, int32_t *rect)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        visible[i] = 0;
+        for (int c = 0; c < 4; ++c) rect[4 * i + c] = 0;
+        double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
+        double det = a * c - b * b;
+        double tau = 2.0 * log(255.0 * opacity[i]);
+        if (!(det > 0.0) || !(tau > 0.0) || !(a > 0.0)) continue;
+        double sxx = c / det, syy = a / det;            /* covariance = inverse of the conic */
+        double tau_m = tau * (1.0 + FOOT_REL) + FOOT_ABS;
+        double rx = sqrt(tau_m * sxx) + FOOT_PX, ry = sqrt(tau_m * syy) + FOOT_PX;
+        double x0 = ceil(means2d[2 * i] - rx), x1 = floor(means2d[2 * i] + rx);
+        double y0 = ceil(means2d[2 * i + 1] - ry), y1 = floor(means2d[2 * i + 1] + ry);
+        if (!(isfinite(x0) && isfinite(x1) && isfinite(y0) && isfinite(y1))) continue;
+        if (x0 < 0) x0 = 0;
+        if (y0 < 0) y0 = 0;
+        if (x1 > W - 1) x1 = W - 1;
+        if (y1 > H - 1) y1 = H - 1;
+        if (x0 > x1 || y0 > y1) continue;
+        rect[4 * i] = (int)x0 / TILE; rect[4 * i + 1] = (int)y0 / TILE;
+        rect[4 * i + 2] = (int)x1 / TILE + 1; rect[4 * i + 3] = (int)y1 / TILE + 1;
+        visible[i] = 1;
+    }
 }

@@ -221,3 +221,19 @@ def scene_gradients(scene, gC, gT=None, view=0) -> dict:
                           scene.sh, g2["means2d"], g2["conic"], g2["opacity"], g2["rgb"])
     g3["projected"] = g2
     return g3
+
+
+def footprint(width, height, means2d, conic, opacity):
+    """(visible [n] int32, rect [n,4] int32) of screen-space splats."""
+    n = int(np.asarray(opacity).shape[0])
+    vis = np.zeros(n, np.int32)
+    rect = np.zeros((n, 4), np.int32)
+    lib().oracle_footprint(C.c_int(width), C.c_int(height), C.c_int64(n), _p(_f64(means2d)), _p(_f64(conic)),
+                           _p(_f64(opacity)), _p(vis), _p(rect))
+    return vis, rect
+
+
+def flagged(margin, guard):
+    """Pixels whose blend took a skip / stop decision within `guard` (log
+    space) of its threshold: either outcome is a correct result there."""
+    return np.asarray(margin) < guard

@@ -1,0 +1,428 @@
+// Preprocessing: projection of 3D Gaussians to screen-space splats, and its
+// gradient.  Sec. II-A / Fig. 2 of the paper (preprocessing stage, inherited
+// unchanged from 3DGS).  The stage streams the raw parameters once from HBM,
+// so its geometry runs in double precision at no cost in throughput on
+// gfx950 (full-rate FP64 FMA).
+#include "common.hpp"
+
+namespace lgs {
+namespace {
+
+// real SH constants (Condon-Shortley phase), as closed forms
+constexpr double kPi = 3.14159265358979323846;
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+struct ShConst {
+    double k0, k1, k2a, k2b, k2c, k3a, k3b, k3c, k3d, k3e;
+};
+__device__ __forceinline__ ShConst sh_consts()
+{
+    ShConst k;
+    k.k0 = 0.5 / sqrt(kPi);               // Y_0^0
+    k.k1 = sqrt(3.0 / (4.0 * kPi));       // degree 1
+    k.k2a = 0.5 * sqrt(15.0 / kPi);       // xy, yz, xz terms
+    k.k2b = 0.25 * sqrt(5.0 / kPi);       // 3z^2 - 1
+    k.k2c = 0.25 * sqrt(15.0 / kPi);      // x^2 - y^2
+    k.k3a = 0.25 * sqrt(35.0 / (2.0 * kPi));
+    k.k3b = 0.5 * sqrt(105.0 / kPi);
+    k.k3c = 0.25 * sqrt(21.0 / (2.0 * kPi));
+    k.k3d = 0.25 * sqrt(7.0 / kPi);
+    k.k3e = 0.25 * sqrt(105.0 / kPi);
+    return k;
+}
+
+// SH basis in index order l*l + l + m (m = -l..l) at unit direction (x, y, z);
+// optionally the gradient of each basis function w.r.t. (x, y, z).
+template <int DEG, bool GRAD>
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y, double (*dY)[3])
+{
+    const ShConst k = sh_consts();
+    Y[0] = k.k0;
+    if (GRAD) { dY[0][0] = dY[0][1] = dY[0][2] = 0.0; }
+    if (DEG >= 1) {
+        Y[1] = -k.k1 * y; Y[2] = k.k1 * z; Y[3] = -k.k1 * x;
+        if (GRAD) {
+            dY[1][0] = 0; dY[1][1] = -k.k1; dY[1][2] = 0;
+            dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = k.k1;
+            dY[3][0] = -k.k1; dY[3][1] = 0; dY[3][2] = 0;
+        }
+    }
+    if (DEG >= 2) {
+        Y[4] = k.k2a * x * y;
+        Y[5] = -k.k2a * y * z;
+        Y[6] = k.k2b * (3.0 * z * z - 1.0);
+        Y[7] = -k.k2a * x * z;
+        Y[8] = k.k2c * (x * x - y * y);
+        if (GRAD) {
+            dY[4][0] = k.k2a * y; dY[4][1] = k.k2a * x; dY[4][2] = 0;
+            dY[5][0] = 0; dY[5][1] = -k.k2a * z; dY[5][2] = -k.k2a * y;
+            dY[6][0] = 0; dY[6][1] = 0; dY[6][2] = 6.0 * k.k2b * z;
+            dY[7][0] = -k.k2a * z; dY[7][1] = 0; dY[7][2] = -k.k2a * x;
+            dY[8][0] = 2.0 * k.k2c * x; dY[8][1] = -2.0 * k.k2c * y; dY[8][2] = 0;
+        }
+    }
+    if (DEG >= 3) {
+        const double zz5 = 5.0 * z * z - 1.0;
+        Y[9] = -k.k3a * y * (3.0 * x * x - y * y);
+        Y[10] = k.k3b * x * y * z;
+        Y[11] = -k.k3c * y * zz5;
+        Y[12] = k.k3d * z * (5.0 * z * z - 3.0);
+        Y[13] = -k.k3c * x * zz5;
+        Y[14] = k.k3e * z * (x * x - y * y);
+        Y[15] = -k.k3a * x * (x * x - 3.0 * y * y);
+        if (GRAD) {
+            dY[9][0] = -k.k3a * 6.0 * x * y; dY[9][1] = -k.k3a * (3.0 * x * x - 3.0 * y * y); dY[9][2] = 0;
+            dY[10][0] = k.k3b * y * z; dY[10][1] = k.k3b * x * z; dY[10][2] = k.k3b * x * y;
+            dY[11][0] = 0; dY[11][1] = -k.k3c * zz5; dY[11][2] = -k.k3c * 10.0 * y * z;
+            dY[12][0] = 0; dY[12][1] = 0; dY[12][2] = k.k3d * (15.0 * z * z - 3.0);
+            dY[13][0] = -k.k3c * zz5; dY[13][1] = 0; dY[13][2] = -k.k3c * 10.0 * x * z;
+            dY[14][0] = 2.0 * k.k3e * x * z; dY[14][1] = -2.0 * k.k3e * y * z; dY[14][2] = k.k3e * (x * x - y * y);
+            dY[15][0] = -k.k3a * (3.0 * x * x - 3.0 * y * y); dY[15][1] = k.k3a * 6.0 * x * y; dY[15][2] = 0;
+        }
+    }
+}
+
+// Forward intermediates of one Gaussian, kept for the backward recompute.
+struct Proj {
+    bool visible;
+    double m[3], s[3], qn[4], qlen, o;
+    double t[3];
+    double R[3][3], M[3][3], S3[3][3];
+    double u, v;             // clamped tangent-plane coordinates
+    bool uc, vc;             // clamp active
+    double J00, J02, J11, J12;
+    double T[2][3];
+    double X, Y, Z;          // Sigma2 xx, yy, xy (with the low-pass)
+    double det;
+    double a, b, c;          // conic
+    double mx, my;           // projected mean
+    double dir[3], dlen;     // unit view direction and |mean - campos|
+};
+
+__device__ __forceinline__ bool all_finite(const float *p, int k)
+{
+    bool ok = true;
+    for (int i = 0; i < k; ++i) ok = ok && isfinite(p[i]);
+    return ok;
+}
+
+// Geometry of the projection (no colour).  Returns false if culled before
+// the footprint test.
+__device__ bool project_geometry(const Cam &cam, const float *m3, const float *ls, const float *qt, float logit,
+                                 Proj &P)
+{
+    if (!(all_finite(m3, 3) && all_finite(ls, 3) && all_finite(qt, 4) && isfinite(logit))) return false;
+    const float *V = cam.view;
+    for (int i = 0; i < 3; ++i) P.m[i] = m3[i];
+    // camera-space position; this FMA order defines the depth key
+    for (int k = 0; k < 3; ++k)
+        P.t[k] = fma((double)V[4 * k + 2], P.m[2], fma((double)V[4 * k + 1], P.m[1],
+                 fma((double)V[4 * k + 0], P.m[0], (double)V[4 * k + 3])));
+    if (!(P.t[2] > (double)cam.znear)) return false;
+    double q0 = qt[0], q1 = qt[1], q2 = qt[2], q3 = qt[3];
+    double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    if (!(n2 > 0.0)) return false;
+    P.qlen = sqrt(n2);
+    double inv = 1.0 / P.qlen;
+    double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+    P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
+    P.R[0][0] = 1.0 - 2.0 * (y * y + z * z); P.R[0][1] = 2.0 * (x * y - w * z); P.R[0][2] = 2.0 * (x * z + w * y);
+    P.R[1][0] = 2.0 * (x * y + w * z); P.R[1][1] = 1.0 - 2.0 * (x * x + z * z); P.R[1][2] = 2.0 * (y * z - w * x);
+    P.R[2][0] = 2.0 * (x * z - w * y); P.R[2][1] = 2.0 * (y * z + w * x); P.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    for (int j = 0; j < 3; ++j) P.s[j] = exp((double)ls[j]);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) P.M[i][j] = P.R[i][j] * P.s[j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            P.S3[i][j] = P.M[i][0] * P.M[j][0] + P.M[i][1] * P.M[j][1] + P.M[i][2] * P.M[j][2];
+    const double fx = cam.fx, fy = cam.fy;
+    const double limx = kGuard * (double)cam.tanx, limy = kGuard * (double)cam.tany;
+    const double tz = P.t[2], rz = 1.0 / tz;
+    double u = P.t[0] / tz, v = P.t[1] / tz;
+    P.uc = false; P.vc = false;
+    if (u < -limx) { u = -limx; P.uc = true; } else if (u > limx) { u = limx; P.uc = true; }
+    if (v < -limy) { v = -limy; P.vc = true; } else if (v > limy) { v = limy; P.vc = true; }
+    P.u = u; P.v = v;
+    P.J00 = fx * rz; P.J02 = -fx * u * rz; P.J11 = fy * rz; P.J12 = -fy * v * rz;
+    for (int j = 0; j < 3; ++j) {
+        P.T[0][j] = P.J00 * (double)V[0 * 4 + j] + P.J02 * (double)V[2 * 4 + j];
+        P.T[1][j] = P.J11 * (double)V[1 * 4 + j] + P.J12 * (double)V[2 * 4 + j];
+    }
+    double TS[2][3];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j)
+            TS[i][j] = P.T[i][0] * P.S3[0][j] + P.T[i][1] * P.S3[1][j] + P.T[i][2] * P.S3[2][j];
+    P.X = TS[0][0] * P.T[0][0] + TS[0][1] * P.T[0][1] + TS[0][2] * P.T[0][2] + kLowpass;
+    P.Y = TS[1][0] * P.T[1][0] + TS[1][1] * P.T[1][1] + TS[1][2] * P.T[1][2] + kLowpass;
+    P.Z = TS[0][0] * P.T[1][0] + TS[0][1] * P.T[1][1] + TS[0][2] * P.T[1][2];
+    P.det = P.X * P.Y - P.Z * P.Z;
+    if (!(P.det > 0.0)) return false;
+    const double id = 1.0 / P.det;
+    P.a = P.Y * id; P.b = -P.Z * id; P.c = P.X * id;
+    P.mx = fx * P.t[0] * rz + (double)cam.cx;
+    P.my = fy * P.t[1] * rz + (double)cam.cy;
+    P.o = 1.0 / (1.0 + exp(-(double)logit));
+    double d0 = P.m[0] - (double)cam.campos[0], d1 = P.m[1] - (double)cam.campos[1], d2 = P.m[2] - (double)cam.campos[2];
+    P.dlen = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (P.dlen > 0.0) { P.dir[0] = d0 / P.dlen; P.dir[1] = d1 / P.dlen; P.dir[2] = d2 / P.dlen; }
+    else { P.dir[0] = 0.0; P.dir[1] = 0.0; P.dir[2] = 1.0; }
+    return true;
+}
+
+// Tile rectangle of the footprint; false if it covers no pixel centre.
+__device__ bool footprint(const Cam &cam, const Proj &P, int4 &rect)
+{
+    double tau = 2.0 * log(255.0 * P.o);
+    if (!(tau > 0.0)) return false;
+    double tm = tau * (1.0 + kFootRel) + kFootAbs;
+    double rx = sqrt(tm * P.X) + kFootPx, ry = sqrt(tm * P.Y) + kFootPx;
+    double x0 = ceil(P.mx - rx), x1 = floor(P.mx + rx), y0 = ceil(P.my - ry), y1 = floor(P.my + ry);
+    if (!(isfinite(x0) && isfinite(x1) && isfinite(y0) && isfinite(y1))) return false;
+    x0 = fmax(x0, 0.0); y0 = fmax(y0, 0.0);
+    x1 = fmin(x1, (double)(cam.W - 1)); y1 = fmin(y1, (double)(cam.H - 1));
+    if (x0 > x1 || y0 > y1) return false;
+    rect.x = (int)x0 / kTile; rect.y = (int)y0 / kTile;
+    rect.z = (int)x1 / kTile + 1; rect.w = (int)y1 / kTile + 1;
+    return true;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+                                                          const float *__restrict__ log_scales,
+                                                          const float *__restrict__ quats,
+                                                          const float *__restrict__ logits,
+                                                          const float *__restrict__ sh, float2 *__restrict__ means2d,
+                                                          float4 *__restrict__ conic_opacity, float *__restrict__ rgb,
+                                                          float *__restrict__ depth, int4 *__restrict__ rect)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Proj P;
+    int4 r = make_int4(0, 0, 0, 0);
+    const float *shi = sh + i * (3 * K);
+    bool vis = project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P)
+               && all_finite(shi, 3 * K) && footprint(cam, P, r);
+    if (!vis) {
+        means2d[i] = make_float2(0.f, 0.f);
+        conic_opacity[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rgb[3 * i] = 0.f; rgb[3 * i + 1] = 0.f; rgb[3 * i + 2] = 0.f;
+        depth[i] = INFINITY;
+        rect[i] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    double Y[K];
+    sh_eval<DEG, false>(P.dir[0], P.dir[1], P.dir[2], Y, nullptr);
+    double col[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+    }
+    means2d[i] = make_float2((float)P.mx, (float)P.my);
+    conic_opacity[i] = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
+    for (int ch = 0; ch < 3; ++ch) rgb[3 * i + ch] = (float)fmax(col[ch], 0.0);
+    depth[i] = (float)P.t[2];
+    rect[i] = r;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+                                                          const float *__restrict__ log_scales,
+                                                          const float *__restrict__ quats,
+                                                          const float *__restrict__ logits,
+                                                          const float *__restrict__ sh, const int4 *__restrict__ rect,
+                                                          const float2 *__restrict__ g_means2d,
+                                                          const float *__restrict__ g_conic,
+                                                          const float *__restrict__ g_opacity,
+                                                          const float *__restrict__ g_rgb, float *__restrict__ d_means3d,
+                                                          float *__restrict__ d_log_scales, float *__restrict__ d_quats,
+                                                          float *__restrict__ d_logits, float *__restrict__ d_sh)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int4 r = rect[i];
+    Proj P;
+    const float *shi = sh + i * (3 * K);
+    float *dshi = d_sh + i * (3 * K);
+    bool vis = (r.z > r.x) && (r.w > r.y)
+               && project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P);
+    if (!vis) {
+        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = 0.f; d_log_scales[3 * i + k] = 0.f; }
+        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = 0.f;
+        d_logits[i] = 0.f;
+        for (int k = 0; k < 3 * K; ++k) dshi[k] = 0.f;
+        return;
+    }
+    const double gmx = g_means2d[i].x, gmy = g_means2d[i].y;
+    const double ga = g_conic[3 * i], gb = g_conic[3 * i + 1], gc = g_conic[3 * i + 2];
+    const double go = g_opacity[i];
+    double gcol[3] = {g_rgb[3 * i], g_rgb[3 * i + 1], g_rgb[3 * i + 2]};
+
+    // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
+    double Y[K], dY[K][3];
+    sh_eval<DEG, true>(P.dir[0], P.dir[1], P.dir[2], Y, dY);
+    double gdir[3] = {0.0, 0.0, 0.0};
+    for (int ch = 0; ch < 3; ++ch) {
+        double val = 0.5;
+        for (int k = 0; k < K; ++k) val += (double)shi[3 * k + ch] * Y[k];
+        if (val < 0.0) gcol[ch] = 0.0;
+    }
+    for (int k = 0; k < K; ++k) {
+        for (int ch = 0; ch < 3; ++ch) {
+            dshi[3 * k + ch] = (float)(gcol[ch] * Y[k]);
+            const double w = gcol[ch] * (double)shi[3 * k + ch];
+            gdir[0] += w * dY[k][0]; gdir[1] += w * dY[k][1]; gdir[2] += w * dY[k][2];
+        }
+    }
+    double gm[3] = {0.0, 0.0, 0.0};
+    if (P.dlen > 0.0) {
+        const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
+        for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - P.dir[k] * dd) / P.dlen;
+    }
+
+    // opacity = sigmoid(logit)
+    d_logits[i] = (float)(go * P.o * (1.0 - P.o));
+
+    // conic (a, b, c) = (Y, -Z, X) / det  ->  Sigma2 entries X, Y, Z
+    const double id = 1.0 / P.det, id2 = id * id;
+    const double gX = ga * (-P.Y * P.Y * id2) + gb * (P.Z * P.Y * id2) + gc * (id - P.X * P.Y * id2);
+    const double gY = ga * (id - P.Y * P.X * id2) + gb * (P.Z * P.X * id2) + gc * (-P.X * P.X * id2);
+    const double gZ = ga * (2.0 * P.Y * P.Z * id2) + gb * (-id - 2.0 * P.Z * P.Z * id2) + gc * (2.0 * P.X * P.Z * id2);
+    // symmetric gradient of Sigma2 = T Sigma3 T^T (+ low-pass)
+    const double G2[2][2] = {{gX, 0.5 * gZ}, {0.5 * gZ, gY}};
+    // dL/dSigma3 = T^T G2 T
+    double GT[2][3];
+    for (int i2 = 0; i2 < 2; ++i2)
+        for (int j = 0; j < 3; ++j) GT[i2][j] = G2[i2][0] * P.T[0][j] + G2[i2][1] * P.T[1][j];
+    double G3[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) G3[k][j] = P.T[0][k] * GT[0][j] + P.T[1][k] * GT[1][j];
+    // dL/dT = 2 G2 T Sigma3
+    double gT[2][3];
+    for (int i2 = 0; i2 < 2; ++i2)
+        for (int j = 0; j < 3; ++j)
+            gT[i2][j] = 2.0 * (GT[i2][0] * P.S3[0][j] + GT[i2][1] * P.S3[1][j] + GT[i2][2] * P.S3[2][j]);
+    // T = J W: dL/dJ[i][k] = sum_j gT[i][j] W[k][j]
+    const float *V = cam.view;
+    double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+    for (int j = 0; j < 3; ++j) {
+        gJ00 += gT[0][j] * (double)V[0 * 4 + j];
+        gJ02 += gT[0][j] * (double)V[2 * 4 + j];
+        gJ11 += gT[1][j] * (double)V[1 * 4 + j];
+        gJ12 += gT[1][j] * (double)V[2 * 4 + j];
+    }
+    const double fx = cam.fx, fy = cam.fy, tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    const double rz = 1.0 / tz, rz2 = rz * rz;
+    double gt[3] = {0.0, 0.0, 0.0};
+    // J00 = fx/tz, J11 = fy/tz
+    gt[2] += gJ00 * (-fx * rz2) + gJ11 * (-fy * rz2);
+    // J02 = -fx u / tz with u = tx/tz unless clamped
+    if (!P.uc) { gt[0] += gJ02 * (-fx * rz2); gt[2] += gJ02 * (2.0 * fx * tx * rz2 * rz); }
+    else gt[2] += gJ02 * (fx * P.u * rz2);
+    if (!P.vc) { gt[1] += gJ12 * (-fy * rz2); gt[2] += gJ12 * (2.0 * fy * ty * rz2 * rz); }
+    else gt[2] += gJ12 * (fy * P.v * rz2);
+    // projected mean
+    gt[0] += gmx * fx * rz; gt[2] += gmx * (-fx * tx * rz2);
+    gt[1] += gmy * fy * rz; gt[2] += gmy * (-fy * ty * rz2);
+    // t = W m + t_c
+    for (int k = 0; k < 3; ++k)
+        gm[k] += (double)V[0 * 4 + k] * gt[0] + (double)V[1 * 4 + k] * gt[1] + (double)V[2 * 4 + k] * gt[2];
+    for (int k = 0; k < 3; ++k) d_means3d[3 * i + k] = (float)gm[k];
+
+    // Sigma3 = M M^T, M = R diag(s): dL/dM = 2 G3 M
+    double gR[3][3], gs[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const double gM = 2.0 * (G3[a][0] * P.M[0][b] + G3[a][1] * P.M[1][b] + G3[a][2] * P.M[2][b]);
+            gR[a][b] = gM * P.s[b];
+            gs[b] += gM * P.R[a][b];
+        }
+    for (int k = 0; k < 3; ++k) d_log_scales[3 * i + k] = (float)(gs[k] * P.s[k]);
+    // rotation matrix of the unit quaternion
+    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    double gq[4];
+    gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0]
+                   + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    gq[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0]
+                   + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    gq[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1]
+                   + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    // normalisation q / |q|
+    const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+    d_quats[4 * i + 0] = (float)((gq[0] - w * dq) / P.qlen);
+    d_quats[4 * i + 1] = (float)((gq[1] - x * dq) / P.qlen);
+    d_quats[4 * i + 2] = (float)((gq[2] - y * dq) / P.qlen);
+    d_quats[4 * i + 3] = (float)((gq[3] - z * dq) / P.qlen);
+}
+
+}  // namespace
+}  // namespace lgs
+
+using namespace lgs;
+
+extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t sh_degree, const float *means3d,
+                                  const float *log_scales, const float *quats, const float *opacity_logits,
+                                  const float *sh, float *means2d, float *conic_opacity, float *rgb, float *depth,
+                                  int32_t *rect, void *stream)
+{
+    Cam cam;
+    LGS_REQUIRE(cam_from(camera, cam), "lgs_project: invalid camera");
+    LGS_REQUIRE(n >= 0, "lgs_project: n < 0");
+    LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project: sh_degree must be 0..3");
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh, "lgs_project: null input");
+    LGS_REQUIRE(means2d && conic_opacity && rgb && depth && rect, "lgs_project: null output");
+    LGS_REQUIRE(((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0) && ((uintptr_t)rect % 16 == 0),
+                "lgs_project: means2d must be 8-byte and conic_opacity/rect 16-byte aligned");
+    hipStream_t s = as_stream(stream);
+    const dim3 grid(grid_for(n, 256)), block(256);
+    auto *m2 = reinterpret_cast<float2 *>(means2d);
+    auto *co = reinterpret_cast<float4 *>(conic_opacity);
+    auto *rc = reinterpret_cast<int4 *>(rect);
+    switch (sh_degree) {
+    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
+    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
+    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
+    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
+    }
+    LGS_LAUNCHED("lgs_project");
+    return LGS_OK;
+}
+
+extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, int32_t sh_degree,
+                                           const float *means3d, const float *log_scales, const float *quats,
+                                           const float *opacity_logits, const float *sh, const int32_t *rect,
+                                           const float *g_means2d, const float *g_conic, const float *g_opacity,
+                                           const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                           float *d_quats, float *d_opacity_logits, float *d_sh, void *stream)
+{
+    Cam cam;
+    LGS_REQUIRE(cam_from(camera, cam), "lgs_project_backward: invalid camera");
+    LGS_REQUIRE(n >= 0, "lgs_project_backward: n < 0");
+    LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project_backward: sh_degree must be 0..3");
+    if (n == 0) return LGS_OK;
+    LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh && rect, "lgs_project_backward: null input");
+    LGS_REQUIRE(g_means2d && g_conic && g_opacity && g_rgb, "lgs_project_backward: null gradient input");
+    LGS_REQUIRE(d_means3d && d_log_scales && d_quats && d_opacity_logits && d_sh, "lgs_project_backward: null output");
+    LGS_REQUIRE(((uintptr_t)g_means2d % 8 == 0) && ((uintptr_t)rect % 16 == 0),
+                "lgs_project_backward: g_means2d must be 8-byte and rect 16-byte aligned");
+    hipStream_t s = as_stream(stream);
+    const dim3 grid(grid_for(n, 256)), block(256);
+    auto *rc = reinterpret_cast<const int4 *>(rect);
+    auto *gm = reinterpret_cast<const float2 *>(g_means2d);
+#define LGS_PB(D)                                                                                                   \
+    hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, \
+                       sh, rc, gm, g_conic, g_opacity, g_rgb, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
+    switch (sh_degree) {
+    case 0: LGS_PB(0); break;
+    case 1: LGS_PB(1); break;
+    case 2: LGS_PB(2); break;
+    default: LGS_PB(3); break;
+    }
+#undef LGS_PB
+    LGS_LAUNCHED("lgs_project_backward");
+    return LGS_OK;
+}

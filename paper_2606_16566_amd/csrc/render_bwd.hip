@@ -1,0 +1,289 @@
+// Backward of the blending stage (not part of the paper, which covers
+// inference only).  For pixel p with contributors k (front to back), alpha_k,
+// T_k = prod_{j<k} (1 - alpha_j) and final transmittance T_f:
+//   C = sum_k c_k alpha_k T_k + T_f bg
+//   dC/dc_k      = alpha_k T_k
+//   dC/dalpha_k  = c_k T_k - R_k / (1 - alpha_k),  R_k = sum_{i>k} c_i alpha_i T_i + T_f bg
+//   dT_f/dalpha_k = -T_f / (1 - alpha_k)
+// The replay walks each tile's list back to front from the largest last-
+// contributor position in the workgroup, recovering T_k = T_{k+1} / (1 -
+// alpha_k) from the stored final T and accumulating R_k on the way.  Through
+// alpha = o exp(-q/2) (unclamped): dalpha/do = alpha/o, dalpha/dq = -alpha/2,
+// dq/dmean = -2 K d, dq/d(a, b, c) = (dx^2, 2 dx dy, dy^2).
+//
+// The LOCAL variant reuses the forward's hoisting and wavefront culling: each
+// wavefront visits, in reverse, only the entries whose strip bit is set.  The
+// nine per-Gaussian partial gradients are summed across the wavefront, then
+// across the four wavefronts in LDS, and flushed with one atomic per
+// (tile, Gaussian, component).
+#include "common.hpp"
+
+namespace lgs {
+namespace {
+
+constexpr float kLog2AlphaMinB = -7.99435343685885793f;
+constexpr int kNG = 9;   // mean x, y; conic a, b, c; opacity; r, g, b
+
+struct BwdArgs {
+    const uint2 *ranges;
+    const uint32_t *values;
+    const float2 *means2d;
+    const float4 *conic_opacity;
+    const float *rgb;
+    const float *out_T;
+    const int32_t *out_nc;
+    const float *grad_rgb;
+    const float *grad_T;
+    float *g_means2d, *g_conic, *g_opacity, *g_rgb;
+    int W, H, tiles_x, num_tiles;
+    float bg0, bg1, bg2;
+};
+
+__device__ __forceinline__ int xcd_tile_b(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// same tight-box mask as the forward (Sec. III-C-2)
+__device__ __forceinline__ uint32_t strip_mask_b(double a, double b, double c, double tau, double x0, double x1,
+                                                 double my, int ty0, int H)
+{
+    if (!(tau > 0.0)) return 0u;
+    const double det = a * c - b * b;
+    if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return 0xFu;
+    const double dy = sqrt(a * tau / det);
+    double ymax, ymin;
+    if (-b * dy < a * x0) {
+        const double arg = c * tau - det * x0 * x0;
+        if (arg < 0.0) return 0u;
+        ymax = (-b * x0 + sqrt(arg)) / c;
+    } else if (-b * dy > a * x1) {
+        const double arg = c * tau - det * x1 * x1;
+        if (arg < 0.0) return 0u;
+        ymax = (-b * x1 + sqrt(arg)) / c;
+    } else {
+        ymax = dy;
+    }
+    if (b * dy < a * x0) {
+        const double arg = c * tau - det * x0 * x0;
+        if (arg < 0.0) return 0u;
+        ymin = (-b * x0 - sqrt(arg)) / c;
+    } else if (b * dy > a * x1) {
+        const double arg = c * tau - det * x1 * x1;
+        if (arg < 0.0) return 0u;
+        ymin = (-b * x1 - sqrt(arg)) / c;
+    } else {
+        ymin = -dy;
+    }
+    const double lo = ceil(my + ymin - 1e-3), hi = floor(my + ymax + 1e-3);
+    int r0 = (int)fmax(lo, (double)ty0), r1 = (int)fmin(hi, (double)(ty0 + kTile - 1));
+    if (r1 > H - 1) r1 = H - 1;
+    if (!(lo <= (double)(ty0 + kTile - 1)) || !(hi >= (double)ty0) || r0 > r1) return 0u;
+    const int w0 = (r0 - ty0) >> 2, w1 = (r1 - ty0) >> 2;
+    return ((1u << (w1 - w0 + 1)) - 1u) << w0;
+}
+
+template <bool LOCAL>
+__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
+{
+    __shared__ double s_v[kBlock][6];        // hoisted exponent coefficients
+    __shared__ float4 s_co[kBlock];          // a, b, c, o
+    __shared__ float2 s_mu[kBlock];          // mean
+    __shared__ float4 s_c[kBlock];           // colour
+    __shared__ uint32_t s_id[kBlock];
+    __shared__ uint8_t s_m[kBlock];
+    __shared__ float s_g[kNG][kBlock];
+    __shared__ int s_max[kBlock / 64];
+
+    const int tile = xcd_tile_b(blockIdx.x, a.num_tiles);
+    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int lx = lane & 15, ly = (wid << 2) | (lane >> 4);
+    const int px = tx * kTile + lx, py = ty * kTile + ly;
+    const bool inside = px < a.W && py < a.H;
+    const double ox = tx * kTile + 7.5, oy = ty * kTile + 7.5;
+    const double xl = lx - 7.5, yl = ly - 7.5;
+    const double bxx = xl * xl, bxy = xl * yl, byy = yl * yl;
+
+    const int64_t HW = (int64_t)a.W * a.H;
+    const int64_t p = (int64_t)py * a.W + px;
+    const int last = inside ? a.out_nc[p] : 0;
+    const double Tf = inside ? (double)a.out_T[p] : 1.0;
+    double T = Tf;
+    const float gc0 = inside ? a.grad_rgb[p] : 0.f, gc1 = inside ? a.grad_rgb[HW + p] : 0.f,
+                gc2 = inside ? a.grad_rgb[2 * HW + p] : 0.f;
+    const double gt = (inside && a.grad_T) ? (double)a.grad_T[p] : 0.0;
+    double R0 = Tf * a.bg0, R1 = Tf * a.bg1, R2 = Tf * a.bg2;
+
+    int wmax = last;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) wmax = max(wmax, __shfl_xor(wmax, off, 64));
+    if (lane == 0) s_max[wid] = wmax;
+    __syncthreads();
+    const int bmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+    const uint2 range = a.ranges[tile];
+    const uint32_t end = range.x + (uint32_t)bmax;
+
+    for (int64_t bend = end; bend > (int64_t)range.x; bend -= kBlock) {
+        const uint32_t bstart = (uint32_t)max((int64_t)range.x, bend - kBlock);
+        const int nb = (int)(bend - bstart);
+        __syncthreads();                                   // previous batch fully flushed
+        if ((int)threadIdx.x < nb) {
+            const int k = threadIdx.x;
+            const uint32_t g = a.values[bstart + k];
+            const float2 m = a.means2d[g];
+            const float4 co = a.conic_opacity[g];
+            s_id[k] = g;
+            s_mu[k] = m;
+            s_co[k] = co;
+            s_c[k] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], 0.f);
+            const float lo = __builtin_amdgcn_logf(co.w);
+            if (LOCAL) {
+                const double L = kLog2e, ca = co.x, cb = co.y, cc = co.z;
+                const double dx = (double)m.x - ox, dy = (double)m.y - oy;
+                s_v[k][0] = -0.5 * L * ca;
+                s_v[k][1] = -L * cb;
+                s_v[k][2] = -0.5 * L * cc;
+                s_v[k][3] = L * (ca * dx + cb * dy);
+                s_v[k][4] = L * (cb * dx + cc * dy);
+                s_v[k][5] = (double)lo - 0.5 * L * (ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy);
+                const double tau = 2.0 * ((double)lo - (double)kLog2AlphaMinB) / kLog2e * (1.0 + 1e-6) + 1e-5;
+                const double x0 = (double)(tx * kTile) - (double)m.x;
+                s_m[k] = (uint8_t)strip_mask_b(co.x, co.y, co.z, tau, x0, x0 + (kTile - 1), (double)m.y, ty * kTile,
+                                               a.H);
+            } else {
+                s_v[k][5] = (double)lo;
+                s_m[k] = 0xF;
+            }
+#pragma unroll
+            for (int f = 0; f < kNG; ++f) s_g[f][k] = 0.f;
+        }
+        __syncthreads();
+
+        // wavefront's own range: skip entries past its last contributor
+        const int wlimit = (int)min((int64_t)nb, (int64_t)range.x + wmax - (int64_t)bstart);
+        for (int c0 = ((wlimit - 1) >> 6) << 6; wlimit > 0 && c0 >= 0; c0 -= 64) {
+            const int j = c0 + lane;
+            const bool bit = j < wlimit && ((s_m[j] >> wid) & 1u);
+            uint64_t bits = __ballot(bit);
+            while (bits) {
+                const int kk = 63 - __builtin_clzll(bits);
+                bits &= ~(1ull << kk);
+                const int k = c0 + kk;
+                const int pos1 = (int)(bstart + k - range.x) + 1;
+                const float4 co = s_co[k];
+                const float2 m = s_mu[k];
+                const double dx = (double)px - (double)m.x, dy = (double)py - (double)m.y;
+                double s;
+                if (LOCAL) {
+                    s = fma(s_v[k][0], bxx, fma(s_v[k][1], bxy, fma(s_v[k][2], byy,
+                        fma(s_v[k][3], xl, fma(s_v[k][4], yl, s_v[k][5])))));
+                } else {
+                    const double q = (double)co.x * dx * dx + 2.0 * (double)co.y * dx * dy + (double)co.z * dy * dy;
+                    s = s_v[k][5] - 0.5 * kLog2e * q;
+                }
+                const float s32 = (float)s;
+                const float raw = __builtin_amdgcn_exp2f(s32);
+                const bool act = pos1 <= last && s32 >= kLog2AlphaMinB;
+                float g[kNG];
+#pragma unroll
+                for (int f = 0; f < kNG; ++f) g[f] = 0.f;
+                if (act) {
+                    const bool clamped = !(raw < kAlphaMax);
+                    const double al = clamped ? (double)kAlphaMax : (double)raw;
+                    const double om = 1.0 - al;
+                    T = T / om;                                  // T before this Gaussian
+                    const double w = al * T;
+                    const float4 f = s_c[k];
+                    double dLda = (double)gc0 * ((double)f.x * T - R0 / om) + (double)gc1 * ((double)f.y * T - R1 / om)
+                                  + (double)gc2 * ((double)f.z * T - R2 / om) - gt * Tf / om;
+                    R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
+                    g[6] = (float)(gc0 * w); g[7] = (float)(gc1 * w); g[8] = (float)(gc2 * w);
+                    if (!clamped) {
+                        const double dLdq = -0.5 * al * dLda;
+                        const double ca = co.x, cb = co.y, cc = co.z;
+                        g[0] = (float)(-2.0 * dLdq * (ca * dx + cb * dy));
+                        g[1] = (float)(-2.0 * dLdq * (cb * dx + cc * dy));
+                        g[2] = (float)(dLdq * dx * dx);
+                        g[3] = (float)(dLdq * 2.0 * dx * dy);
+                        g[4] = (float)(dLdq * dy * dy);
+                        g[5] = (float)(dLda * al / (double)co.w);
+                    }
+                }
+                if (__ballot(act) != 0ull) {
+#pragma unroll
+                    for (int f = 0; f < kNG; ++f) {
+                        const float sum = wave_sum(g[f]);
+                        if (lane == 0 && sum != 0.f) atomicAdd(&s_g[f][k], sum);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            const int k = threadIdx.x;
+            const uint32_t gid = s_id[k];
+            float v;
+            if ((v = s_g[0][k]) != 0.f) unsafeAtomicAdd(&a.g_means2d[2 * gid], v);
+            if ((v = s_g[1][k]) != 0.f) unsafeAtomicAdd(&a.g_means2d[2 * gid + 1], v);
+            if ((v = s_g[2][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid], v);
+            if ((v = s_g[3][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid + 1], v);
+            if ((v = s_g[4][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid + 2], v);
+            if ((v = s_g[5][k]) != 0.f) unsafeAtomicAdd(&a.g_opacity[gid], v);
+            if ((v = s_g[6][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid], v);
+            if ((v = s_g[7][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid + 1], v);
+            if ((v = s_g[8][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid + 2], v);
+        }
+    }
+}
+
+}  // namespace
+}  // namespace lgs
+
+using namespace lgs;
+
+extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *camera, int64_t n, const uint32_t *ranges,
+                                          const uint32_t *values, const float *means2d, const float *conic_opacity,
+                                          const float *rgb, const float *out_T, const int32_t *out_ncontrib,
+                                          const float *grad_rgb, const float *grad_T, float *g_means2d, float *g_conic,
+                                          float *g_opacity, float *g_rgb, void *stream)
+{
+    Cam cam;
+    LGS_REQUIRE(cam_from(camera, cam), "lgs_render_backward: invalid camera");
+    const int v = variant & 0xF;
+    LGS_REQUIRE(v == LGS_RENDER_PLAIN || v == LGS_RENDER_LOCAL, "lgs_render_backward: variant must be PLAIN or LOCAL");
+    LGS_REQUIRE(n >= 0, "lgs_render_backward: n < 0");
+    LGS_REQUIRE(ranges && out_T && out_ncontrib && grad_rgb, "lgs_render_backward: null input");
+    LGS_REQUIRE(n == 0 || (values && means2d && conic_opacity && rgb && g_means2d && g_conic && g_opacity && g_rgb),
+                "lgs_render_backward: null argument");
+    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0),
+                "lgs_render_backward: misaligned ranges/means2d/conic_opacity");
+    hipStream_t s = as_stream(stream);
+    fill_async<float>(g_means2d, 0.f, 2 * n, s);
+    fill_async<float>(g_conic, 0.f, 3 * n, s);
+    fill_async<float>(g_opacity, 0.f, n, s);
+    fill_async<float>(g_rgb, 0.f, 3 * n, s);
+    BwdArgs a;
+    a.ranges = reinterpret_cast<const uint2 *>(ranges);
+    a.values = values;
+    a.means2d = reinterpret_cast<const float2 *>(means2d);
+    a.conic_opacity = reinterpret_cast<const float4 *>(conic_opacity);
+    a.rgb = rgb; a.out_T = out_T; a.out_nc = out_ncontrib; a.grad_rgb = grad_rgb; a.grad_T = grad_T;
+    a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
+    a.W = cam.W; a.H = cam.H; a.tiles_x = cam.tiles_x; a.num_tiles = cam.tiles_x * cam.tiles_y;
+    a.bg0 = cam.bg[0]; a.bg1 = cam.bg[1]; a.bg2 = cam.bg[2];
+    if (v == LGS_RENDER_LOCAL)
+        hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.num_tiles), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.num_tiles), dim3(kBlock), 0, s, a);
+    LGS_LAUNCHED("lgs_render_backward");
+    return LGS_OK;
+}

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every entry point the header declares;
+host-side argument checks reject bad calls before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "localgs.h")
+
+
+def _lib():
+    from paper_2606_16566_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return L
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lgs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_pipeline():
+    names = declared()
+    for must in ["lgs_project", "lgs_sort", "lgs_tile_ranges", "lgs_render", "lgs_render_backward",
+                 "lgs_project_backward", "lgs_l1_loss", "lgs_sort_workspace_size", "lgs_last_error"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lb = C.CDLL(L.LIB_PATH)
+    for name in declared():
+        assert hasattr(lb, name), name
+    assert set(L.EXPORTS) >= set(declared())
+
+
+def test_version_and_workspace_query():
+    L = _lib()
+    assert L.lib().lgs_version().startswith(b"localgs")
+    a = L.lib().lgs_sort_workspace_size(1000, 5000, 100)
+    b = L.lib().lgs_sort_workspace_size(100000, 5000000, 100)
+    assert 0 < a < b and a % 256 == 0
+    assert L.lib().lgs_sort_workspace_size(-1, 10, 10) == 0
+
+
+def test_invalid_arguments_rejected_on_host():
+    L = _lib()
+    cam = L.LgsCamera()
+    cam.width, cam.height, cam.fx, cam.fy = 0, 10, 100.0, 100.0          # width 0: invalid
+    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 11))
+    assert st == L.LGS_ERR_INVALID_ARG
+    assert b"camera" in L.lib().lgs_last_error()
+    cam.width = 16
+    st = L.lib().lgs_project(C.byref(cam), 10, 5, *([None] * 11))     # sh degree 5
+    assert st == L.LGS_ERR_INVALID_ARG
+    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 11))     # null pointers
+    assert st == L.LGS_ERR_INVALID_ARG and b"null" in L.lib().lgs_last_error()
+    st = L.lib().lgs_render(7, C.byref(cam), *([None] * 10))            # unknown variant
+    assert st == L.LGS_ERR_INVALID_ARG
+    st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, 100, None, None, None, 0, None)
+    assert st == L.LGS_ERR_INVALID_ARG
+    st = L.lib().lgs_l1_loss(None, None, 0, None, None, None)
+    assert st == L.LGS_ERR_INVALID_ARG
+
+
+def test_variant_codes():
+    from paper_2606_16566_amd import rasterizer as R
+    L = _lib()
+    assert R.variant_code("plain") == L.RENDER_PLAIN
+    assert R.variant_code("local") == L.RENDER_LOCAL
+    assert R.variant_code("hoist_cull_fp32") == L.RENDER_HOIST_CULL | L.RENDER_FP32
