@@ -40,7 +40,44 @@ def parse():
     ap.add_argument("--baseline", default="plain")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--extra", action="store_true", help="also time every render variant")
+    ap.add_argument("--no-fwdbwd", action="store_true", help="skip the forward+backward workload")
     return ap.parse_args()
+
+
+def time_fwdbwd(args, R, scenes, torch, np):
+    """Forward + L1 loss + backward through the autograd Function on the
+    3M-Gaussian 1920x1080 workload (SH degree 0), Local vs Plain."""
+    dev = torch.device("cuda:0")
+    sc = scenes.make_config(4)
+    cam = sc.cameras[0]
+    params = [torch.from_numpy(a).to(dev).requires_grad_() for a in
+              (sc.means3d, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh)]
+    target = torch.from_numpy(scenes.make_target(cam.height, cam.width, 104)).to(dev)
+    binner = R.Binner(capacity=0)
+    R.rasterize(cam, *[p.detach() for p in params], variant="local", binner=binner, check_overflow=True)
+    torch.cuda.synchronize()
+    res = {}
+    for variant in ("local", "plain"):
+        def step():
+            for p in params:
+                p.grad = None
+            img, T, nc = R.LocalGSFunction.apply(*params, cam, variant, binner)
+            loss, g = R.l1_loss(img.detach(), target)
+            img.backward(g)
+            return loss
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        steps = max(3, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[variant] = {"ms_per_step": ms, "mpix_s": cam.width * cam.height / (ms * 1e-3) / 1e6}
+    res["local_over_plain"] = res["local"]["mpix_s"] / res["plain"]["mpix_s"]
+    res["workload"] = f"{scenes.CONFIG_NAMES[4]}: forward + L1 loss + backward to raw parameters"
+    return res
 
 
 def main():
@@ -111,6 +148,10 @@ def main():
                   "local_fp32"]:
             extra[v] = timed(v, max(5, args.steps // 2), 2)["render_ms"]
 
+    fwdbwd = None
+    if not args.no_fwdbwd:
+        fwdbwd = time_fwdbwd(args, R, scenes, torch, np)
+
     cpu = None
     if not args.no_cpu:
         from oracle import oracle as O
@@ -138,6 +179,8 @@ def main():
     }
     if extra:
         out["render_ms_by_variant"] = extra
+    if fwdbwd:
+        out["fwd_bwd"] = fwdbwd
     print(json.dumps(out), flush=True)
 
 

@@ -68,10 +68,12 @@ typedef struct lgs_camera {
 } lgs_camera;
 
 /* Render-kernel variants: the cumulative ablation ladder of the paper
- * (Table "ablation", Sec. IV-C).  OR with LGS_RENDER_FP32 for single-precision
- * exponent and transmittance arithmetic (the paper's own precision); the
- * default evaluates the exponent and the transmittance in double, which the
- * gfx950 vector ALU issues at the same rate as single precision. */
+ * (Table "ablation", Sec. IV-C).  By default the exponent of alpha (the
+ * hoisted dot product or the plain quadratic) is evaluated in double, which
+ * the gfx950 vector ALU issues at the single-precision rate, and alpha, T and
+ * the colour are float with the fused update T <- fma(-alpha, T, T) in every
+ * variant.  OR with LGS_RENDER_FP32 for the paper's single-precision
+ * arithmetic throughout. */
 typedef enum {
     LGS_RENDER_PLAIN = 0,       /* baseline per-pixel loop (Alg. 1, baseline column) */
     LGS_RENDER_HOIST = 1,       /* + tile-local hoisted dot product (Sec. III-B) */

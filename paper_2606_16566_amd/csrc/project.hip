@@ -99,11 +99,13 @@ struct Proj {
     double dir[3], dlen;     // unit view direction and |mean - campos|
 };
 
+// true if none of the k floats is inf or NaN (exponent bits all ones), with
+// no early exit so that the check stays branch-free
 __device__ __forceinline__ bool all_finite(const float *p, int k)
 {
-    bool ok = true;
-    for (int i = 0; i < k; ++i) ok = ok && isfinite(p[i]);
-    return ok;
+    uint32_t bad = 0;
+    for (int i = 0; i < k; ++i) bad |= ((__float_as_uint(p[i]) & 0x7f800000u) == 0x7f800000u) ? 1u : 0u;
+    return bad == 0;
 }
 
 // Geometry of the projection (no colour).  Returns false if culled before
@@ -111,7 +113,8 @@ __device__ __forceinline__ bool all_finite(const float *p, int k)
 __device__ bool project_geometry(const Cam &cam, const float *m3, const float *ls, const float *qt, float logit,
                                  Proj &P)
 {
-    if (!(all_finite(m3, 3) && all_finite(ls, 3) && all_finite(qt, 4) && isfinite(logit))) return false;
+    const bool finite = all_finite(m3, 3) & all_finite(ls, 3) & all_finite(qt, 4) & all_finite(&logit, 1);
+    if (!finite) return false;
     const float *V = cam.view;
     for (int i = 0; i < 3; ++i) P.m[i] = m3[i];
     // camera-space position; this FMA order defines the depth key
@@ -186,6 +189,24 @@ __device__ bool footprint(const Cam &cam, const Proj &P, int4 &rect)
     return true;
 }
 
+// Wavefront-cooperative copy of the SH coefficients of this wavefront's 64
+// Gaussians (one contiguous run of 64 * 3K floats) into LDS with 16-byte
+// loads, so that no lane reads its own strided 12K-byte record from HBM.
+template <int K3>
+__device__ __forceinline__ void stage_sh(const float *__restrict__ sh, int64_t g0, int cnt, float *s_sh)
+{
+    const float *src = sh + g0 * K3;
+    const int total = cnt * K3;
+    const int nv = total >> 2;
+    const float4 *src4 = reinterpret_cast<const float4 *>(src);
+    float4 *dst4 = reinterpret_cast<float4 *>(s_sh);
+    for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
+    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) s_sh[i] = src[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
                                                           const float *__restrict__ log_scales,
@@ -196,11 +217,16 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, co
                                                           float *__restrict__ depth, int4 *__restrict__ rect)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float s_sh[4][64 * 3 * K];
+    const int wid = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
+    if (g0 >= n) return;                                   // whole wavefront past the end
+    stage_sh<3 * K>(sh, g0, (int)min((int64_t)64, n - g0), s_sh[wid]);
+    const int64_t i = g0 + __lane_id();
     if (i >= n) return;
     Proj P;
     int4 r = make_int4(0, 0, 0, 0);
-    const float *shi = sh + i * (3 * K);
+    const float *shi = s_sh[wid] + __lane_id() * (3 * K);
     bool vis = project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P)
                && all_finite(shi, 3 * K) && footprint(cam, P, r);
     if (!vis) {
@@ -226,26 +252,24 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, co
     rect[i] = r;
 }
 
+// Gradient of one Gaussian.  shi points at its SH coefficients and dshi at
+// the output slot; they may alias (the coefficients are read first).
 template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+__device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const float *__restrict__ means3d,
                                                           const float *__restrict__ log_scales,
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
-                                                          const float *__restrict__ sh, const int4 *__restrict__ rect,
+                                                          const float *shi, const int4 *__restrict__ rect,
                                                           const float2 *__restrict__ g_means2d,
                                                           const float *__restrict__ g_conic,
                                                           const float *__restrict__ g_opacity,
                                                           const float *__restrict__ g_rgb, float *__restrict__ d_means3d,
                                                           float *__restrict__ d_log_scales, float *__restrict__ d_quats,
-                                                          float *__restrict__ d_logits, float *__restrict__ d_sh)
+                                                          float *__restrict__ d_logits, float *dshi)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const int4 r = rect[i];
     Proj P;
-    const float *shi = sh + i * (3 * K);
-    float *dshi = d_sh + i * (3 * K);
     bool vis = (r.z > r.x) && (r.w > r.y)
                && project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P);
     if (!vis) {
@@ -271,11 +295,12 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, co
     }
     for (int k = 0; k < K; ++k) {
         for (int ch = 0; ch < 3; ++ch) {
-            dshi[3 * k + ch] = (float)(gcol[ch] * Y[k]);
             const double w = gcol[ch] * (double)shi[3 * k + ch];
             gdir[0] += w * dY[k][0]; gdir[1] += w * dY[k][1]; gdir[2] += w * dY[k][2];
         }
     }
+    for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] = (float)(gcol[ch] * Y[k]);
     double gm[3] = {0.0, 0.0, 0.0};
     if (P.dlen > 0.0) {
         const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
@@ -358,6 +383,52 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, co
     d_quats[4 * i + 3] = (float)((gq[3] - z * dq) / P.qlen);
 }
 
+
+// copy this wavefront's LDS slots back to HBM with 16-byte stores
+template <int K3>
+__device__ __forceinline__ void unstage_sh(float *__restrict__ dst_all, int64_t g0, int cnt, const float *s_sh)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float *dst = dst_all + g0 * K3;
+    const int total = cnt * K3;
+    const int nv = total >> 2;
+    float4 *dst4 = reinterpret_cast<float4 *>(dst);
+    const float4 *src4 = reinterpret_cast<const float4 *>(s_sh);
+    for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
+    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) dst[i] = s_sh[i];
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+                                                          const float *__restrict__ log_scales,
+                                                          const float *__restrict__ quats,
+                                                          const float *__restrict__ logits,
+                                                          const float *__restrict__ sh, const int4 *__restrict__ rect,
+                                                          const float2 *__restrict__ g_means2d,
+                                                          const float *__restrict__ g_conic,
+                                                          const float *__restrict__ g_opacity,
+                                                          const float *__restrict__ g_rgb, float *__restrict__ d_means3d,
+                                                          float *__restrict__ d_log_scales, float *__restrict__ d_quats,
+                                                          float *__restrict__ d_logits, float *__restrict__ d_sh)
+{
+    constexpr int K3 = 3 * (DEG + 1) * (DEG + 1);
+    __shared__ float s_sh[4][64 * K3];
+    const int wid = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
+    if (g0 >= n) return;                                   // whole wavefront past the end
+    const int cnt = (int)min((int64_t)64, n - g0);
+    stage_sh<K3>(sh, g0, cnt, s_sh[wid]);
+    const int64_t i = g0 + __lane_id();
+    if (i < n) {
+        float *slot = s_sh[wid] + __lane_id() * K3;
+        project_bwd_one<DEG>(cam, i, means3d, log_scales, quats, logits, slot, rect, g_means2d, g_conic, g_opacity,
+                             g_rgb, d_means3d, d_log_scales, d_quats, d_logits, slot);
+    }
+    unstage_sh<K3>(d_sh, g0, cnt, s_sh[wid]);
+}
+
 }  // namespace
 }  // namespace lgs
 
@@ -375,8 +446,9 @@ extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t s
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh, "lgs_project: null input");
     LGS_REQUIRE(means2d && conic_opacity && rgb && depth && rect, "lgs_project: null output");
-    LGS_REQUIRE(((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0) && ((uintptr_t)rect % 16 == 0),
-                "lgs_project: means2d must be 8-byte and conic_opacity/rect 16-byte aligned");
+    LGS_REQUIRE(((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0) && ((uintptr_t)rect % 16 == 0)
+                    && ((uintptr_t)sh % 16 == 0),
+                "lgs_project: means2d must be 8-byte and conic_opacity/rect/sh 16-byte aligned");
     hipStream_t s = as_stream(stream);
     const dim3 grid(grid_for(n, 256)), block(256);
     auto *m2 = reinterpret_cast<float2 *>(means2d);
@@ -407,8 +479,9 @@ extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, 
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh && rect, "lgs_project_backward: null input");
     LGS_REQUIRE(g_means2d && g_conic && g_opacity && g_rgb, "lgs_project_backward: null gradient input");
     LGS_REQUIRE(d_means3d && d_log_scales && d_quats && d_opacity_logits && d_sh, "lgs_project_backward: null output");
-    LGS_REQUIRE(((uintptr_t)g_means2d % 8 == 0) && ((uintptr_t)rect % 16 == 0),
-                "lgs_project_backward: g_means2d must be 8-byte and rect 16-byte aligned");
+    LGS_REQUIRE(((uintptr_t)g_means2d % 8 == 0) && ((uintptr_t)rect % 16 == 0) && ((uintptr_t)sh % 16 == 0)
+                    && ((uintptr_t)d_sh % 16 == 0),
+                "lgs_project_backward: g_means2d must be 8-byte and rect/sh/d_sh 16-byte aligned");
     hipStream_t s = as_stream(stream);
     const dim3 grid(grid_for(n, 256)), block(256);
     auto *rc = reinterpret_cast<const int4 *>(rect);

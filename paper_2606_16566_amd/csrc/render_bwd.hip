@@ -18,32 +18,21 @@
 // (tile, Gaussian, component).
 #include "common.hpp"
 
+#include "render_common.hpp"
+
 namespace lgs {
 namespace {
 
-constexpr float kLog2AlphaMinB = -7.99435343685885793f;
+using namespace render;
+
 constexpr int kNG = 9;   // mean x, y; conic a, b, c; opacity; r, g, b
 
 struct BwdArgs {
-    const uint2 *ranges;
-    const uint32_t *values;
-    const float2 *means2d;
-    const float4 *conic_opacity;
-    const float *rgb;
-    const float *out_T;
-    const int32_t *out_nc;
+    RenderArgs r;          // ranges, values, attributes, out_T, out_nc (read)
     const float *grad_rgb;
     const float *grad_T;
     float *g_means2d, *g_conic, *g_opacity, *g_rgb;
-    int W, H, tiles_x, num_tiles;
-    float bg0, bg1, bg2;
 };
-
-__device__ __forceinline__ int xcd_tile_b(int b, int G)
-{
-    const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
-    return x * q + (x < r ? x : r) + k;
-}
 
 __device__ __forceinline__ float wave_sum(float v)
 {
@@ -52,49 +41,10 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// same tight-box mask as the forward (Sec. III-C-2)
-__device__ __forceinline__ uint32_t strip_mask_b(double a, double b, double c, double tau, double x0, double x1,
-                                                 double my, int ty0, int H)
-{
-    if (!(tau > 0.0)) return 0u;
-    const double det = a * c - b * b;
-    if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return 0xFu;
-    const double dy = sqrt(a * tau / det);
-    double ymax, ymin;
-    if (-b * dy < a * x0) {
-        const double arg = c * tau - det * x0 * x0;
-        if (arg < 0.0) return 0u;
-        ymax = (-b * x0 + sqrt(arg)) / c;
-    } else if (-b * dy > a * x1) {
-        const double arg = c * tau - det * x1 * x1;
-        if (arg < 0.0) return 0u;
-        ymax = (-b * x1 + sqrt(arg)) / c;
-    } else {
-        ymax = dy;
-    }
-    if (b * dy < a * x0) {
-        const double arg = c * tau - det * x0 * x0;
-        if (arg < 0.0) return 0u;
-        ymin = (-b * x0 - sqrt(arg)) / c;
-    } else if (b * dy > a * x1) {
-        const double arg = c * tau - det * x1 * x1;
-        if (arg < 0.0) return 0u;
-        ymin = (-b * x1 - sqrt(arg)) / c;
-    } else {
-        ymin = -dy;
-    }
-    const double lo = ceil(my + ymin - 1e-3), hi = floor(my + ymax + 1e-3);
-    int r0 = (int)fmax(lo, (double)ty0), r1 = (int)fmin(hi, (double)(ty0 + kTile - 1));
-    if (r1 > H - 1) r1 = H - 1;
-    if (!(lo <= (double)(ty0 + kTile - 1)) || !(hi >= (double)ty0) || r0 > r1) return 0u;
-    const int w0 = (r0 - ty0) >> 2, w1 = (r1 - ty0) >> 2;
-    return ((1u << (w1 - w0 + 1)) - 1u) << w0;
-}
-
 template <bool LOCAL>
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
+__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
 {
-    __shared__ double s_v[kBlock][6];        // hoisted exponent coefficients
+    __shared__ Hoisted<double> s_v[kBlock];  // hoisted exponent coefficients
     __shared__ float4 s_co[kBlock];          // a, b, c, o
     __shared__ float2 s_mu[kBlock];          // mean
     __shared__ float4 s_c[kBlock];           // colour
@@ -103,24 +53,20 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
     __shared__ float s_g[kNG][kBlock];
     __shared__ int s_max[kBlock / 64];
 
-    const int tile = xcd_tile_b(blockIdx.x, a.num_tiles);
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    const int lx = lane & 15, ly = (wid << 2) | (lane >> 4);
-    const int px = tx * kTile + lx, py = ty * kTile + ly;
-    const bool inside = px < a.W && py < a.H;
-    const double ox = tx * kTile + 7.5, oy = ty * kTile + 7.5;
-    const double xl = lx - 7.5, yl = ly - 7.5;
-    const double bxx = xl * xl, bxy = xl * yl, byy = yl * yl;
-
+    const RenderArgs &a = ba.r;
+    const TileCtx<double> tc(a);
+    const int lane = __lane_id(), wid = tc.wid;
+    const int px = tc.px, py = tc.py;
+    const bool inside = tc.inside;
+    const int tx = tc.tx, ty = tc.ty;
     const int64_t HW = (int64_t)a.W * a.H;
     const int64_t p = (int64_t)py * a.W + px;
     const int last = inside ? a.out_nc[p] : 0;
     const double Tf = inside ? (double)a.out_T[p] : 1.0;
     double T = Tf;
-    const float gc0 = inside ? a.grad_rgb[p] : 0.f, gc1 = inside ? a.grad_rgb[HW + p] : 0.f,
-                gc2 = inside ? a.grad_rgb[2 * HW + p] : 0.f;
-    const double gt = (inside && a.grad_T) ? (double)a.grad_T[p] : 0.0;
+    const float gc0 = inside ? ba.grad_rgb[p] : 0.f, gc1 = inside ? ba.grad_rgb[HW + p] : 0.f,
+                gc2 = inside ? ba.grad_rgb[2 * HW + p] : 0.f;
+    const double gt = (inside && ba.grad_T) ? (double)ba.grad_T[p] : 0.0;
     double R0 = Tf * a.bg0, R1 = Tf * a.bg1, R2 = Tf * a.bg2;
 
     int wmax = last;
@@ -129,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
     if (lane == 0) s_max[wid] = wmax;
     __syncthreads();
     const int bmax = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
-    const uint2 range = a.ranges[tile];
+    const uint2 range = a.ranges[tc.tile];
     const uint32_t end = range.x + (uint32_t)bmax;
 
     for (int64_t bend = end; bend > (int64_t)range.x; bend -= kBlock) {
@@ -147,20 +93,19 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
             s_c[k] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], 0.f);
             const float lo = __builtin_amdgcn_logf(co.w);
             if (LOCAL) {
-                const double L = kLog2e, ca = co.x, cb = co.y, cc = co.z;
-                const double dx = (double)m.x - ox, dy = (double)m.y - oy;
-                s_v[k][0] = -0.5 * L * ca;
-                s_v[k][1] = -L * cb;
-                s_v[k][2] = -0.5 * L * cc;
-                s_v[k][3] = L * (ca * dx + cb * dy);
-                s_v[k][4] = L * (cb * dx + cc * dy);
-                s_v[k][5] = (double)lo - 0.5 * L * (ca * dx * dx + 2.0 * cb * dx * dy + cc * dy * dy);
-                const double tau = 2.0 * ((double)lo - (double)kLog2AlphaMinB) / kLog2e * (1.0 + 1e-6) + 1e-5;
-                const double x0 = (double)(tx * kTile) - (double)m.x;
-                s_m[k] = (uint8_t)strip_mask_b(co.x, co.y, co.z, tau, x0, x0 + (kTile - 1), (double)m.y, ty * kTile,
-                                               a.H);
+                s_v[k] = hoist<double>(m, co, lo, tc.ox, tc.oy);
+                // strip bits of the four wavefronts (same test as the forward)
+                uint32_t mk = 0;
+                const float x0 = (float)(tx * kTile) - m.x, x1 = (float)(tx * kTile + kTile - 1) - m.x;
+                for (int w = 0; w < 4; ++w) {
+                    const int r0 = ty * kTile + 4 * w;
+                    if (r0 > a.H - 1) break;
+                    const int r1 = min(r0 + 3, a.H - 1);
+                    if (strip_hit(co.x, co.y, co.z, lo, x0, x1, (float)r0 - m.y, (float)r1 - m.y)) mk |= 1u << w;
+                }
+                s_m[k] = (uint8_t)mk;
             } else {
-                s_v[k][5] = (double)lo;
+                s_v[k].v[5] = (double)lo;
                 s_m[k] = 0xF;
             }
 #pragma unroll
@@ -184,15 +129,14 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
                 const double dx = (double)px - (double)m.x, dy = (double)py - (double)m.y;
                 double s;
                 if (LOCAL) {
-                    s = fma(s_v[k][0], bxx, fma(s_v[k][1], bxy, fma(s_v[k][2], byy,
-                        fma(s_v[k][3], xl, fma(s_v[k][4], yl, s_v[k][5])))));
+                    s = dot_exponent(s_v[k], tc);
                 } else {
                     const double q = (double)co.x * dx * dx + 2.0 * (double)co.y * dx * dy + (double)co.z * dy * dy;
-                    s = s_v[k][5] - 0.5 * kLog2e * q;
+                    s = s_v[k].v[5] - 0.5 * kLog2e * q;
                 }
                 const float s32 = (float)s;
                 const float raw = __builtin_amdgcn_exp2f(s32);
-                const bool act = pos1 <= last && s32 >= kLog2AlphaMinB;
+                const bool act = pos1 <= last && s32 >= kLog2AlphaMin;
                 float g[kNG];
 #pragma unroll
                 for (int f = 0; f < kNG; ++f) g[f] = 0.f;
@@ -232,15 +176,15 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs a)
             const int k = threadIdx.x;
             const uint32_t gid = s_id[k];
             float v;
-            if ((v = s_g[0][k]) != 0.f) unsafeAtomicAdd(&a.g_means2d[2 * gid], v);
-            if ((v = s_g[1][k]) != 0.f) unsafeAtomicAdd(&a.g_means2d[2 * gid + 1], v);
-            if ((v = s_g[2][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid], v);
-            if ((v = s_g[3][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid + 1], v);
-            if ((v = s_g[4][k]) != 0.f) unsafeAtomicAdd(&a.g_conic[3 * gid + 2], v);
-            if ((v = s_g[5][k]) != 0.f) unsafeAtomicAdd(&a.g_opacity[gid], v);
-            if ((v = s_g[6][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid], v);
-            if ((v = s_g[7][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid + 1], v);
-            if ((v = s_g[8][k]) != 0.f) unsafeAtomicAdd(&a.g_rgb[3 * gid + 2], v);
+            if ((v = s_g[0][k]) != 0.f) unsafeAtomicAdd(&ba.g_means2d[2 * gid], v);
+            if ((v = s_g[1][k]) != 0.f) unsafeAtomicAdd(&ba.g_means2d[2 * gid + 1], v);
+            if ((v = s_g[2][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid], v);
+            if ((v = s_g[3][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid + 1], v);
+            if ((v = s_g[4][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid + 2], v);
+            if ((v = s_g[5][k]) != 0.f) unsafeAtomicAdd(&ba.g_opacity[gid], v);
+            if ((v = s_g[6][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid], v);
+            if ((v = s_g[7][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid + 1], v);
+            if ((v = s_g[8][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid + 2], v);
         }
     }
 }
@@ -272,18 +216,14 @@ extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam
     fill_async<float>(g_opacity, 0.f, n, s);
     fill_async<float>(g_rgb, 0.f, 3 * n, s);
     BwdArgs a;
-    a.ranges = reinterpret_cast<const uint2 *>(ranges);
-    a.values = values;
-    a.means2d = reinterpret_cast<const float2 *>(means2d);
-    a.conic_opacity = reinterpret_cast<const float4 *>(conic_opacity);
-    a.rgb = rgb; a.out_T = out_T; a.out_nc = out_ncontrib; a.grad_rgb = grad_rgb; a.grad_T = grad_T;
+    a.r = make_args(cam, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
+                    const_cast<int32_t *>(out_ncontrib), nullptr);
+    a.grad_rgb = grad_rgb; a.grad_T = grad_T;
     a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
-    a.W = cam.W; a.H = cam.H; a.tiles_x = cam.tiles_x; a.num_tiles = cam.tiles_x * cam.tiles_y;
-    a.bg0 = cam.bg[0]; a.bg1 = cam.bg[1]; a.bg2 = cam.bg[2];
     if (v == LGS_RENDER_LOCAL)
-        hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.num_tiles), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.num_tiles), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
     LGS_LAUNCHED("lgs_render_backward");
     return LGS_OK;
 }

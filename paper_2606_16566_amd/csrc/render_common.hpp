@@ -1,0 +1,197 @@
+// Pieces shared by the forward and backward render kernels: tile geometry,
+// the hoist transform, the tight-box strip test and output helpers.
+#pragma once
+
+#include "common.hpp"
+
+namespace lgs {
+namespace render {
+
+// log2(1/255) rounded to float: the alpha floor in the log2 domain
+constexpr float kLog2AlphaMin = -7.99435343685885793f;
+constexpr float kAlphaMinF = 1.0f / 255.0f;
+constexpr float kLn2f = 0.693147180559945309f;
+
+struct RenderArgs {
+    const uint2 *ranges;
+    const uint32_t *values;
+    const float2 *means2d;
+    const float4 *conic_opacity;
+    const float *rgb;
+    float *out_rgb;
+    float *out_T;
+    int32_t *out_nc;
+    unsigned long long *stats;
+    int W, H, tiles_x, num_tiles;
+    float bg0, bg1, bg2;
+};
+
+inline RenderArgs make_args(const Cam &cam, const uint32_t *ranges, const uint32_t *values, const float *means2d,
+                            const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
+                            int32_t *out_nc, uint64_t *stats)
+{
+    RenderArgs a;
+    a.ranges = reinterpret_cast<const uint2 *>(ranges);
+    a.values = values;
+    a.means2d = reinterpret_cast<const float2 *>(means2d);
+    a.conic_opacity = reinterpret_cast<const float4 *>(conic_opacity);
+    a.rgb = rgb;
+    a.out_rgb = out_rgb; a.out_T = out_T; a.out_nc = out_nc;
+    a.stats = reinterpret_cast<unsigned long long *>(stats);
+    a.W = cam.W; a.H = cam.H; a.tiles_x = cam.tiles_x; a.num_tiles = cam.tiles_x * cam.tiles_y;
+    a.bg0 = cam.bg[0]; a.bg1 = cam.bg[1]; a.bg2 = cam.bg[2];
+    return a;
+}
+
+// workgroup index -> tile, so that each XCD (dispatch is round-robin over 8)
+// processes a contiguous band of tiles and shares their splats in its L2
+__device__ __forceinline__ int xcd_tile(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Geometry of one lane: pixel, tile, wavefront strip and the tile-local
+// basis.  The tile-local origin is the tile centre, so the basis coordinates
+// are the exact values -7.5 .. 7.5.
+template <typename R>
+struct TileCtx {
+    int tile, tx, ty, wid, px, py;
+    bool inside;
+    double ox, oy;
+    R xl, yl, bxx, bxy, byy;
+    __device__ __forceinline__ explicit TileCtx(const RenderArgs &a)
+    {
+        tile = xcd_tile(blockIdx.x, a.num_tiles);
+        tx = tile % a.tiles_x;
+        ty = tile / a.tiles_x;
+        const int lane = __lane_id();
+        wid = threadIdx.x >> 6;
+        const int lx = lane & 15, ly = (wid << 2) | (lane >> 4);
+        px = tx * kTile + lx;
+        py = ty * kTile + ly;
+        inside = px < a.W && py < a.H;
+        ox = tx * kTile + 7.5;
+        oy = ty * kTile + 7.5;
+        xl = (R)(lx - 7.5);
+        yl = (R)(ly - 7.5);
+        bxx = xl * xl; bxy = xl * yl; byy = yl * yl;
+    }
+};
+
+// Hoisted exponent coefficients (Eq. hoist_transform, log2(e) folded in):
+// log2 alpha = A x'^2 + B x'y' + C y'^2 + D x' + E y' + F
+template <typename R>
+struct Hoisted {
+    R v[6];
+};
+
+template <typename R>
+__device__ __forceinline__ Hoisted<R> hoist(float2 m, float4 co, float lo, double ox, double oy)
+{
+    const R L = (R)kLog2e;
+    const R a = co.x, b = co.y, c = co.z;
+    const R dx = (R)((double)m.x - ox), dy = (R)((double)m.y - oy);
+    Hoisted<R> h;
+    h.v[0] = (R)(-0.5) * L * a;
+    h.v[1] = -L * b;
+    h.v[2] = (R)(-0.5) * L * c;
+    h.v[3] = L * (a * dx + b * dy);
+    h.v[4] = L * (b * dx + c * dy);
+    h.v[5] = (R)lo - (R)0.5 * L * (a * dx * dx + (R)2 * b * dx * dy + c * dy * dy);
+    return h;
+}
+
+// the per-lane 5-FMA dot product with [x'^2, x'y', y'^2, x', y', 1]
+template <typename R>
+__device__ __forceinline__ R dot_exponent(const Hoisted<R> &h, const TileCtx<R> &tc)
+{
+    return fma(h.v[0], tc.bxx, fma(h.v[1], tc.bxy, fma(h.v[2], tc.byy, fma(h.v[3], tc.xl, fma(h.v[4], tc.yl, h.v[5])))));
+}
+
+// Does the footprint alpha >= 1/255, i.e. q <= tau with
+// tau = 2 ln 2 (log2 o - log2(1/255)), meet the rectangle [x0, x1] x [y0, y1]
+// (coordinates relative to the splat centre)?  Tight vertical span of the
+// ellipse over [x0, x1] (Sec. III-C-2: cases A/B/C for the top, the mirrored
+// cases for the bottom), then an interval test against [y0, y1].
+// Evaluated in float on a slightly larger ellipse, tau' = tau (1 + 1e-3) +
+// 1e-2: the enlargement exceeds every float rounding error of the test (the
+// product b^2 is split exactly so det keeps full relative accuracy, and the
+// square-root arguments stay >= c (tau' - tau) at the true tangent points),
+// so a Gaussian that can reach alpha >= 1/255 at a pixel of the strip is
+// never culled.
+__device__ __forceinline__ bool strip_hit(float a, float b, float c, float lo, float x0, float x1, float y0,
+                                          float y1)
+{
+    float tau = 2.0f * kLn2f * (lo - kLog2AlphaMin);
+    if (!(tau > 0.0f)) return false;
+    tau = fmaf(tau, 1e-3f, tau) + 1e-2f;
+    const float p = b * b;
+    const float pe = fmaf(b, b, -p);
+    const float det = fmaf(a, c, -p) - pe;
+    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return true;
+    const float dy = sqrtf(a * tau / det);
+    const float bdy = b * dy;
+    float ymax, ymin;
+    if (-bdy < a * x0) {                       // case A: peak left of the columns
+        const float arg = c * tau - det * x0 * x0;
+        if (arg < 0.0f) return false;
+        ymax = (-b * x0 + sqrtf(arg)) / c;
+    } else if (-bdy > a * x1) {                // case B: peak right of the columns
+        const float arg = c * tau - det * x1 * x1;
+        if (arg < 0.0f) return false;
+        ymax = (-b * x1 + sqrtf(arg)) / c;
+    } else {
+        ymax = dy;                             // case C: peak inside
+    }
+    if (bdy < a * x0) {                        // mirrored cases for the bottom
+        const float arg = c * tau - det * x0 * x0;
+        if (arg < 0.0f) return false;
+        ymin = (-b * x0 - sqrtf(arg)) / c;
+    } else if (bdy > a * x1) {
+        const float arg = c * tau - det * x1 * x1;
+        if (arg < 0.0f) return false;
+        ymin = (-b * x1 - sqrtf(arg)) / c;
+    } else {
+        ymin = -dy;
+    }
+    return ymax >= y0 - 1e-3f && ymin <= y1 + 1e-3f;
+}
+
+template <typename R>
+__device__ __forceinline__ void write_pixel(const RenderArgs &a, const TileCtx<R> &tc, float C0, float C1, float C2,
+                                            float T, int32_t last)
+{
+    if (!tc.inside) return;
+    const int64_t HW = (int64_t)a.W * a.H;
+    const int64_t p = (int64_t)tc.py * a.W + tc.px;
+    a.out_rgb[p] = C0 + T * a.bg0;
+    a.out_rgb[HW + p] = C1 + T * a.bg1;
+    a.out_rgb[2 * HW + p] = C2 + T * a.bg2;
+    a.out_T[p] = T;
+    a.out_nc[p] = last;
+}
+
+// Counters: [0] (wavefront, Gaussian) steps met by live wavefronts, [1] steps
+// evaluated, [2] entries staged, [3] lane evaluations (64 per evaluated step).
+// Per-lane counts are reduced to the wavefront maximum (a lane only ever
+// leaves the loop, so the last lane to leave saw every step).
+template <bool PER_WAVE_STAGED>
+__device__ __forceinline__ void flush_stats(const RenderArgs &a, unsigned long long seen, unsigned long long ev,
+                                            unsigned long long staged)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        seen = max(seen, (unsigned long long)__shfl_xor(seen, off, 64));
+        ev = max(ev, (unsigned long long)__shfl_xor(ev, off, 64));
+    }
+    if (__lane_id() == 0) {
+        atomicAdd(&a.stats[0], seen);
+        atomicAdd(&a.stats[1], ev);
+        atomicAdd(&a.stats[3], ev * 64ull);
+        if (PER_WAVE_STAGED) atomicAdd(&a.stats[2], staged);
+    }
+    if (!PER_WAVE_STAGED && threadIdx.x == 0) atomicAdd(&a.stats[2], staged);
+}
+
+}  // namespace render
+}  // namespace lgs

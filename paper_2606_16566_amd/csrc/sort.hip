@@ -1,15 +1,16 @@
 // Binning: prefix scans, stable LSD radix sort, key duplication and tile
-// ranges (Sec. II-A of the paper: "parallel prefix scan ... duplicates ...
-// into key-value pairs, which are sorted by GPU radix sort to produce
-// front-to-back index ranges").
+// ranges (Sec. II-A of the paper: a parallel prefix scan drives the
+// duplication of every Gaussian into key/value pairs, one per touched tile,
+// which a GPU radix sort orders front to back within each tile; tile ranges
+// are then read off the sorted keys).
 //
 // Two-stage ordering.  Instead of radix-sorting 64-bit (tile << 32 | depth)
 // keys over all P pairs (ceil(log2 tiles) + 32 bits: six 8-bit passes over P),
-// the visible Gaussians are first sorted by depth (32-bit key, N elements),
-// duplicated in that order, and the pairs are then stably sorted by tile id
-// only (ceil(log2 tiles) bits: two passes for 1080p).  Because both sorts
-// are stable and duplication follows (depth, id) order, the result is
-// identical to the single 64-bit sort.
+// the Gaussians are first sorted by depth (32-bit key over N; culled ones
+// carry depth +inf and sink to the end), duplicated in that order, and the
+// pairs are then stably sorted by tile id only (ceil(log2 tiles) bits: two
+// passes at 1080p).  Both sorts are stable and duplication follows
+// (depth, id) order, so the result is identical to the single 64-bit sort.
 #include "common.hpp"
 
 namespace lgs {
@@ -17,10 +18,11 @@ namespace {
 
 constexpr int kScanItems = 8;                          // per thread
 constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
-constexpr int kRadixItems = 16;                        // per thread
-constexpr int kRadixTile = kBlock * kRadixItems;       // 4096 per block
+constexpr int kRadixItems = 8;                         // per thread
+constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kWaves = kBlock / 64;
 
 // ---------------------------------------------------------------------------
 // block-wide scans (NW wave64 per block)
@@ -63,13 +65,20 @@ __device__ __forceinline__ int64_t live_count(int64_t n_max, const uint32_t *n_d
     return n < n_max ? n : n_max;
 }
 
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // device-wide exclusive scan: reduce -> scan of block partials -> final
 // ---------------------------------------------------------------------------
 template <typename T, typename L>
 __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(L ld, int64_t n_max, const uint32_t *n_dev, T *partials)
 {
-    __shared__ T s_warp[kBlock / 64];
+    __shared__ T s_warp[kWaves];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T sum = 0;
@@ -77,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(L ld, int64_t n_max
     for (int k = 0; k < kScanItems; ++k)
         if (base + k < n) sum += ld(base + k);
     T total;
-    block_exclusive_scan<T, kBlock / 64>(sum, total, s_warp);
+    block_exclusive_scan<T, kWaves>(sum, total, s_warp);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
@@ -101,7 +110,7 @@ template <typename T, typename L, typename S>
 __global__ __launch_bounds__(kBlock) void scan_final_kernel(L ld, S st, int64_t n_max, const uint32_t *n_dev,
                                                             const T *partials)
 {
-    __shared__ T s_warp[kBlock / 64];
+    __shared__ T s_warp[kWaves];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T item[kScanItems];
@@ -112,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void scan_final_kernel(L ld, S st, int64_t 
         sum += item[k];
     }
     T total;
-    T run = block_exclusive_scan<T, kBlock / 64>(sum, total, s_warp) + partials[blockIdx.x];
+    T run = block_exclusive_scan<T, kWaves>(sum, total, s_warp) + partials[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) st(base + k, run, item[k]);
@@ -120,159 +129,320 @@ __global__ __launch_bounds__(kBlock) void scan_final_kernel(L ld, S st, int64_t 
     }
 }
 
-template <typename T>
-struct ArrayLoad {
-    const T *p;
-    __device__ T operator()(int64_t i) const { return p[i]; }
-};
-template <typename T>
-struct ArrayStore {
-    T *p;
-    __device__ void operator()(int64_t i, T excl, T) const { p[i] = excl; }
-};
-
-// visible <=> non-empty tile rectangle
-struct VisibleLoad {
-    const int4 *rect;
-    __device__ uint32_t operator()(int64_t i) const
-    {
-        int4 r = rect[i];
-        return (r.z > r.x && r.w > r.y) ? 1u : 0u;
-    }
-};
-// compaction of visible Gaussians into (depth bits, id)
-struct CompactStore {
-    const float *depth;
-    uint32_t *keys, *vals;
-    __device__ void operator()(int64_t i, uint32_t excl, uint32_t item) const
-    {
-        if (item) {
-            keys[excl] = __float_as_uint(depth[i]);   // depth > znear > 0: bits order like the floats
-            vals[excl] = (uint32_t)i;
-        }
-    }
-};
-// tiles touched by the r-th Gaussian in depth order
-struct PairCountLoad {
+// tiles touched by the r-th Gaussian in depth order; the reduce pass gathers
+// the rectangle and leaves the count in `cnt` for the final pass
+struct PairCountGather {
     const uint32_t *order;
     const int4 *rect;
+    uint32_t *cnt;
     __device__ uint64_t operator()(int64_t r) const
     {
-        int4 q = rect[order[r]];
-        return (uint64_t)(q.z - q.x) * (uint64_t)(q.w - q.y);
+        const int4 q = rect[order[r]];
+        const uint32_t c = (q.z > q.x && q.w > q.y) ? (uint32_t)((q.z - q.x) * (q.w - q.y)) : 0u;
+        cnt[r] = c;
+        return c;
     }
 };
-// duplication: one (tile, id) pair per touched tile, row-major over the rectangle
-struct DuplicateStore {
-    const uint32_t *order;
-    const int4 *rect;
-    int tiles_x;
+struct U32Load {
+    const uint32_t *p;
+    __device__ uint64_t operator()(int64_t i) const { return p[i]; }
+};
+// exclusive pair offsets (in place over the counts), saturated at the capacity
+struct OffsetStore {
+    uint32_t *off;
     uint64_t cap;
-    uint32_t *keys, *vals;
-    __device__ void operator()(int64_t r, uint64_t excl, uint64_t item) const
+    __device__ void operator()(int64_t r, uint64_t excl, uint64_t) const
     {
-        if (!item) return;
-        const uint32_t g = order[r];
-        const int4 q = rect[g];
-        uint64_t o = excl;
-        for (int ty = q.y; ty < q.w; ++ty)
-            for (int tx = q.x; tx < q.z; ++tx, ++o)
-                if (o < cap) {
-                    keys[o] = (uint32_t)(ty * tiles_x + tx);
-                    vals[o] = g;
-                }
+        off[r] = (uint32_t)(excl < cap ? excl : cap);
     }
 };
 
-__global__ void finalize_pairs_kernel(const uint64_t *total, uint64_t cap, int64_t *num_pairs, int32_t *overflow,
-                                      uint32_t *n_eff)
+// scan of the block partials of the pair counts, which also publishes the
+// pair total, the overflow flag and min(P, capacity)
+__global__ __launch_bounds__(1024) void pair_partials_kernel(uint64_t *partials, int64_t nb, uint64_t *total_out,
+                                                             uint64_t cap, int64_t *num_pairs, int32_t *overflow,
+                                                             uint32_t *n_eff)
 {
-    const uint64_t p = *total;
-    *num_pairs = (int64_t)p;
-    *overflow = p > cap ? 1 : 0;
-    *n_eff = (uint32_t)(p > cap ? cap : p);
+    __shared__ uint64_t s_warp[16];
+    uint64_t carry = 0;
+    for (int64_t c = 0; c < nb; c += 1024) {
+        const int64_t i = c + threadIdx.x;
+        const uint64_t v = i < nb ? partials[i] : 0ull;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<uint64_t, 16>(v, tot, s_warp);
+        if (i < nb) partials[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        *total_out = carry;
+        *num_pairs = (int64_t)carry;
+        *overflow = carry > cap ? 1 : 0;
+        *n_eff = (uint32_t)(carry > cap ? cap : carry);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort, 8-bit digits, u32 keys + u32 values
+// Duplication: one (tile, id) pair per touched tile, row-major over the
+// Gaussian's tile rectangle, Gaussians in depth order.  Each block owns 256
+// consecutive Gaussians and their pair range; every lane emits 4 consecutive
+// pairs, locating the first one's Gaussian by binary search over the block's
+// offsets in LDS and stepping through the rectangle from there, so stores
+// are coalesced and a splat covering many tiles is spread over the block.
 // ---------------------------------------------------------------------------
+constexpr int kDupPerLane = 4;
+
+__global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__restrict__ order,
+                                                           const int4 *__restrict__ rect,
+                                                           const uint32_t *__restrict__ off,
+                                                           const uint64_t *p_total, uint64_t cap, int tiles_x,
+                                                           int64_t n, uint32_t *__restrict__ keys,
+                                                           uint32_t *__restrict__ vals)
+{
+    __shared__ uint32_t s_off[kBlock + 1];
+    __shared__ int4 s_rect[kBlock];
+    __shared__ uint32_t s_id[kBlock];
+    const int64_t first = (int64_t)blockIdx.x * kBlock;
+    if (first >= n) return;
+    const int cnt = (int)min((int64_t)kBlock, n - first);
+    const uint64_t total = *p_total;
+    const uint32_t lim = (uint32_t)(total < cap ? total : cap);
+    if ((int)threadIdx.x < cnt) {
+        const uint32_t g = order[first + threadIdx.x];
+        s_id[threadIdx.x] = g;
+        s_rect[threadIdx.x] = rect[g];
+        s_off[threadIdx.x] = off[first + threadIdx.x];
+    }
+    if (threadIdx.x == 0) s_off[cnt] = first + cnt < n ? off[first + cnt] : lim;
+    __syncthreads();
+    const uint32_t beg = s_off[0], end = s_off[cnt];
+    // lanes take aligned groups of 4 positions so interior groups are written
+    // with 16-byte stores
+    const uint32_t g0 = beg / kDupPerLane, g1 = (end + kDupPerLane - 1) / kDupPerLane;
+    for (uint32_t grp = g0 + threadIdx.x; grp < g1; grp += kBlock) {
+        const uint32_t pa = grp * kDupPerLane;
+        const uint32_t p0 = pa > beg ? pa : beg;          // first position of this group in range
+        if (p0 >= end) continue;
+        // last Gaussian k with s_off[k] <= p0 (a Gaussian without pairs shares
+        // its successor's offset, so the last of a run of equal offsets owns p0)
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p0) lo = mid; else hi = mid - 1;
+        }
+        int k = lo;
+        int4 q = s_rect[k];
+        uint32_t w = (uint32_t)(q.z - q.x);
+        const uint32_t i = p0 - s_off[k];
+        uint32_t ty = i / w, tx = i - ty * w;
+        uint32_t kk[kDupPerLane], vv[kDupPerLane];
+#pragma unroll
+        for (int e = 0; e < kDupPerLane; ++e) {
+            const uint32_t p = pa + e;
+            kk[e] = 0u; vv[e] = 0u;
+            if (p < p0 || p >= end) continue;
+            while (p >= s_off[k + 1]) {                 // next Gaussian that has pairs
+                ++k;
+                q = s_rect[k];
+                w = (uint32_t)(q.z - q.x);
+                tx = 0; ty = 0;
+            }
+            kk[e] = (uint32_t)((q.y + (int)ty) * tiles_x + q.x + (int)tx);
+            vv[e] = s_id[k];
+            if (++tx == w) { tx = 0; ++ty; }
+        }
+        if (pa >= beg && pa + kDupPerLane <= end) {
+            *reinterpret_cast<uint4 *>(keys + pa) = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+            *reinterpret_cast<uint4 *>(vals + pa) = make_uint4(vv[0], vv[1], vv[2], vv[3]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < kDupPerLane; ++e) {
+                const uint32_t p = pa + e;
+                if (p >= p0 && p < end) { keys[p] = kk[e]; vals[p] = vv[e]; }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits, u32 keys + u32 values.
+// One pass = histogram (per block, digit-major [256][nblocks]) -> per-digit
+// row scan (one workgroup per digit, also writes the digit totals) ->
+// scatter (each block derives its digit bases from the totals).
+// ---------------------------------------------------------------------------
+
+// lanes of this round of 64 whose digit equals this lane's (eight ballots)
+__device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d)
+{
+    uint64_t match = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        match &= bit ? bb : ~bb;
+    }
+    return match;
+}
+
+// Per-block digit histogram (per-wavefront sub-histograms in LDS, so the
+// atomics of one wavefront never contend with another's).
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
-                                                            const uint32_t *n_dev, int shift,
+                                                            const uint32_t *n_dev, int shift, uint32_t mask,
                                                             uint32_t *__restrict__ hist, int64_t nblocks)
 {
-    __shared__ uint32_t s_h[kBlock / 64][kRadixBins];
-    const int wid = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < (kBlock / 64) * kRadixBins; i += kBlock) (&s_h[0][0])[i] = 0;
+    __shared__ uint32_t s_h[kWaves][kRadixBins];
+    const int wid = threadIdx.x >> 6, lane = __lane_id();
+#pragma unroll
+    for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
     __syncthreads();
     const int64_t n = live_count(n_max, n_dev);
     const int64_t start = (int64_t)blockIdx.x * kRadixTile;
-    const int64_t end = start + kRadixTile < n ? start + kRadixTile : n;
-    for (int64_t e = start + threadIdx.x; e < end; e += kBlock)
-        atomicAdd(&s_h[wid][(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+    if (start < n) {
+        const int cnt = (int)min((int64_t)kRadixTile, n - start);
+        const uint32_t *k4 = keys + start;
+        if (cnt == kRadixTile && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
+#pragma unroll
+            for (int r = 0; r < kRadixItems / 4; ++r) {
+                const uint4 v = reinterpret_cast<const uint4 *>(k4)[r * kBlock + threadIdx.x];
+                atomicAdd(&s_h[wid][(v.x >> shift) & mask], 1u);
+                atomicAdd(&s_h[wid][(v.y >> shift) & mask], 1u);
+                atomicAdd(&s_h[wid][(v.z >> shift) & mask], 1u);
+                atomicAdd(&s_h[wid][(v.w >> shift) & mask], 1u);
+            }
+        } else {
+            for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(k4[e] >> shift) & mask], 1u);
+        }
+    }
     __syncthreads();
     uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) c += s_h[w][threadIdx.x];
+    for (int w = 0; w < kWaves; ++w) c += s_h[w][threadIdx.x];
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = c;
 }
 
-// Each block re-reads its 4096 elements in 16 rounds of 256 and scatters them
-// to digit offset + (elements of that digit before it in the block).  Within a
-// round the rank among equal digits comes from eight wave ballots; across
-// waves and rounds from per-wave digit counts in LDS.
+// Exclusive scan, in place, of one digit's row of per-block counts over the
+// blocks that hold elements: chunks of 2048 (8 consecutive per lane), block
+// scan of the lane sums, running carry between chunks.
+__global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t nblocks,
+                                                               int64_t n_max, const uint32_t *n_dev,
+                                                               uint32_t *__restrict__ digit_total)
+{
+    constexpr int kPer = 8;
+    __shared__ uint32_t s_warp[kWaves];
+    uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+    const int64_t n = live_count(n_max, n_dev);
+    const int64_t live = (n + kRadixTile - 1) / kRadixTile;
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < live; c += kBlock * kPer) {
+        const int64_t b0 = c + (int64_t)threadIdx.x * kPer;
+        uint32_t v[kPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            v[k] = b0 + k < live ? row[b0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t run = carry + block_exclusive_scan<uint32_t, kWaves>(sum, tot, s_warp);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            if (b0 + k < live) row[b0 + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+// Stable scatter of one 2048-element block.  Wavefront w owns the contiguous
+// elements [512 w, 512 (w+1)) of the block and ranks them in 8 rounds of 64
+// against its own running digit counts, so no workgroup barrier is needed
+// while ranking.  The block then orders its elements by digit in LDS (a local
+// counting sort) and writes each digit run to its global offset with
+// consecutive lanes on consecutive addresses.  vals_in == nullptr means the
+// values are the element indices.
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
                                                                const uint32_t *__restrict__ vals_in,
                                                                uint32_t *__restrict__ keys_out,
                                                                uint32_t *__restrict__ vals_out, int64_t n_max,
-                                                               const uint32_t *n_dev, int shift,
-                                                               const uint32_t *__restrict__ hist_scan, int64_t nblocks)
+                                                               const uint32_t *n_dev, int shift, uint32_t mask,
+                                                               const uint32_t *__restrict__ hist_scan,
+                                                               const uint32_t *__restrict__ digit_total,
+                                                               int64_t nblocks)
 {
-    __shared__ uint32_t s_base[kRadixBins];
-    __shared__ uint32_t s_wc[kBlock / 64][kRadixBins];
+    constexpr int kPerWave = kRadixTile / kWaves;          // 512
+    __shared__ uint32_t s_wc[kWaves][kRadixBins];          // running, then exclusive-over-waves counts
+    __shared__ uint32_t s_lbase[kRadixBins];               // block-local digit offsets
+    __shared__ uint32_t s_gbase[kRadixBins];               // global digit offsets of this block
+    __shared__ uint32_t s_key[kRadixTile];
+    __shared__ uint32_t s_val[kRadixTile];
+    __shared__ uint32_t s_tot[kWaves];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t start = (int64_t)blockIdx.x * kRadixTile;
     if (start >= n) return;                                  // uniform across the block
+    const int count = (int)min((int64_t)kRadixTile, n - start);
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    s_base[threadIdx.x] = hist_scan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
     const uint64_t lt = lanemask_lt();
-    for (int round = 0; round < kRadixItems; ++round) {
-        const int64_t e = start + (int64_t)round * kBlock + threadIdx.x;
-        if (start + (int64_t)round * kBlock >= n) break;     // uniform
-        const bool active = e < n;
-        const uint32_t key = active ? keys_in[e] : 0u;
-        const uint32_t val = active ? vals_in[e] : 0u;
-        const uint32_t d = (key >> shift) & (kRadixBins - 1);
 #pragma unroll
-        for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
-        uint64_t match = __ballot(active);
+    for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
+    {
+        // global base of digit t: all smaller digits + this digit in earlier blocks
+        const uint32_t tot = digit_total[threadIdx.x];
+        uint32_t all;
+        const uint32_t before = block_exclusive_scan<uint32_t, kWaves>(tot, all, s_tot);
+        s_gbase[threadIdx.x] = before + hist_scan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+    }
+
+    uint32_t key[kRadixItems], val[kRadixItems], rank[kRadixItems];
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            match &= bit ? bb : ~bb;
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int local = wid * kPerWave + r * 64 + lane;
+        const bool active = local < count;
+        key[r] = active ? keys_in[start + local] : 0u;
+        val[r] = active ? (vals_in ? vals_in[start + local] : (uint32_t)(start + local)) : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
+        const uint64_t match = digit_match(active, d);
+        const uint32_t before = active ? s_wc[wid][d] : 0u;
+        const uint32_t within = (uint32_t)__popcll(match & lt);
+        rank[r] = before + within;
+        if (active && within == 0) s_wc[wid][d] = before + (uint32_t)__popcll(match);
+        wave_sync_lds();
+    }
+    __syncthreads();
+    // digit t: prefix over wavefronts, block total, exclusive scan over digits
+    {
+        const int t = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_wc[w][t];
+            s_wc[w][t] = run;
+            run += c;
         }
-        const uint32_t rank = __popcll(match & lt);
-        if (active && rank == 0) s_wc[wid][d] = (uint32_t)__popcll(match);
-        __syncthreads();
-        if (active) {
-            uint32_t before = 0;
+        uint32_t tot;
+        s_lbase[t] = block_exclusive_scan<uint32_t, kWaves>(run, tot, s_tot);
+    }
+    __syncthreads();
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) before += (w < wid) ? s_wc[w][d] : 0u;
-            const uint32_t pos = s_base[d] + before + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int local = wid * kPerWave + r * 64 + lane;
+        if (local < count) {
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t lp = s_lbase[d] + s_wc[wid][d] + rank[r];
+            s_key[lp] = key[r];
+            s_val[lp] = val[r];
         }
-        __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) add += s_wc[w][threadIdx.x];
-        s_base[threadIdx.x] += add;
-        __syncthreads();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += kBlock) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
+        keys_out[pos] = k;
+        vals_out[pos] = s_val[i];
     }
 }
 
 // ---------------------------------------------------------------------------
-// tile ranges
+// tile ranges: 4 sorted keys per lane, vector loads
 // ---------------------------------------------------------------------------
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *num_pairs, const int32_t *overflow,
                               int64_t cap, uint2 *__restrict__ ranges)
@@ -280,16 +450,31 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *
     if (overflow && *overflow) return;
     int64_t n = *num_pairs;
     if (n > cap) n = cap;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t t = keys[i];
-        if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-        if (i == n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < n; i0 += stride) {
+        uint32_t k[5];
+        if (i0 + 3 < n && ((reinterpret_cast<uintptr_t>(keys + i0) & 15) == 0)) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(keys + i0);
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+            for (int e = 0; e < 4; ++e) k[e] = i0 + e < n ? keys[i0 + e] : 0xFFFFFFFFu;
+        }
+        k[4] = i0 + 4 < n ? keys[i0 + 4] : 0xFFFFFFFFu;
+        uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + e;
+            if (i < n) {
+                if (prev != k[e]) ranges[k[e]].x = (uint32_t)i;
+                if (i + 1 >= n || k[e + 1] != k[e]) ranges[k[e]].y = (uint32_t)(i + 1);
+            }
+            prev = k[e];
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// host helpers
+// host side
 // ---------------------------------------------------------------------------
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -297,8 +482,9 @@ struct SortWorkspace {
     uint32_t *dk[2], *dv[2];      // depth keys / ids, ping-pong [n]
     uint32_t *pk, *pv;            // alternate pair buffers [cap]
     uint32_t *hist;               // [256 * nblocks_max]
+    uint32_t *digit_total;        // [256]
+    uint32_t *pair_off;           // [n] pair counts, then exclusive offsets
     uint64_t *partials;           // scan partials
-    uint32_t *n_vis;              // visible count
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
     size_t bytes;
@@ -324,42 +510,29 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.pv = (uint32_t *)take(sizeof(uint32_t) * (cap > 0 ? cap : 1));
     const int64_t nbmax = radix_blocks(n > cap ? n : cap) + 1;
     w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * nbmax);
-    int64_t scan_max = kRadixBins * nbmax;
-    if (n > scan_max) scan_max = n;
-    w.partials = (uint64_t *)take(sizeof(uint64_t) * ((scan_max + kScanTile - 1) / kScanTile + 1));
-    w.n_vis = (uint32_t *)take(sizeof(uint32_t));
+    w.digit_total = (uint32_t *)take(sizeof(uint32_t) * kRadixBins);
+    w.pair_off = (uint32_t *)take(sizeof(uint32_t) * nm);
+    w.partials = (uint64_t *)take(sizeof(uint64_t) * ((nm + kScanTile - 1) / kScanTile + 1));
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
     w.bytes = off;
     return w;
 }
 
-// exclusive scan of ld(0..n) with a device-resident count (n_dev may be NULL)
-template <typename T, typename L, typename S>
-void device_scan(L ld, S st, int64_t n_max, const uint32_t *n_dev, T *partials, T *total, hipStream_t s)
-{
-    const int64_t nb = (n_max + kScanTile - 1) / kScanTile;
-    if (nb == 0) {
-        hipLaunchKernelGGL(scan_partials_kernel<T>, dim3(1), dim3(1024), 0, s, partials, (int64_t)0, total);
-        return;
-    }
-    hipLaunchKernelGGL((scan_reduce_kernel<T, L>), dim3((unsigned)nb), dim3(kBlock), 0, s, ld, n_max, n_dev, partials);
-    hipLaunchKernelGGL(scan_partials_kernel<T>, dim3(1), dim3(1024), 0, s, partials, nb, total);
-    hipLaunchKernelGGL((scan_final_kernel<T, L, S>), dim3((unsigned)nb), dim3(kBlock), 0, s, ld, st, n_max, n_dev,
-                       (const T *)partials);
-}
-
-// one stable radix pass over [0, min(n_max, *n_dev))
+// one stable radix pass over [0, min(n_max, *n_dev)) on key bits
+// [shift, shift + bits)
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                const uint32_t *n_dev, int shift, const SortWorkspace &w, hipStream_t s)
+                const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s)
 {
     const int64_t nb = radix_blocks(n_max);
     if (nb == 0) return;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, shift, w.hist, nb);
-    device_scan<uint32_t>(ArrayLoad<uint32_t>{w.hist}, ArrayStore<uint32_t>{w.hist}, kRadixBins * nb, nullptr,
-                          reinterpret_cast<uint32_t *>(w.partials), (uint32_t *)nullptr, s);
+    const uint32_t mask = (1u << bits) - 1u;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
+                       w.hist, nb);
+    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, nb, n_max, n_dev,
+                       w.digit_total);
     hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n_max,
-                       n_dev, shift, (const uint32_t *)w.hist, nb);
+                       n_dev, shift, mask, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, nb);
 }
 
 }  // namespace
@@ -384,6 +557,8 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
     LGS_REQUIRE(num_pairs && overflow, "lgs_sort: null num_pairs/overflow");
     LGS_REQUIRE(n == 0 || (depth && rect), "lgs_sort: null input");
     LGS_REQUIRE(capacity_pairs == 0 || (tile_keys && values), "lgs_sort: null output");
+    LGS_REQUIRE(((uintptr_t)tile_keys % 16 == 0) && ((uintptr_t)values % 16 == 0),
+                "lgs_sort: tile_keys and values must be 16-byte aligned");
     LGS_REQUIRE(rect == nullptr || (uintptr_t)rect % 16 == 0, "lgs_sort: rect must be 16-byte aligned");
     const size_t need = plan_workspace(nullptr, n, capacity_pairs).bytes;
     LGS_REQUIRE(workspace && workspace_bytes >= need, "lgs_sort: workspace too small (%zu < %zu bytes)",
@@ -393,30 +568,46 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
     SortWorkspace w = plan_workspace(static_cast<char *>(workspace), n, capacity_pairs);
     const int4 *rc = reinterpret_cast<const int4 *>(rect);
 
-    // 1. compact visible Gaussians into (depth bits, id)
-    device_scan<uint32_t>(VisibleLoad{rc}, CompactStore{depth, w.dk[0], w.dv[0]}, n, nullptr,
-                          reinterpret_cast<uint32_t *>(w.partials), w.n_vis, s);
-    // 2. stable sort by depth: four 8-bit passes, result back in buffer 0
-    for (int pass = 0; pass < 4; ++pass) {
-        const int a = pass & 1;
-        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, w.n_vis, 8 * pass, w, s);
+    // 1. stable sort of all Gaussians by depth bits (positive floats order
+    //    like their bit patterns; culled ones hold +inf and end up last):
+    //    four 8-bit passes, the first reading the depths and implicit ids
+    const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
+    radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s);
+    for (int pass = 1; pass < 4; ++pass) {
+        const int a = (pass - 1) & 1;
+        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s);
     }
-    // 3. scan of tile counts in depth order, fused with duplication.  The
-    //    number of tile-sort passes decides which buffer receives the pairs so
-    //    that the sorted result ends in the caller's buffers.
+    const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
+    // 2. pair counts in depth order, their exclusive scan (total P) and the
+    //    overflow check.  The number of tile-sort passes decides which buffer
+    //    receives the pairs so that the sorted result ends in the caller's.
     int bits = 1;
     while ((1ll << bits) < (int64_t)tiles_x * tiles_y) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint32_t *k0 = (passes & 1) ? w.pk : tile_keys, *v0 = (passes & 1) ? w.pv : values;
     uint32_t *k1 = (passes & 1) ? tile_keys : w.pk, *v1 = (passes & 1) ? values : w.pv;
-    device_scan<uint64_t>(PairCountLoad{w.dv[0], rc}, DuplicateStore{w.dv[0], rc, tiles_x, (uint64_t)capacity_pairs, k0, v0},
-                          n, w.n_vis, w.partials, w.p_total, s);
-    hipLaunchKernelGGL(finalize_pairs_kernel, dim3(1), dim3(1), 0, s, (const uint64_t *)w.p_total,
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb > 0)
+        hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, PairCountGather>), dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           PairCountGather{order, rc, w.pair_off}, n, (const uint32_t *)nullptr, w.partials);
+    hipLaunchKernelGGL(pair_partials_kernel, dim3(1), dim3(1024), 0, s, w.partials, nb, w.p_total,
                        (uint64_t)capacity_pairs, num_pairs, overflow, w.n_eff);
-    // 4. stable sort of the pairs by tile id
-    for (int pass = 0; pass < passes; ++pass) {
-        if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, 8 * pass, w, s);
-        else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, 8 * pass, w, s);
+    if (nb > 0)
+        hipLaunchKernelGGL((scan_final_kernel<uint64_t, U32Load, OffsetStore>), dim3((unsigned)nb), dim3(kBlock), 0, s,
+                           U32Load{w.pair_off}, OffsetStore{w.pair_off, (uint64_t)capacity_pairs}, n,
+                           (const uint32_t *)nullptr, (const uint64_t *)w.partials);
+    // 3. duplication in depth order
+    if (n > 0)
+        hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order, rc,
+                           (const uint32_t *)w.pair_off, (const uint64_t *)w.p_total, (uint64_t)capacity_pairs,
+                           tiles_x, n, k0, v0);
+    // 4. stable sort of the pairs by tile id, the key bits split evenly over
+    //    the passes (longer digit runs per block than 8 + remainder)
+    for (int pass = 0, shift = 0; pass < passes; ++pass) {
+        const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
+        if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, shift, b, w, s);
+        else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, shift, b, w, s);
+        shift += b;
     }
     LGS_LAUNCHED("lgs_sort");
     return LGS_OK;
@@ -431,8 +622,8 @@ extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *
     hipStream_t s = as_stream(stream);
     fill_async<uint64_t>(reinterpret_cast<uint64_t *>(ranges), 0ull, num_tiles, s);
     if (capacity_pairs > 0) {
-        unsigned g = grid_for(capacity_pairs, 256);
-        if (g > 8192) g = 8192;
+        unsigned g = grid_for(capacity_pairs, 256 * 4);
+        if (g > 4096) g = 4096;
         hipLaunchKernelGGL(ranges_kernel, dim3(g), dim3(256), 0, s, tile_keys, num_pairs, overflow, capacity_pairs,
                            reinterpret_cast<uint2 *>(ranges));
     }
