@@ -73,13 +73,16 @@ typedef struct lgs_camera {
  * the gfx950 vector ALU issues at the single-precision rate, and alpha, T and
  * the colour are float with the fused update T <- fma(-alpha, T, T) in every
  * variant.  OR with LGS_RENDER_FP32 for the paper's single-precision
- * arithmetic throughout. */
+ * arithmetic throughout, and with LGS_RENDER_Q8 to change the wavefront
+ * sub-tile shape of the culling variants. */
 typedef enum {
     LGS_RENDER_PLAIN = 0,       /* baseline per-pixel loop (Alg. 1, baseline column) */
     LGS_RENDER_HOIST = 1,       /* + tile-local hoisted dot product (Sec. III-B) */
     LGS_RENDER_HOIST_CULL = 2,  /* + wavefront-level tight-box culling (Sec. III-C) */
     LGS_RENDER_LOCAL = 3,       /* + uniform blend, wave-wide termination vote (Sec. III-D) */
-    LGS_RENDER_FP32 = 0x10
+    LGS_RENDER_FP32 = 0x10,
+    LGS_RENDER_Q8 = 0x20        /* HOIST_CULL / LOCAL: each wavefront owns an 8x8 quadrant of
+                                   the tile instead of a 16x4 row strip (same results) */
 } lgs_render_variant;
 
 /* Message for the last non-OK status on the calling host thread. */
@@ -118,10 +121,11 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * lgs_sort -- duplication of every visible Gaussian into one (tile, id) pair
  * per touched tile and a stable sort so that each tile's pairs are in
  * ascending (depth, id) order (Sec. II-A: prefix scan, key duplication,
- * radix sort).  Implemented as a stable depth sort of the visible Gaussians,
- * a scan of their tile counts, duplication in depth order and a stable radix
- * sort on the tile id; the result equals a stable sort of 64-bit
- * (tile << 32 | depth bits) keys emitted in id order.
+ * radix sort).  Implemented as a stable radix sort of all n depth keys
+ * (culled ones hold +inf and sort last), a scan of their tile counts in that
+ * order, duplication in depth order and a stable radix sort on the tile id
+ * alone; the result equals a stable sort of 64-bit (tile << 32 | depth bits)
+ * keys emitted in id order.
  *
  * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
  * Outputs (device):
@@ -198,6 +202,103 @@ lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_deg
                                 const float *g_means2d, const float *g_conic, const float *g_opacity,
                                 const float *g_rgb, float *d_means3d, float *d_log_scales,
                                 float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
+
+/*
+ * Multi-view batches.  A batch renders up to LGS_MAX_VIEWS cameras (sizes may
+ * differ) of one Gaussian set in single launches, the paper's stages applied
+ * to each view unchanged (Sec. II-A, Sec. III).  Layouts:
+ *   - per-Gaussian projected arrays are view-major: element e = v * n + i
+ *     (means2d [V*n,2], conic_opacity [V*n,4], rgb [V*n,3], depth [V*n],
+ *     rect [V*n,4] and their gradients);
+ *   - tiles of all views form one global index space: view v owns tiles
+ *     [T_v, T_v + tiles_x(v) * tiles_y(v)) with T_v the sum of the tile
+ *     counts of the views before it; pair values are element ids e;
+ *   - images are packed: view v's out_rgb [3,H_v,W_v] starts at float
+ *     3 * P_v and out_T / out_ncontrib [H_v,W_v] at element P_v, where P_v
+ *     is the sum of W*H over the views before it.
+ * Each *_batch call with num_views = 1 is exactly its single-view form.
+ */
+#define LGS_MAX_VIEWS 16
+
+/* lgs_project for num_views cameras; the raw parameters are read once.
+ * Outputs [num_views * n, ...], view-major. */
+lgs_status lgs_project_batch(const lgs_camera *cams, int32_t num_views, int64_t n, int32_t sh_degree,
+                             const float *means3d, const float *log_scales, const float *quats,
+                             const float *opacity_logits, const float *sh,
+                             float *means2d, float *conic_opacity, float *rgb, float *depth,
+                             int32_t *rect, void *stream);
+
+/* lgs_sort over num_views * n_per_view elements; tiles_x / tiles_y are host
+ * arrays [num_views].  The workspace size is
+ * lgs_sort_workspace_size(num_views * n_per_view, capacity_pairs, total tiles). */
+lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
+                          int64_t n_per_view, const float *depth, const int32_t *rect,
+                          uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                          int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
+                          void *stream);
+
+/* lgs_render over the global tiles of num_views cameras (ranges [total,2]
+ * from lgs_tile_ranges with num_tiles = total tiles).
+ * queue: NULL for one workgroup per tile; else a device uint32 work counter
+ *   (cleared by the call itself) that turns the culling variants
+ *   (HOIST_CULL, LOCAL) into a persistent kernel of blocks_per_cu workgroups
+ *   per compute unit (<= 0: 8) whose wavefronts take 16x4 strips from the
+ *   counter until none is left.  Other variants ignore it.  Concurrent calls
+ *   must not share a queue.
+ * tile_order: NULL to hand out tiles in index order, else a device
+ *   permutation [total tiles] (e.g. from lgs_tile_order) giving the tile of
+ *   each queue position.  Outputs do not depend on the order. */
+lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num_views,
+                            const uint32_t *ranges, const uint32_t *values,
+                            const float *means2d, const float *conic_opacity, const float *rgb,
+                            float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
+                            uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
+                            void *stream);
+
+/* lgs_tile_order -- longest-first work order for the persistent render: a
+ * permutation of the tile ids (device uint32 [num_tiles]) by non-increasing
+ * list length, lengths compared in classes of 1/8 octave (tiles of one class
+ * stay in index order).  Not a step of the paper; it balances the tail of a
+ * queue-driven launch.  workspace: 256-byte aligned device scratch of
+ * lgs_tile_order_workspace_size(num_tiles) bytes. */
+size_t lgs_tile_order_workspace_size(int32_t num_tiles);
+lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *order, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
+/* lgs_render_backward of a batch: n_elem = num_views * n elements of the
+ * view-major gradient outputs. */
+lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, int32_t num_views, int64_t n_elem,
+                                     const uint32_t *ranges, const uint32_t *values, const float *means2d,
+                                     const float *conic_opacity, const float *rgb, const float *out_T,
+                                     const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
+                                     float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
+                                     void *stream);
+
+/* lgs_project_backward of a batch: the view-major gradients of the projected
+ * attributes are summed over the views into the raw-parameter gradients
+ * [n, ...] (overwritten). */
+lgs_status lgs_project_backward_batch(const lgs_camera *cams, int32_t num_views, int64_t n, int32_t sh_degree,
+                                      const float *means3d, const float *log_scales, const float *quats,
+                                      const float *opacity_logits, const float *sh, const int32_t *rect,
+                                      const float *g_means2d, const float *g_conic, const float *g_opacity,
+                                      const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                      float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
+
+/*
+ * Step graphs: lgs_graph_begin starts capturing the calls enqueued on
+ * `stream` by this host thread (a created stream, not NULL) instead of
+ * running them; lgs_graph_end stops and instantiates them as one HIP graph.
+ * lgs_graph_launch replays the whole sequence on a stream with one call, on
+ * the same device buffers and arguments as captured.  Every library call is
+ * capturable (clears are kernels, never memset nodes) except the host-side
+ * read of a pair count, which stays outside: capture a step with a fixed
+ * pair capacity and check the overflow flag after replays.
+ */
+typedef struct lgs_graph lgs_graph;
+lgs_status lgs_graph_begin(void *stream);
+lgs_status lgs_graph_end(void *stream, lgs_graph **graph);
+lgs_status lgs_graph_launch(lgs_graph *graph, void *stream);
+lgs_status lgs_graph_destroy(lgs_graph *graph);
 
 /*
  * lgs_l1_loss -- L = mean |image - target| over `count` floats and

@@ -23,9 +23,15 @@ RENDER_HOIST = 1
 RENDER_HOIST_CULL = 2
 RENDER_LOCAL = 3
 RENDER_FP32 = 0x10
+RENDER_Q8 = 0x20
+
+MAX_VIEWS = 16
 
 EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort",
-           "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_loss"]
+           "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_loss",
+           "lgs_project_batch", "lgs_sort_batch", "lgs_render_batch", "lgs_render_backward_batch",
+           "lgs_project_backward_batch", "lgs_graph_begin", "lgs_graph_end", "lgs_graph_launch",
+           "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order"]
 
 
 class LgsCamera(C.Structure):
@@ -50,8 +56,20 @@ _SIG = {
     "lgs_tile_ranges": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P]),
     "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 10),
     "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 14),
-    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 15),
+    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 16),
     "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 11),
+    "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _I64, _P, _P, _P,
+                                 C.c_size_t, _P]),
+    "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9 + [_P, _P, _I32, _P]),
+    "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
+    "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
+    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 14),
+    "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 16),
+    "lgs_graph_begin": (C.c_int, [_P]),
+    "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
+    "lgs_graph_launch": (C.c_int, [_P, _P]),
+    "lgs_graph_destroy": (C.c_int, [_P]),
 }
 
 _lib = None
@@ -77,6 +95,14 @@ def check(status: int, what: str) -> None:
     if status != LGS_OK:
         msg = lib().lgs_last_error().decode(errors="replace")
         raise LocalGSError(f"{what} failed with status {status}: {msg}")
+
+
+def camera_array(cams):
+    """Sequence of scenes.Camera -> contiguous LgsCamera array."""
+    arr = (LgsCamera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera_struct(c)
+    return arr
 
 
 def camera_struct(cam) -> LgsCamera:

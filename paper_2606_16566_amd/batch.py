@@ -1,0 +1,283 @@
+"""Multi-view batches and step graphs.
+
+`ViewBatch` renders up to 16 cameras of one Gaussian set with one launch per
+pipeline stage: view-batched projection (raw parameters read once), one sort
+over the global tile space of all views, one persistent render whose
+wavefronts pull 16x4 strips from a device queue (optionally longest tile
+first), and the matching backward that sums the gradients over the views.
+Every buffer is allocated up front, so a whole step enqueues library calls
+only and can be captured once with `StepGraph` and replayed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .rasterizer import _p, _req, _stream, variant_code
+
+
+def _aligned(buf: torch.Tensor):
+    base = buf.data_ptr()
+    a = (base + 255) & ~255
+    return C.c_void_p(a), buf.numel() - (a - base)
+
+
+class ViewBatch:
+    """Device buffers and launch settings for rendering `cams` from n
+    Gaussians of SH degree `sh_degree`.
+
+    variant        render variant name or code (see rasterizer.variant_code)
+    persistent     queue-driven render for the culling variants
+    blocks_per_cu  workgroups per compute unit of the persistent render (0: 8)
+    lpt            hand out tiles longest first (persistent render only)
+    capacity       initial pair capacity; `fit()` grows it from a measured count
+    """
+
+    def __init__(self, cams, n: int, sh_degree: int, variant="local", persistent: bool = True,
+                 blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda"):
+        cams = list(cams)
+        if not 1 <= len(cams) <= L.MAX_VIEWS:
+            raise ValueError(f"a batch holds 1..{L.MAX_VIEWS} cameras, got {len(cams)}")
+        self.cams = cams
+        self.V = V = len(cams)
+        self.n = int(n)
+        self.deg = int(sh_degree)
+        self.K = (self.deg + 1) ** 2
+        self.variant = variant_code(variant)
+        self.persistent = bool(persistent)
+        self.blocks_per_cu = int(blocks_per_cu)
+        self.lpt = bool(lpt)
+        self.dev = torch.device(device)
+        self.cam_arr = L.camera_array(cams)
+        self.tiles_x = (C.c_int32 * V)(*[c.tiles_x for c in cams])
+        self.tiles_y = (C.c_int32 * V)(*[c.tiles_y for c in cams])
+        self.tile_off = np.concatenate([[0], np.cumsum([c.num_tiles for c in cams])]).astype(np.int64)
+        self.pix_off = np.concatenate([[0], np.cumsum([c.num_pixels for c in cams])]).astype(np.int64)
+        self.num_tiles = int(self.tile_off[-1])
+        self.num_pixels = int(self.pix_off[-1])
+        E = V * self.n
+        f32, i32, dev = torch.float32, torch.int32, self.dev
+        z = lambda *shape, dtype=f32: torch.zeros(shape, dtype=dtype, device=dev)
+        # projected attributes and their gradients, view-major [V*n, ...]
+        self.means2d, self.conic_opacity, self.rgb = z(E, 2), z(E, 4), z(E, 3)
+        self.depth, self.rect = z(E), z(E, 4, dtype=i32)
+        self.g_means2d, self.g_conic, self.g_opacity, self.g_rgb = z(E, 2), z(E, 3), z(E), z(E, 3)
+        # raw-parameter gradients [n, ...], summed over views
+        self.d_means3d, self.d_log_scales, self.d_quats = z(self.n, 3), z(self.n, 3), z(self.n, 4)
+        self.d_logits, self.d_sh = z(self.n), z(self.n, self.K, 3)
+        # packed images
+        self.out_rgb, self.out_T = z(3 * self.num_pixels), z(self.num_pixels)
+        self.out_nc = z(self.num_pixels, dtype=i32)
+        self.grad_rgb = z(3 * self.num_pixels)
+        self.loss = z(1)
+        # binning
+        self.num_pairs = z(1, dtype=torch.int64)
+        self.overflow = z(1, dtype=i32)
+        self.ranges = z(self.num_tiles, 2, dtype=i32)
+        self.queue = z(1, dtype=i32)
+        self.order = z(self.num_tiles, dtype=i32)
+        self.order_ws = torch.empty(L.lib().lgs_tile_order_workspace_size(self.num_tiles) + 256, dtype=torch.uint8,
+                                    device=dev)
+        self.capacity = 0
+        self._alloc_pairs(max(int(capacity), 1024))
+
+    # -- buffers ---------------------------------------------------------
+    def _alloc_pairs(self, cap: int):
+        self.capacity = int(cap)
+        self.keys = torch.empty(cap, dtype=torch.int32, device=self.dev)
+        self.vals = torch.empty(cap, dtype=torch.int32, device=self.dev)
+        need = L.lib().lgs_sort_workspace_size(self.V * self.n, cap, self.num_tiles)
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.dev)
+
+    def fit(self, params, headroom: float = 1.15) -> int:
+        """Run the forward once and grow the pair buffers until the pair
+        count fits (host synchronisation; call before capturing)."""
+        for _ in range(4):
+            self.forward(params)
+            p = int(self.num_pairs.item())
+            if p <= self.capacity:
+                return p
+            self._alloc_pairs(int(p * headroom) + 1024)
+        raise RuntimeError("pair count did not settle")
+
+    def overflowed(self) -> bool:
+        return bool(int(self.overflow.item()))
+
+    # -- views of the packed outputs ---------------------------------------
+    def image(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        a, b = self.pix_off[v], self.pix_off[v + 1]
+        return self.out_rgb[3 * a:3 * b].view(3, c.height, c.width)
+
+    def final_T(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        return self.out_T[self.pix_off[v]:self.pix_off[v + 1]].view(c.height, c.width)
+
+    def n_contrib(self, v: int) -> torch.Tensor:
+        c = self.cams[v]
+        return self.out_nc[self.pix_off[v]:self.pix_off[v + 1]].view(c.height, c.width)
+
+    def pack(self, images) -> torch.Tensor:
+        """Per-view [3,H,W] tensors -> one packed buffer in the output layout."""
+        return torch.cat([im.reshape(-1) for im in images]).contiguous()
+
+    # -- the step ------------------------------------------------------------
+    def _check(self, params):
+        means3d, log_scales, quats, logits, sh = params
+        for t, nm in ((means3d, "means3d"), (log_scales, "log_scales"), (quats, "quats"), (logits, "logits"),
+                      (sh, "sh")):
+            _req(t, torch.float32, nm)
+        if means3d.shape[0] != self.n or sh.shape[1] != self.K:
+            raise ValueError("parameters do not match the batch's n / SH degree")
+
+    def forward(self, params, stats: torch.Tensor | None = None):
+        """Enqueue project -> sort -> ranges -> [order] -> render for all views."""
+        self.bin(params)
+        self.render(stats)
+
+    def configure(self, variant=None, persistent=None, blocks_per_cu=None, lpt=None):
+        """Change launch settings (e.g. from the autotuner); buffers are kept."""
+        if variant is not None:
+            self.variant = variant_code(variant)
+        if persistent is not None:
+            self.persistent = bool(persistent)
+        if blocks_per_cu is not None:
+            self.blocks_per_cu = int(blocks_per_cu)
+        if lpt is not None:
+            self.lpt = bool(lpt)
+
+    def bin(self, params):
+        """Enqueue project -> sort -> ranges for all views."""
+        self.project(params)
+        self.sort()
+
+    def project(self, params):
+        """Enqueue the view-batched projection."""
+        self._check(params)
+        lb, s = L.lib(), _stream()
+        means3d, log_scales, quats, logits, sh = params
+        L.check(lb.lgs_project_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales), _p(quats),
+                                     _p(logits), _p(sh), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
+                                     _p(self.depth), _p(self.rect), s), "lgs_project_batch")
+
+    def sort(self):
+        """Enqueue the pair sort and the tile ranges of all views."""
+        lb, s = L.lib(), _stream()
+        ws, wsb = _aligned(self.ws)
+        L.check(lb.lgs_sort_batch(self.V, self.tiles_x, self.tiles_y, self.n, _p(self.depth), _p(self.rect),
+                                  _p(self.keys), _p(self.vals), self.capacity, _p(self.num_pairs), _p(self.overflow),
+                                  ws, wsb, s), "lgs_sort_batch")
+        L.check(lb.lgs_tile_ranges(_p(self.keys), _p(self.num_pairs), _p(self.overflow), self.capacity,
+                                   self.num_tiles, _p(self.ranges), s), "lgs_tile_ranges")
+
+    def render(self, stats: torch.Tensor | None = None):
+        """Enqueue [order] -> render over the binned pairs."""
+        self.tile_order()
+        self.blend(stats)
+
+    def tile_order(self):
+        """Enqueue the longest-first tile order (when the settings use it)."""
+        if self.persistent and self.lpt:
+            ows, owsb = _aligned(self.order_ws)
+            L.check(L.lib().lgs_tile_order(_p(self.ranges), self.num_tiles, _p(self.order), ows, owsb, _stream()),
+                    "lgs_tile_order")
+
+    def blend(self, stats: torch.Tensor | None = None):
+        """Enqueue the render launch itself."""
+        lb, s = L.lib(), _stream()
+        order = _p(self.order) if (self.persistent and self.lpt) else None
+        L.check(lb.lgs_render_batch(self.variant, self.cam_arr, self.V, _p(self.ranges), _p(self.vals),
+                                    _p(self.means2d), _p(self.conic_opacity), _p(self.rgb), _p(self.out_rgb),
+                                    _p(self.out_T), _p(self.out_nc), _p(stats),
+                                    _p(self.queue) if self.persistent else None, order, self.blocks_per_cu, s),
+                "lgs_render_batch")
+
+    def l1(self, target_packed: torch.Tensor):
+        """Enqueue L = mean |images - target| (loss -> self.loss) and its
+        gradient (-> self.grad_rgb)."""
+        _req(target_packed, torch.float32, "target")
+        if target_packed.numel() != self.out_rgb.numel():
+            raise ValueError("target does not match the packed image size")
+        L.check(L.lib().lgs_l1_loss(_p(self.out_rgb), _p(target_packed), self.out_rgb.numel(), _p(self.loss),
+                                    _p(self.grad_rgb), _stream()), "lgs_l1_loss")
+
+    def backward(self, params, grad_rgb: torch.Tensor | None = None, grad_T: torch.Tensor | None = None):
+        """Enqueue the gradient of the step into d_* (raw parameters, summed
+        over views).  grad_rgb defaults to self.grad_rgb (set by l1)."""
+        self._check(params)
+        lb, s = L.lib(), _stream()
+        means3d, log_scales, quats, logits, sh = params
+        g = self.grad_rgb if grad_rgb is None else _req(grad_rgb, torch.float32, "grad_rgb")
+        bv = L.RENDER_PLAIN if (self.variant & 0xF) == L.RENDER_PLAIN else L.RENDER_LOCAL
+        L.check(lb.lgs_render_backward_batch(bv, self.cam_arr, self.V, self.V * self.n, _p(self.ranges),
+                                             _p(self.vals), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
+                                             _p(self.out_T), _p(self.out_nc), _p(g), _p(grad_T), _p(self.g_means2d),
+                                             _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb), s),
+                "lgs_render_backward_batch")
+        L.check(lb.lgs_project_backward_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales),
+                                              _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_means2d),
+                                              _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
+                                              _p(self.d_means3d), _p(self.d_log_scales), _p(self.d_quats),
+                                              _p(self.d_logits), _p(self.d_sh), s), "lgs_project_backward_batch")
+
+    def train_step(self, params, target_packed):
+        """forward + L1 + backward, all enqueued."""
+        self.forward(params)
+        self.l1(target_packed)
+        self.backward(params)
+
+    def grads(self):
+        return dict(means3d=self.d_means3d, log_scales=self.d_log_scales, quats=self.d_quats,
+                    opacity_logits=self.d_logits, sh=self.d_sh)
+
+
+class StepGraph:
+    """A sequence of library calls captured once as a HIP graph and replayed.
+
+    `fn` must only enqueue library work on the current stream (no host reads,
+    no tensor allocation); it runs `warmup` times eagerly, then once under
+    capture on a private stream.  `replay()` orders the graph after the
+    caller's current stream and the caller's stream after the graph.
+    """
+
+    def __init__(self, fn, warmup: int = 1):
+        self.stream = torch.cuda.Stream()
+        self.handle = None
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            for _ in range(warmup):
+                fn()
+        self.stream.synchronize()
+        h = C.c_void_p()
+        sp = C.c_void_p(self.stream.cuda_stream)
+        with torch.cuda.stream(self.stream):
+            L.check(L.lib().lgs_graph_begin(sp), "lgs_graph_begin")
+            try:
+                fn()
+            finally:
+                st = L.lib().lgs_graph_end(sp, C.byref(h))
+            L.check(st, "lgs_graph_end")
+        self.handle = h
+
+    def replay(self):
+        if self.handle is None:
+            raise RuntimeError("graph destroyed")
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        L.check(L.lib().lgs_graph_launch(self.handle, C.c_void_p(self.stream.cuda_stream)), "lgs_graph_launch")
+        cur.wait_stream(self.stream)
+
+    def close(self):
+        if self.handle is not None:
+            L.check(L.lib().lgs_graph_destroy(self.handle), "lgs_graph_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

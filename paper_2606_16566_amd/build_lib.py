@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "liblocalgs.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_bwd.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_bwd.hip", "graph.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",

@@ -68,8 +68,14 @@ extern "C" lgs_status lgs_l1_loss(const float *image, const float *target, int64
 {
     LGS_REQUIRE(count > 0 && image && target && loss && grad, "lgs_l1_loss: bad arguments");
     hipStream_t s = as_stream(stream);
-    double *acc = nullptr;
-    LGS_HIP(hipGetSymbolAddress((void **)&acc, HIP_SYMBOL(g_l1_acc)));
+    // the accumulator's device address, looked up once per device (so the
+    // call stays capturable into a graph)
+    static double *acc_of[64] = {nullptr};
+    int dev = 0;
+    LGS_HIP(hipGetDevice(&dev));
+    LGS_REQUIRE(dev >= 0 && dev < 64, "lgs_l1_loss: device index %d out of range", dev);
+    if (!acc_of[dev]) LGS_HIP(hipGetSymbolAddress((void **)&acc_of[dev], HIP_SYMBOL(g_l1_acc)));
+    double *acc = acc_of[dev];
     unsigned g = grid_for(count, 256);
     if (g > 2048) g = 2048;
     hipLaunchKernelGGL(l1_kernel, dim3(g), dim3(256), 0, s, image, target, count, (float)(1.0 / (double)count), grad,

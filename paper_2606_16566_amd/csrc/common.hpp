@@ -14,6 +14,7 @@ namespace lgs {
 
 constexpr int kTile = LGS_TILE;          // 16x16 pixel tiles
 constexpr int kBlock = 256;              // one workgroup per tile: 4 wave64
+constexpr int kMaxViews = LGS_MAX_VIEWS; // cameras per view batch
 constexpr float kAlphaMax = 0.99f;       // opacity clamp (Sec. III-D-1)
 constexpr double kTMin = 1e-4;           // termination threshold (Alg. 1)
 constexpr double kLowpass = 0.3;         // 2D covariance dilation, px^2

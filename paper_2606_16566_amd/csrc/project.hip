@@ -207,8 +207,17 @@ __device__ __forceinline__ void stage_sh(const float *__restrict__ sh, int64_t g
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// cameras of a view batch, passed by value as a kernel argument
+struct CamBatch {
+    Cam cam[kMaxViews];
+    int V;
+};
+
+// Projection of n Gaussians for every camera of the batch: the raw
+// parameters (and the SH coefficients, staged in LDS) are read once and
+// projected V times; outputs are view-major, element v * n + i.
 template <int DEG>
-__global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+__global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n, const float *__restrict__ means3d,
                                                           const float *__restrict__ log_scales,
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
@@ -224,65 +233,65 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(Cam cam, int64_t n, co
     stage_sh<3 * K>(sh, g0, (int)min((int64_t)64, n - g0), s_sh[wid]);
     const int64_t i = g0 + __lane_id();
     if (i >= n) return;
-    Proj P;
-    int4 r = make_int4(0, 0, 0, 0);
+    const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
+    const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+    const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
+    const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float logit = logits[i];
     const float *shi = s_sh[wid] + __lane_id() * (3 * K);
-    bool vis = project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P)
-               && all_finite(shi, 3 * K) && footprint(cam, P, r);
-    if (!vis) {
-        means2d[i] = make_float2(0.f, 0.f);
-        conic_opacity[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        rgb[3 * i] = 0.f; rgb[3 * i + 1] = 0.f; rgb[3 * i + 2] = 0.f;
-        depth[i] = INFINITY;
-        rect[i] = make_int4(0, 0, 0, 0);
-        return;
-    }
-    double Y[K];
-    sh_eval<DEG, false>(P.dir[0], P.dir[1], P.dir[2], Y, nullptr);
-    double col[3] = {0.5, 0.5, 0.5};
+    const bool sh_ok = all_finite(shi, 3 * K);
+    for (int v = 0; v < cb.V; ++v) {
+        const Cam &cam = cb.cam[v];
+        const int64_t o = (int64_t)v * n + i;
+        Proj P;
+        int4 r = make_int4(0, 0, 0, 0);
+        const bool vis = sh_ok && project_geometry(cam, m3, ls, qt, logit, P) && footprint(cam, P, r);
+        if (!vis) {
+            means2d[o] = make_float2(0.f, 0.f);
+            conic_opacity[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rgb[3 * o] = 0.f; rgb[3 * o + 1] = 0.f; rgb[3 * o + 2] = 0.f;
+            depth[o] = INFINITY;
+            rect[o] = make_int4(0, 0, 0, 0);
+            continue;
+        }
+        double Y[K];
+        sh_eval<DEG, false>(P.dir[0], P.dir[1], P.dir[2], Y, nullptr);
+        double col[3] = {0.5, 0.5, 0.5};
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < K; ++k) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+            for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+        }
+        means2d[o] = make_float2((float)P.mx, (float)P.my);
+        conic_opacity[o] = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
+        for (int ch = 0; ch < 3; ++ch) rgb[3 * o + ch] = (float)fmax(col[ch], 0.0);
+        depth[o] = (float)P.t[2];
+        rect[o] = r;
     }
-    means2d[i] = make_float2((float)P.mx, (float)P.my);
-    conic_opacity[i] = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
-    for (int ch = 0; ch < 3; ++ch) rgb[3 * i + ch] = (float)fmax(col[ch], 0.0);
-    depth[i] = (float)P.t[2];
-    rect[i] = r;
 }
 
-// Gradient of one Gaussian.  shi points at its SH coefficients and dshi at
-// the output slot; they may alias (the coefficients are read first).
+// Raw-parameter gradient of one Gaussian, summed over views.
+struct RawGrad {
+    double m[3], ls[3], q[4], logit;
+};
+
+// Adds one view's contribution.  m3/ls/qt/logit are the Gaussian's raw
+// parameters, shi its SH coefficients and dshi the slot accumulating
+// dL/d sh; g* are this view's gradients of the projected attributes.
 template <int DEG>
-__device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const float *__restrict__ means3d,
-                                                          const float *__restrict__ log_scales,
-                                                          const float *__restrict__ quats,
-                                                          const float *__restrict__ logits,
-                                                          const float *shi, const int4 *__restrict__ rect,
-                                                          const float2 *__restrict__ g_means2d,
-                                                          const float *__restrict__ g_conic,
-                                                          const float *__restrict__ g_opacity,
-                                                          const float *__restrict__ g_rgb, float *__restrict__ d_means3d,
-                                                          float *__restrict__ d_log_scales, float *__restrict__ d_quats,
-                                                          float *__restrict__ d_logits, float *dshi)
+__device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m3, const float *ls, const float *qt,
+                                                  float logit, const float *shi, const int4 r, const float2 g2,
+                                                  const float *g_con, float g_op, const float *g_col, RawGrad &acc,
+                                                  float *dshi)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    const int4 r = rect[i];
     Proj P;
-    bool vis = (r.z > r.x) && (r.w > r.y)
-               && project_geometry(cam, means3d + 3 * i, log_scales + 3 * i, quats + 4 * i, logits[i], P);
-    if (!vis) {
-        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = 0.f; d_log_scales[3 * i + k] = 0.f; }
-        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = 0.f;
-        d_logits[i] = 0.f;
-        for (int k = 0; k < 3 * K; ++k) dshi[k] = 0.f;
-        return;
-    }
-    const double gmx = g_means2d[i].x, gmy = g_means2d[i].y;
-    const double ga = g_conic[3 * i], gb = g_conic[3 * i + 1], gc = g_conic[3 * i + 2];
-    const double go = g_opacity[i];
-    double gcol[3] = {g_rgb[3 * i], g_rgb[3 * i + 1], g_rgb[3 * i + 2]};
+    const bool vis = (r.z > r.x) && (r.w > r.y) && project_geometry(cam, m3, ls, qt, logit, P);
+    if (!vis) return;
+    const double gmx = g2.x, gmy = g2.y;
+    const double ga = g_con[0], gb = g_con[1], gc = g_con[2];
+    const double go = g_op;
+    double gcol[3] = {g_col[0], g_col[1], g_col[2]};
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
     double Y[K], dY[K][3];
@@ -300,7 +309,7 @@ __device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const
         }
     }
     for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] = (float)(gcol[ch] * Y[k]);
+        for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] += (float)(gcol[ch] * Y[k]);
     double gm[3] = {0.0, 0.0, 0.0};
     if (P.dlen > 0.0) {
         const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
@@ -308,7 +317,7 @@ __device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const
     }
 
     // opacity = sigmoid(logit)
-    d_logits[i] = (float)(go * P.o * (1.0 - P.o));
+    acc.logit += go * P.o * (1.0 - P.o);
 
     // conic (a, b, c) = (Y, -Z, X) / det  ->  Sigma2 entries X, Y, Z
     const double id = 1.0 / P.det, id2 = id * id;
@@ -354,7 +363,7 @@ __device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const
     // t = W m + t_c
     for (int k = 0; k < 3; ++k)
         gm[k] += (double)V[0 * 4 + k] * gt[0] + (double)V[1 * 4 + k] * gt[1] + (double)V[2 * 4 + k] * gt[2];
-    for (int k = 0; k < 3; ++k) d_means3d[3 * i + k] = (float)gm[k];
+    for (int k = 0; k < 3; ++k) acc.m[k] += gm[k];
 
     // Sigma3 = M M^T, M = R diag(s): dL/dM = 2 G3 M
     double gR[3][3], gs[3] = {0.0, 0.0, 0.0};
@@ -364,7 +373,7 @@ __device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const
             gR[a][b] = gM * P.s[b];
             gs[b] += gM * P.R[a][b];
         }
-    for (int k = 0; k < 3; ++k) d_log_scales[3 * i + k] = (float)(gs[k] * P.s[k]);
+    for (int k = 0; k < 3; ++k) acc.ls[k] += gs[k] * P.s[k];
     // rotation matrix of the unit quaternion
     const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
     double gq[4];
@@ -377,10 +386,10 @@ __device__ __forceinline__ void project_bwd_one(const Cam &cam, int64_t i, const
                    + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     // normalisation q / |q|
     const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
-    d_quats[4 * i + 0] = (float)((gq[0] - w * dq) / P.qlen);
-    d_quats[4 * i + 1] = (float)((gq[1] - x * dq) / P.qlen);
-    d_quats[4 * i + 2] = (float)((gq[2] - y * dq) / P.qlen);
-    d_quats[4 * i + 3] = (float)((gq[3] - z * dq) / P.qlen);
+    acc.q[0] += (gq[0] - w * dq) / P.qlen;
+    acc.q[1] += (gq[1] - x * dq) / P.qlen;
+    acc.q[2] += (gq[2] - y * dq) / P.qlen;
+    acc.q[3] += (gq[3] - z * dq) / P.qlen;
 }
 
 
@@ -401,7 +410,7 @@ __device__ __forceinline__ void unstage_sh(float *__restrict__ dst_all, int64_t 
 }
 
 template <int DEG>
-__global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, const float *__restrict__ means3d,
+__global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n, const float *__restrict__ means3d,
                                                           const float *__restrict__ log_scales,
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
@@ -414,19 +423,36 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, co
                                                           float *__restrict__ d_logits, float *__restrict__ d_sh)
 {
     constexpr int K3 = 3 * (DEG + 1) * (DEG + 1);
-    __shared__ float s_sh[4][64 * K3];
+    __shared__ float s_sh[2][64 * K3];
+    __shared__ float s_dsh[2][64 * K3];
     const int wid = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
     if (g0 >= n) return;                                   // whole wavefront past the end
     const int cnt = (int)min((int64_t)64, n - g0);
     stage_sh<K3>(sh, g0, cnt, s_sh[wid]);
     const int64_t i = g0 + __lane_id();
+    float *dslot = s_dsh[wid] + __lane_id() * K3;
+    for (int k = 0; k < K3; ++k) dslot[k] = 0.f;
     if (i < n) {
-        float *slot = s_sh[wid] + __lane_id() * K3;
-        project_bwd_one<DEG>(cam, i, means3d, log_scales, quats, logits, slot, rect, g_means2d, g_conic, g_opacity,
-                             g_rgb, d_means3d, d_log_scales, d_quats, d_logits, slot);
+        const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
+        const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+        const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
+        const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
+        const float logit = logits[i];
+        const float *shi = s_sh[wid] + __lane_id() * K3;
+        RawGrad acc = {};
+        for (int v = 0; v < cb.V; ++v) {
+            const int64_t o = (int64_t)v * n + i;
+            const float gc3[3] = {g_conic[3 * o], g_conic[3 * o + 1], g_conic[3 * o + 2]};
+            const float gr3[3] = {g_rgb[3 * o], g_rgb[3 * o + 1], g_rgb[3 * o + 2]};
+            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], g_means2d[o], gc3, g_opacity[o], gr3,
+                                   acc, dslot);
+        }
+        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
+        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)acc.q[k];
+        d_logits[i] = (float)acc.logit;
     }
-    unstage_sh<K3>(d_sh, g0, cnt, s_sh[wid]);
+    unstage_sh<K3>(d_sh, g0, cnt, s_dsh[wid]);
 }
 
 }  // namespace
@@ -434,45 +460,71 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(Cam cam, int64_t n, co
 
 using namespace lgs;
 
-extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t sh_degree, const float *means3d,
-                                  const float *log_scales, const float *quats, const float *opacity_logits,
-                                  const float *sh, float *means2d, float *conic_opacity, float *rgb, float *depth,
-                                  int32_t *rect, void *stream)
+static bool cams_from(const lgs_camera *cameras, int32_t V, CamBatch &cb)
 {
-    Cam cam;
-    LGS_REQUIRE(cam_from(camera, cam), "lgs_project: invalid camera");
+    if (!cameras || V < 1 || V > kMaxViews) return false;
+    cb.V = V;
+    for (int v = 0; v < V; ++v)
+        if (!cam_from(&cameras[v], cb.cam[v])) return false;
+    for (int v = V; v < kMaxViews; ++v) cb.cam[v] = cb.cam[0];
+    return true;
+}
+
+extern "C" lgs_status lgs_project_batch(const lgs_camera *cameras, int32_t num_views, int64_t n, int32_t sh_degree,
+                                        const float *means3d, const float *log_scales, const float *quats,
+                                        const float *opacity_logits, const float *sh, float *means2d,
+                                        float *conic_opacity, float *rgb, float *depth, int32_t *rect, void *stream)
+{
+    CamBatch cb;
+    LGS_REQUIRE(cams_from(cameras, num_views, cb), "lgs_project: invalid camera(s) or num_views not in 1..%d",
+                kMaxViews);
     LGS_REQUIRE(n >= 0, "lgs_project: n < 0");
     LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project: sh_degree must be 0..3");
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh, "lgs_project: null input");
     LGS_REQUIRE(means2d && conic_opacity && rgb && depth && rect, "lgs_project: null output");
     LGS_REQUIRE(((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0) && ((uintptr_t)rect % 16 == 0)
-                    && ((uintptr_t)sh % 16 == 0),
-                "lgs_project: means2d must be 8-byte and conic_opacity/rect/sh 16-byte aligned");
+                    && ((uintptr_t)sh % 16 == 0) && ((uintptr_t)quats % 16 == 0),
+                "lgs_project: means2d must be 8-byte and conic_opacity/rect/sh/quats 16-byte aligned");
     hipStream_t s = as_stream(stream);
     const dim3 grid(grid_for(n, 256)), block(256);
     auto *m2 = reinterpret_cast<float2 *>(means2d);
     auto *co = reinterpret_cast<float4 *>(conic_opacity);
     auto *rc = reinterpret_cast<int4 *>(rect);
+#define LGS_PF(D)                                                                                                 \
+    hipLaunchKernelGGL(project_fwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \
+                       sh, m2, co, rgb, depth, rc)
     switch (sh_degree) {
-    case 0: hipLaunchKernelGGL(project_fwd_kernel<0>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
-    case 1: hipLaunchKernelGGL(project_fwd_kernel<1>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
-    case 2: hipLaunchKernelGGL(project_fwd_kernel<2>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
-    default: hipLaunchKernelGGL(project_fwd_kernel<3>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, sh, m2, co, rgb, depth, rc); break;
+    case 0: LGS_PF(0); break;
+    case 1: LGS_PF(1); break;
+    case 2: LGS_PF(2); break;
+    default: LGS_PF(3); break;
     }
+#undef LGS_PF
     LGS_LAUNCHED("lgs_project");
     return LGS_OK;
 }
 
-extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, int32_t sh_degree,
-                                           const float *means3d, const float *log_scales, const float *quats,
-                                           const float *opacity_logits, const float *sh, const int32_t *rect,
-                                           const float *g_means2d, const float *g_conic, const float *g_opacity,
-                                           const float *g_rgb, float *d_means3d, float *d_log_scales,
-                                           float *d_quats, float *d_opacity_logits, float *d_sh, void *stream)
+extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t sh_degree, const float *means3d,
+                                  const float *log_scales, const float *quats, const float *opacity_logits,
+                                  const float *sh, float *means2d, float *conic_opacity, float *rgb, float *depth,
+                                  int32_t *rect, void *stream)
 {
-    Cam cam;
-    LGS_REQUIRE(cam_from(camera, cam), "lgs_project_backward: invalid camera");
+    return lgs_project_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, means2d,
+                             conic_opacity, rgb, depth, rect, stream);
+}
+
+extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int32_t num_views, int64_t n,
+                                                 int32_t sh_degree, const float *means3d, const float *log_scales,
+                                                 const float *quats, const float *opacity_logits, const float *sh,
+                                                 const int32_t *rect, const float *g_means2d, const float *g_conic,
+                                                 const float *g_opacity, const float *g_rgb, float *d_means3d,
+                                                 float *d_log_scales, float *d_quats, float *d_opacity_logits,
+                                                 float *d_sh, void *stream)
+{
+    CamBatch cb;
+    LGS_REQUIRE(cams_from(cameras, num_views, cb),
+                "lgs_project_backward: invalid camera(s) or num_views not in 1..%d", kMaxViews);
     LGS_REQUIRE(n >= 0, "lgs_project_backward: n < 0");
     LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project_backward: sh_degree must be 0..3");
     if (n == 0) return LGS_OK;
@@ -480,14 +532,14 @@ extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, 
     LGS_REQUIRE(g_means2d && g_conic && g_opacity && g_rgb, "lgs_project_backward: null gradient input");
     LGS_REQUIRE(d_means3d && d_log_scales && d_quats && d_opacity_logits && d_sh, "lgs_project_backward: null output");
     LGS_REQUIRE(((uintptr_t)g_means2d % 8 == 0) && ((uintptr_t)rect % 16 == 0) && ((uintptr_t)sh % 16 == 0)
-                    && ((uintptr_t)d_sh % 16 == 0),
-                "lgs_project_backward: g_means2d must be 8-byte and rect/sh/d_sh 16-byte aligned");
+                    && ((uintptr_t)d_sh % 16 == 0) && ((uintptr_t)quats % 16 == 0),
+                "lgs_project_backward: g_means2d must be 8-byte and rect/sh/d_sh/quats 16-byte aligned");
     hipStream_t s = as_stream(stream);
-    const dim3 grid(grid_for(n, 256)), block(256);
+    const dim3 grid(grid_for(n, 128)), block(128);
     auto *rc = reinterpret_cast<const int4 *>(rect);
     auto *gm = reinterpret_cast<const float2 *>(g_means2d);
 #define LGS_PB(D)                                                                                                   \
-    hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cam, n, means3d, log_scales, quats, opacity_logits, \
+    hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \
                        sh, rc, gm, g_conic, g_opacity, g_rgb, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
     switch (sh_degree) {
     case 0: LGS_PB(0); break;
@@ -498,4 +550,16 @@ extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, 
 #undef LGS_PB
     LGS_LAUNCHED("lgs_project_backward");
     return LGS_OK;
+}
+
+extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, int32_t sh_degree,
+                                           const float *means3d, const float *log_scales, const float *quats,
+                                           const float *opacity_logits, const float *sh, const int32_t *rect,
+                                           const float *g_means2d, const float *g_conic, const float *g_opacity,
+                                           const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                           float *d_quats, float *d_opacity_logits, float *d_sh, void *stream)
+{
+    return lgs_project_backward_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, rect,
+                                      g_means2d, g_conic, g_opacity, g_rgb, d_means3d, d_log_scales, d_quats,
+                                      d_opacity_logits, d_sh, stream);
 }

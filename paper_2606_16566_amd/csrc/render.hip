@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void render_block_kernel(RenderArgs args)
     __shared__ float4 s_c[kBlock];
     __shared__ int s_alive[kBlock / 64];
 
-    const TileCtx<R> tc(args);
+    const TileCtx<R> tc(args, xcd_tile(blockIdx.x, args.num_tiles), threadIdx.x >> 6);
     float T = 1.f;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int32_t last = 0;
@@ -142,24 +142,24 @@ __global__ __launch_bounds__(kBlock) void render_block_kernel(RenderArgs args)
 // ---------------------------------------------------------------------------
 // HOIST_CULL and LOCAL: wavefront-autonomous, culling before prefetching
 // ---------------------------------------------------------------------------
-template <bool UNIFORM, typename R, bool STATS>
-__global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
-{
-    __shared__ Hoisted<R> s_e[kBlock / 64][64];
-    __shared__ float4 s_c[kBlock / 64][64];        // colour, list position in .w
+struct WaveStats {
+    unsigned long long seen = 0, eval = 0, staged = 0;
+};
 
-    const TileCtx<R> tc(args);
+// One 16x4 strip of one tile, processed by one wavefront with its own LDS
+// slots (no workgroup barrier).
+template <bool UNIFORM, typename R, bool STATS>
+__device__ __forceinline__ void render_strip(const RenderArgs &args, const TileCtx<R> &tc, Hoisted<R> *s_e,
+                                             float4 *s_c, WaveStats &st)
+{
     float T = 1.f;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int32_t last = 0;
     bool live = tc.inside;
-    unsigned long long st_seen = 0, st_eval = 0, st_staged = 0;
     const uint2 range = args.ranges[tc.tile];
     const uint64_t lt = lanemask_lt();
-    // this wavefront's strip: columns [sx0, sx0+15], rows [sy0, sy1]
-    const int sx0 = tc.tx * kTile;
-    const int sy0 = tc.ty * kTile + 4 * tc.wid;
-    const int sy1 = min(sy0 + 3, args.H - 1);
+    // this wavefront's sub-tile: columns [sx0, sx1], rows [sy0, sy1]
+    const int sx0 = tc.sx0, sx1 = tc.sx1, sy0 = tc.sy0, sy1 = tc.sy1;
     bool wave_live = __ballot(live) != 0ull;
 
     for (uint32_t base = range.x; wave_live && base < range.y; base += 64) {
@@ -174,17 +174,17 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
             m = args.means2d[g];
             co = args.conic_opacity[g];
             lo = __builtin_amdgcn_logf(co.w);
-            hit = strip_hit(co.x, co.y, co.z, lo, (float)sx0 - m.x, (float)(sx0 + kTile - 1) - m.x,
-                            (float)sy0 - m.y, (float)sy1 - m.y);
+            hit = strip_hit(co.x, co.y, co.z, lo, (float)sx0 - m.x, (float)sx1 - m.x, (float)sy0 - m.y,
+                            (float)sy1 - m.y);
         }
         const uint64_t bits = __ballot(hit);
         const int cnt = __popcll(bits);
-        if (STATS) st_staged += cnt;
+        if (STATS) st.staged += cnt;
         if (hit) {
             const int slot = __popcll(bits & lt);
-            s_e[tc.wid][slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
-            s_c[tc.wid][slot] = make_float4(args.rgb[3 * g], args.rgb[3 * g + 1], args.rgb[3 * g + 2],
-                                            __int_as_float((int)(j - range.x + 1)));
+            s_e[slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
+            s_c[slot] = make_float4(args.rgb[3 * g], args.rgb[3 * g + 1], args.rgb[3 * g + 2],
+                                    __int_as_float((int)(j - range.x + 1)));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -194,8 +194,8 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
         int consumed = chunk;
         if constexpr (UNIFORM) {
             for (int k = 0; k < cnt; ++k) {
-                const float4 f = s_c[tc.wid][k];
-                const float s32 = (float)dot_exponent(s_e[tc.wid][k], tc);
+                const float4 f = s_c[k];
+                const float s32 = (float)dot_exponent(s_e[k], tc);
                 const bool keep = s32 >= kLog2AlphaMin;
                 const float alpha = keep ? fminf(__builtin_amdgcn_exp2f(s32), kAlphaMax) : 0.f;
                 const float w = alpha * T;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
                 T = lv ? Tn : T;
                 last = (lv && keep) ? __float_as_int(f.w) : last;
                 live = lv;
-                if (STATS) st_eval++;
+                if (STATS) st.eval++;
                 if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
                     wave_live = false;
                     if (STATS) consumed = __float_as_int(f.w) - (int)(base - range.x);
@@ -221,8 +221,8 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
             for (int k = 0; k < cnt; ++k) {
                 if (done) break;
                 if (STATS) lane_evals++;
-                const float4 f = s_c[tc.wid][k];
-                const float s32 = (float)dot_exponent(s_e[tc.wid][k], tc);
+                const float4 f = s_c[k];
+                const float s32 = (float)dot_exponent(s_e[k], tc);
                 const float al = fminf(__builtin_amdgcn_exp2f(s32), kAlphaMax);
                 if (!(s32 >= kLog2AlphaMin)) continue;
                 const float test = kLiteral<R> ? T * (1.f - al) : fmaf(-al, T, T);
@@ -238,42 +238,91 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
             if (STATS) {
                 int mx = lane_evals;
                 for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-                st_eval += mx;
+                st.eval += mx;
             }
             wave_live = __ballot(live) != 0ull;
         }
-        if (STATS) st_seen += consumed;
+        if (STATS) st.seen += consumed;
         // all lanes have read this chunk before the next one overwrites it
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     write_pixel(args, tc, C0, C1, C2, T, last);
-    if (STATS) flush_stats<true>(args, st_seen, st_eval, st_staged);
+}
+
+// Grid mode: workgroup = tile, wavefront = strip.  Persistent mode
+// (args.queue != null): every wavefront pops (tile, strip) units from the
+// device counter until all 4 * num_tiles units are taken, so no wavefront
+// waits for the others of its workgroup and the tail is balanced.
+template <bool UNIFORM, typename R, bool STATS, bool Q8>
+__global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
+{
+    __shared__ Hoisted<R> s_e[kBlock / 64][64];
+    __shared__ float4 s_c[kBlock / 64][64];        // colour, list position in .w
+    const int wid = threadIdx.x >> 6;
+    WaveStats st;
+    if (args.queue == nullptr) {
+        const TileCtx<R> tc(args, xcd_tile(blockIdx.x, args.num_tiles), wid, Q8);
+        render_strip<UNIFORM, R, STATS>(args, tc, s_e[wid], s_c[wid], st);
+    } else {
+        const uint32_t units = 4u * (uint32_t)args.num_tiles;
+        for (;;) {
+            uint32_t u = 0;
+            if (__lane_id() == 0) u = atomicAdd(args.queue, 1u);
+            u = __builtin_amdgcn_readfirstlane(u);
+            if (u >= units) break;
+            const int tile = args.order ? (int)args.order[u >> 2] : (int)(u >> 2);
+            const TileCtx<R> tc(args, tile, (int)(u & 3u), Q8);
+            render_strip<UNIFORM, R, STATS>(args, tc, s_e[wid], s_c[wid], st);
+        }
+    }
+    if (STATS) flush_stats<true>(args, st.seen, st.eval, st.staged);
+}
+
+template <bool UNIFORM, typename R, bool Q8>
+void launch_wave(bool stats, dim3 g, dim3 block, hipStream_t s, const RenderArgs &a)
+{
+    if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8>), g, block, 0, s, a);
+    else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8>), g, block, 0, s, a);
 }
 
 template <int V, typename R>
-void launch_render(const RenderArgs &a, bool stats, hipStream_t s)
+void launch_render(const RenderArgs &a, bool stats, bool q8, unsigned grid, hipStream_t s)
 {
-    const dim3 grid(a.num_tiles), block(kBlock);
+    const dim3 g(grid), block(kBlock);
     switch (V) {
     case LGS_RENDER_PLAIN:
-        if (stats) hipLaunchKernelGGL((render_block_kernel<false, R, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((render_block_kernel<false, R, false>), grid, block, 0, s, a);
+        if (stats) hipLaunchKernelGGL((render_block_kernel<false, R, true>), g, block, 0, s, a);
+        else hipLaunchKernelGGL((render_block_kernel<false, R, false>), g, block, 0, s, a);
         break;
     case LGS_RENDER_HOIST:
-        if (stats) hipLaunchKernelGGL((render_block_kernel<true, R, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((render_block_kernel<true, R, false>), grid, block, 0, s, a);
+        if (stats) hipLaunchKernelGGL((render_block_kernel<true, R, true>), g, block, 0, s, a);
+        else hipLaunchKernelGGL((render_block_kernel<true, R, false>), g, block, 0, s, a);
         break;
     case LGS_RENDER_HOIST_CULL:
-        if (stats) hipLaunchKernelGGL((render_wave_kernel<false, R, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((render_wave_kernel<false, R, false>), grid, block, 0, s, a);
+        if (q8) launch_wave<false, R, true>(stats, g, block, s, a);
+        else launch_wave<false, R, false>(stats, g, block, s, a);
         break;
     default:
-        if (stats) hipLaunchKernelGGL((render_wave_kernel<true, R, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((render_wave_kernel<true, R, false>), grid, block, 0, s, a);
+        if (q8) launch_wave<true, R, true>(stats, g, block, s, a);
+        else launch_wave<true, R, false>(stats, g, block, s, a);
         break;
     }
+}
+
+int device_cus()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
 }
 
 }  // namespace
@@ -281,39 +330,65 @@ void launch_render(const RenderArgs &a, bool stats, hipStream_t s)
 
 using namespace lgs;
 
+extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
+                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
+                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
+                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
+                                       const uint32_t *tile_order, int32_t blocks_per_cu, void *stream)
+{
+    LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_batch: num_views must be 1..%d",
+                kMaxViews);
+    LGS_REQUIRE(cameras != nullptr, "lgs_render_batch: null cameras");
+    Cam cams[kMaxViews];
+    for (int v = 0; v < num_views; ++v)
+        LGS_REQUIRE(cam_from(&cameras[v], cams[v]), "lgs_render_batch: invalid camera %d", v);
+    const int v = variant & 0xF;
+    const bool fp32 = (variant & LGS_RENDER_FP32) != 0;
+    const bool q8 = (variant & LGS_RENDER_Q8) != 0;
+    LGS_REQUIRE(v >= 0 && v <= 3 && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8)) == 0,
+                "lgs_render: unknown variant %d", variant);
+    LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
+    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && (means2d == nullptr || (uintptr_t)means2d % 8 == 0)
+                    && (conic_opacity == nullptr || (uintptr_t)conic_opacity % 16 == 0),
+                "lgs_render: misaligned ranges/means2d/conic_opacity");
+    render::RenderArgs a = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb,
+                                             out_T, out_ncontrib, stats);
+    hipStream_t s = as_stream(stream);
+    const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
+    unsigned grid = (unsigned)a.num_tiles;
+    if (persistent) {
+        fill_async<uint32_t>(queue, 0u, 1, s);
+        a.queue = queue;
+        a.order = tile_order;
+        const int per = blocks_per_cu > 0 ? blocks_per_cu : 8;
+        grid = (unsigned)(device_cus() * per);
+    }
+    const bool st = stats != nullptr;
+    if (fp32) {
+        switch (v) {
+        case 0: launch_render<0, float>(a, st, q8, grid, s); break;
+        case 1: launch_render<1, float>(a, st, q8, grid, s); break;
+        case 2: launch_render<2, float>(a, st, q8, grid, s); break;
+        default: launch_render<3, float>(a, st, q8, grid, s); break;
+        }
+    } else {
+        switch (v) {
+        case 0: launch_render<0, double>(a, st, q8, grid, s); break;
+        case 1: launch_render<1, double>(a, st, q8, grid, s); break;
+        case 2: launch_render<2, double>(a, st, q8, grid, s); break;
+        default: launch_render<3, double>(a, st, q8, grid, s); break;
+        }
+    }
+    LGS_LAUNCHED("lgs_render");
+    return LGS_OK;
+}
+
 extern "C" lgs_status lgs_render(int32_t variant, const lgs_camera *camera, const uint32_t *ranges,
                                  const uint32_t *values, const float *means2d, const float *conic_opacity,
                                  const float *rgb, float *out_rgb, float *out_T, int32_t *out_ncontrib,
                                  uint64_t *stats, void *stream)
 {
-    Cam cam;
-    LGS_REQUIRE(cam_from(camera, cam), "lgs_render: invalid camera");
-    const int v = variant & 0xF;
-    const bool fp32 = (variant & LGS_RENDER_FP32) != 0;
-    LGS_REQUIRE(v >= 0 && v <= 3 && (variant & ~0x1F) == 0, "lgs_render: unknown variant %d", variant);
-    LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
-    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && (means2d == nullptr || (uintptr_t)means2d % 8 == 0)
-                    && (conic_opacity == nullptr || (uintptr_t)conic_opacity % 16 == 0),
-                "lgs_render: misaligned ranges/means2d/conic_opacity");
-    render::RenderArgs a = render::make_args(cam, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
-                                             out_ncontrib, stats);
-    hipStream_t s = as_stream(stream);
-    const bool st = stats != nullptr;
-    if (fp32) {
-        switch (v) {
-        case 0: launch_render<0, float>(a, st, s); break;
-        case 1: launch_render<1, float>(a, st, s); break;
-        case 2: launch_render<2, float>(a, st, s); break;
-        default: launch_render<3, float>(a, st, s); break;
-        }
-    } else {
-        switch (v) {
-        case 0: launch_render<0, double>(a, st, s); break;
-        case 1: launch_render<1, double>(a, st, s); break;
-        case 2: launch_render<2, double>(a, st, s); break;
-        default: launch_render<3, double>(a, st, s); break;
-        }
-    }
-    LGS_LAUNCHED("lgs_render");
-    return LGS_OK;
+    LGS_REQUIRE(camera != nullptr, "lgs_render: invalid camera");
+    return lgs_render_batch(variant, camera, 1, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
+                            out_ncontrib, stats, nullptr, nullptr, 0, stream);
 }

@@ -54,20 +54,22 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     __shared__ int s_max[kBlock / 64];
 
     const RenderArgs &a = ba.r;
-    const TileCtx<double> tc(a);
+    const TileCtx<double> tc(a, xcd_tile(blockIdx.x, a.num_tiles), threadIdx.x >> 6);
     const int lane = __lane_id(), wid = tc.wid;
     const int px = tc.px, py = tc.py;
     const bool inside = tc.inside;
     const int tx = tc.tx, ty = tc.ty;
-    const int64_t HW = (int64_t)a.W * a.H;
-    const int64_t p = (int64_t)py * a.W + px;
+    const int64_t HW = (int64_t)tc.W * tc.H;
+    const int64_t p = tc.pix0 + (int64_t)py * tc.W + px;           // packed pixel index
+    const int64_t pc = 3 * tc.pix0 + (int64_t)py * tc.W + px;      // channel-0 index of this view
     const int last = inside ? a.out_nc[p] : 0;
     const double Tf = inside ? (double)a.out_T[p] : 1.0;
     double T = Tf;
-    const float gc0 = inside ? ba.grad_rgb[p] : 0.f, gc1 = inside ? ba.grad_rgb[HW + p] : 0.f,
-                gc2 = inside ? ba.grad_rgb[2 * HW + p] : 0.f;
+    const float gc0 = inside ? ba.grad_rgb[pc] : 0.f, gc1 = inside ? ba.grad_rgb[HW + pc] : 0.f,
+                gc2 = inside ? ba.grad_rgb[2 * HW + pc] : 0.f;
     const double gt = (inside && ba.grad_T) ? (double)ba.grad_T[p] : 0.0;
-    double R0 = Tf * a.bg0, R1 = Tf * a.bg1, R2 = Tf * a.bg2;
+    const float *bg = a.vt.bg[tc.view];
+    double R0 = Tf * bg[0], R1 = Tf * bg[1], R2 = Tf * bg[2];
 
     int wmax = last;
 #pragma unroll
@@ -99,8 +101,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 const float x0 = (float)(tx * kTile) - m.x, x1 = (float)(tx * kTile + kTile - 1) - m.x;
                 for (int w = 0; w < 4; ++w) {
                     const int r0 = ty * kTile + 4 * w;
-                    if (r0 > a.H - 1) break;
-                    const int r1 = min(r0 + 3, a.H - 1);
+                    if (r0 > tc.H - 1) break;
+                    const int r1 = min(r0 + 3, tc.H - 1);
                     if (strip_hit(co.x, co.y, co.z, lo, x0, x1, (float)r0 - m.y, (float)r1 - m.y)) mk |= 1u << w;
                 }
                 s_m[k] = (uint8_t)mk;
@@ -194,36 +196,52 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
 
 using namespace lgs;
 
+extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
+                                                int64_t n_elem, const uint32_t *ranges, const uint32_t *values,
+                                                const float *means2d, const float *conic_opacity, const float *rgb,
+                                                const float *out_T, const int32_t *out_ncontrib,
+                                                const float *grad_rgb, const float *grad_T, float *g_means2d,
+                                                float *g_conic, float *g_opacity, float *g_rgb, void *stream)
+{
+    LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_backward: num_views must be 1..%d", kMaxViews);
+    LGS_REQUIRE(cameras != nullptr, "lgs_render_backward: invalid camera");
+    Cam cams[kMaxViews];
+    for (int v = 0; v < num_views; ++v)
+        LGS_REQUIRE(cam_from(&cameras[v], cams[v]), "lgs_render_backward: invalid camera %d", v);
+    const int v = variant & 0xF;
+    LGS_REQUIRE(v == LGS_RENDER_PLAIN || v == LGS_RENDER_LOCAL, "lgs_render_backward: variant must be PLAIN or LOCAL");
+    LGS_REQUIRE(n_elem >= 0, "lgs_render_backward: n < 0");
+    LGS_REQUIRE(ranges && out_T && out_ncontrib && grad_rgb, "lgs_render_backward: null input");
+    LGS_REQUIRE(n_elem == 0 || (values && means2d && conic_opacity && rgb && g_means2d && g_conic && g_opacity && g_rgb),
+                "lgs_render_backward: null argument");
+    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0),
+                "lgs_render_backward: misaligned ranges/means2d/conic_opacity");
+    hipStream_t s = as_stream(stream);
+    fill_async<float>(g_means2d, 0.f, 2 * n_elem, s);
+    fill_async<float>(g_conic, 0.f, 3 * n_elem, s);
+    fill_async<float>(g_opacity, 0.f, n_elem, s);
+    fill_async<float>(g_rgb, 0.f, 3 * n_elem, s);
+    BwdArgs a;
+    a.r = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
+                    const_cast<int32_t *>(out_ncontrib), nullptr);
+    a.grad_rgb = grad_rgb; a.grad_T = grad_T;
+    a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
+    if (a.r.num_tiles > 0) {
+        if (v == LGS_RENDER_LOCAL)
+            hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+    }
+    LGS_LAUNCHED("lgs_render_backward");
+    return LGS_OK;
+}
+
 extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *camera, int64_t n, const uint32_t *ranges,
                                           const uint32_t *values, const float *means2d, const float *conic_opacity,
                                           const float *rgb, const float *out_T, const int32_t *out_ncontrib,
                                           const float *grad_rgb, const float *grad_T, float *g_means2d, float *g_conic,
                                           float *g_opacity, float *g_rgb, void *stream)
 {
-    Cam cam;
-    LGS_REQUIRE(cam_from(camera, cam), "lgs_render_backward: invalid camera");
-    const int v = variant & 0xF;
-    LGS_REQUIRE(v == LGS_RENDER_PLAIN || v == LGS_RENDER_LOCAL, "lgs_render_backward: variant must be PLAIN or LOCAL");
-    LGS_REQUIRE(n >= 0, "lgs_render_backward: n < 0");
-    LGS_REQUIRE(ranges && out_T && out_ncontrib && grad_rgb, "lgs_render_backward: null input");
-    LGS_REQUIRE(n == 0 || (values && means2d && conic_opacity && rgb && g_means2d && g_conic && g_opacity && g_rgb),
-                "lgs_render_backward: null argument");
-    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0),
-                "lgs_render_backward: misaligned ranges/means2d/conic_opacity");
-    hipStream_t s = as_stream(stream);
-    fill_async<float>(g_means2d, 0.f, 2 * n, s);
-    fill_async<float>(g_conic, 0.f, 3 * n, s);
-    fill_async<float>(g_opacity, 0.f, n, s);
-    fill_async<float>(g_rgb, 0.f, 3 * n, s);
-    BwdArgs a;
-    a.r = make_args(cam, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
-                    const_cast<int32_t *>(out_ncontrib), nullptr);
-    a.grad_rgb = grad_rgb; a.grad_T = grad_T;
-    a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
-    if (v == LGS_RENDER_LOCAL)
-        hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
-    LGS_LAUNCHED("lgs_render_backward");
-    return LGS_OK;
+    return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, means2d, conic_opacity, rgb, out_T,
+                                     out_ncontrib, grad_rgb, grad_T, g_means2d, g_conic, g_opacity, g_rgb, stream);
 }

@@ -12,6 +12,19 @@ constexpr float kLog2AlphaMin = -7.99435343685885793f;
 constexpr float kAlphaMinF = 1.0f / 255.0f;
 constexpr float kLn2f = 0.693147180559945309f;
 
+// Up to kMaxViews cameras of different sizes share one flattened tile space:
+// view v owns global tiles [tile_off[v], tile_off[v+1]) and its outputs start
+// at pixel pix_off[v] of the packed output buffers.
+
+struct ViewTable {
+    int V;
+    int tile_off[kMaxViews + 1];
+    int tiles_x[kMaxViews];
+    int W[kMaxViews], H[kMaxViews];
+    int64_t pix_off[kMaxViews];
+    float bg[kMaxViews][3];
+};
+
 struct RenderArgs {
     const uint2 *ranges;
     const uint32_t *values;
@@ -22,13 +35,37 @@ struct RenderArgs {
     float *out_T;
     int32_t *out_nc;
     unsigned long long *stats;
-    int W, H, tiles_x, num_tiles;
-    float bg0, bg1, bg2;
+    uint32_t *queue;            // persistent mode: work counter (zeroed before launch), else null
+    const uint32_t *order;      // persistent mode: tile of each queue position, or null for index order
+    int num_tiles;              // all views
+    ViewTable vt;
 };
 
-inline RenderArgs make_args(const Cam &cam, const uint32_t *ranges, const uint32_t *values, const float *means2d,
-                            const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
-                            int32_t *out_nc, uint64_t *stats)
+inline void fill_views(ViewTable &vt, const Cam *cams, int V)
+{
+    vt.V = V;
+    int t = 0;
+    int64_t px = 0;
+    for (int v = 0; v < V; ++v) {
+        vt.tile_off[v] = t;
+        vt.tiles_x[v] = cams[v].tiles_x;
+        vt.W[v] = cams[v].W;
+        vt.H[v] = cams[v].H;
+        vt.pix_off[v] = px;
+        for (int c = 0; c < 3; ++c) vt.bg[v][c] = cams[v].bg[c];
+        t += cams[v].tiles_x * cams[v].tiles_y;
+        px += (int64_t)cams[v].W * cams[v].H;
+    }
+    vt.tile_off[V] = t;
+    for (int v = V; v < kMaxViews; ++v) {
+        vt.tiles_x[v] = 1; vt.W[v] = 0; vt.H[v] = 0; vt.pix_off[v] = px;
+        vt.bg[v][0] = vt.bg[v][1] = vt.bg[v][2] = 0.f;
+    }
+}
+
+inline RenderArgs make_args(const Cam *cams, int V, const uint32_t *ranges, const uint32_t *values,
+                            const float *means2d, const float *conic_opacity, const float *rgb, float *out_rgb,
+                            float *out_T, int32_t *out_nc, uint64_t *stats)
 {
     RenderArgs a;
     a.ranges = reinterpret_cast<const uint2 *>(ranges);
@@ -38,8 +75,10 @@ inline RenderArgs make_args(const Cam &cam, const uint32_t *ranges, const uint32
     a.rgb = rgb;
     a.out_rgb = out_rgb; a.out_T = out_T; a.out_nc = out_nc;
     a.stats = reinterpret_cast<unsigned long long *>(stats);
-    a.W = cam.W; a.H = cam.H; a.tiles_x = cam.tiles_x; a.num_tiles = cam.tiles_x * cam.tiles_y;
-    a.bg0 = cam.bg[0]; a.bg1 = cam.bg[1]; a.bg2 = cam.bg[2];
+    a.queue = nullptr;
+    a.order = nullptr;
+    fill_views(a.vt, cams, V);
+    a.num_tiles = a.vt.tile_off[V];
     return a;
 }
 
@@ -51,26 +90,53 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
     return x * q + (x < r ? x : r) + k;
 }
 
-// Geometry of one lane: pixel, tile, wavefront strip and the tile-local
-// basis.  The tile-local origin is the tile centre, so the basis coordinates
-// are the exact values -7.5 .. 7.5.
+// Geometry of one lane for global tile `tile` and wavefront sub-tile
+// `strip` (0..3): view, pixel, output offset and the tile-local basis.  The
+// sub-tiles are 16x4 row strips, or with q8 the four 8x8 quadrants.  The
+// tile-local origin is the tile centre, so the basis coordinates are the
+// exact values -7.5 .. 7.5.  [sx0, sx1] x [sy0, sy1] is the sub-tile clipped
+// to the image (empty when no pixel of it is inside).
 template <typename R>
 struct TileCtx {
-    int tile, tx, ty, wid, px, py;
+    int tile, view, tx, ty, wid, px, py, W, H;
+    int sx0, sx1, sy0, sy1;
     bool inside;
+    int64_t pix0;       // first pixel of this view in the packed outputs
     double ox, oy;
     R xl, yl, bxx, bxy, byy;
-    __device__ __forceinline__ explicit TileCtx(const RenderArgs &a)
+    __device__ __forceinline__ TileCtx(const RenderArgs &a, int gtile, int strip, bool q8 = false)
     {
-        tile = xcd_tile(blockIdx.x, a.num_tiles);
-        tx = tile % a.tiles_x;
-        ty = tile / a.tiles_x;
+        tile = gtile;
+        int v = 0;
+        while (v + 1 < a.vt.V && gtile >= a.vt.tile_off[v + 1]) ++v;
+        view = v;
+        const int lt = gtile - a.vt.tile_off[v];
+        tx = lt % a.vt.tiles_x[v];
+        ty = lt / a.vt.tiles_x[v];
+        W = a.vt.W[v];
+        H = a.vt.H[v];
+        pix0 = a.vt.pix_off[v];
         const int lane = __lane_id();
-        wid = threadIdx.x >> 6;
-        const int lx = lane & 15, ly = (wid << 2) | (lane >> 4);
+        wid = strip;
+        int lx, ly;
+        if (q8) {
+            lx = ((wid & 1) << 3) | (lane & 7);
+            ly = ((wid >> 1) << 3) | (lane >> 3);
+            sx0 = tx * kTile + ((wid & 1) << 3);
+            sy0 = ty * kTile + ((wid >> 1) << 3);
+            sx1 = min(sx0 + 7, W - 1);
+            sy1 = min(sy0 + 7, H - 1);
+        } else {
+            lx = lane & 15;
+            ly = (wid << 2) | (lane >> 4);
+            sx0 = tx * kTile;
+            sy0 = ty * kTile + (wid << 2);
+            sx1 = min(sx0 + kTile - 1, W - 1);
+            sy1 = min(sy0 + 3, H - 1);
+        }
         px = tx * kTile + lx;
         py = ty * kTile + ly;
-        inside = px < a.W && py < a.H;
+        inside = px < W && py < H;
         ox = tx * kTile + 7.5;
         oy = ty * kTile + 7.5;
         xl = (R)(lx - 7.5);
@@ -163,13 +229,15 @@ __device__ __forceinline__ void write_pixel(const RenderArgs &a, const TileCtx<R
                                             float T, int32_t last)
 {
     if (!tc.inside) return;
-    const int64_t HW = (int64_t)a.W * a.H;
-    const int64_t p = (int64_t)tc.py * a.W + tc.px;
-    a.out_rgb[p] = C0 + T * a.bg0;
-    a.out_rgb[HW + p] = C1 + T * a.bg1;
-    a.out_rgb[2 * HW + p] = C2 + T * a.bg2;
-    a.out_T[p] = T;
-    a.out_nc[p] = last;
+    const int64_t HW = (int64_t)tc.W * tc.H;
+    const int64_t p = (int64_t)tc.py * tc.W + tc.px;
+    float *rgb = a.out_rgb + 3 * tc.pix0;
+    const float *bg = a.vt.bg[tc.view];
+    rgb[p] = C0 + T * bg[0];
+    rgb[HW + p] = C1 + T * bg[1];
+    rgb[2 * HW + p] = C2 + T * bg[2];
+    a.out_T[tc.pix0 + p] = T;
+    a.out_nc[tc.pix0 + p] = last;
 }
 
 // Counters: [0] (wavefront, Gaussian) steps met by live wavefronts, [1] steps

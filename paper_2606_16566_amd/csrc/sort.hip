@@ -191,16 +191,26 @@ __global__ __launch_bounds__(1024) void pair_partials_kernel(uint64_t *partials,
 // ---------------------------------------------------------------------------
 constexpr int kDupPerLane = 4;
 
+// Tile grids of a view batch: element e = v * per_view + g belongs to view v,
+// whose tiles are the global ids [tile_off[v], tile_off[v] + tx * ty).
+struct TileGrids {
+    uint32_t per_view;
+    int V;
+    int tile_off[kMaxViews];
+    int tiles_x[kMaxViews];
+};
+
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__restrict__ order,
                                                            const int4 *__restrict__ rect,
                                                            const uint32_t *__restrict__ off,
-                                                           const uint64_t *p_total, uint64_t cap, int tiles_x,
+                                                           const uint64_t *p_total, uint64_t cap, TileGrids tg,
                                                            int64_t n, uint32_t *__restrict__ keys,
                                                            uint32_t *__restrict__ vals)
 {
     __shared__ uint32_t s_off[kBlock + 1];
     __shared__ int4 s_rect[kBlock];
     __shared__ uint32_t s_id[kBlock];
+    __shared__ int2 s_grid[kBlock];     // (first global tile, tiles_x) of the element's view
     const int64_t first = (int64_t)blockIdx.x * kBlock;
     if (first >= n) return;
     const int cnt = (int)min((int64_t)kBlock, n - first);
@@ -208,8 +218,10 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__res
     const uint32_t lim = (uint32_t)(total < cap ? total : cap);
     if ((int)threadIdx.x < cnt) {
         const uint32_t g = order[first + threadIdx.x];
+        const int v = tg.V > 1 ? (int)(g / tg.per_view) : 0;
         s_id[threadIdx.x] = g;
         s_rect[threadIdx.x] = rect[g];
+        s_grid[threadIdx.x] = make_int2(tg.tile_off[v], tg.tiles_x[v]);
         s_off[threadIdx.x] = off[first + threadIdx.x];
     }
     if (threadIdx.x == 0) s_off[cnt] = first + cnt < n ? off[first + cnt] : lim;
@@ -246,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__res
                 w = (uint32_t)(q.z - q.x);
                 tx = 0; ty = 0;
             }
-            kk[e] = (uint32_t)((q.y + (int)ty) * tiles_x + q.x + (int)tx);
+            const int2 gr = s_grid[k];
+            kk[e] = (uint32_t)(gr.x + (q.y + (int)ty) * gr.y + q.x + (int)tx);
             vv[e] = s_id[k];
             if (++tx == w) { tx = 0; ++ty; }
         }
@@ -473,6 +486,25 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *
     }
 }
 
+// Work-order key of a tile for longest-first scheduling: 255 minus a
+// logarithmic code of its list length with 8 steps per octave, so one stable
+// 8-bit pass orders the tiles by non-increasing length class, index order
+// within a class.  Empty tiles get key 255.
+__global__ void lpt_key_kernel(const uint2 *__restrict__ ranges, int64_t num_tiles, uint32_t *__restrict__ keys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= num_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = r.y > r.x ? r.y - r.x : 0u;
+    uint32_t code = 0;
+    if (len > 0) {
+        const uint32_t e = 31u - (uint32_t)__clz(len);
+        const uint32_t m = e >= 3 ? (len >> (e - 3)) & 7u : (len << (3 - e)) & 7u;
+        code = min(e * 8u + m + 1u, 255u);
+    }
+    keys[t] = 255u - code;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -547,12 +579,27 @@ extern "C" size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int
     return plan_workspace(nullptr, n, capacity_pairs).bytes;
 }
 
-extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
-                               uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs, int64_t *num_pairs,
-                               int32_t *overflow, void *workspace, size_t workspace_bytes, void *stream)
+extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
+                                     int64_t n_per_view, const float *depth, const int32_t *rect,
+                                     uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                                     int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
+                                     void *stream)
 {
-    LGS_REQUIRE(n >= 0 && n < (int64_t)UINT32_MAX, "lgs_sort: n out of range");
-    LGS_REQUIRE(tiles_x > 0 && tiles_y > 0 && (int64_t)tiles_x * tiles_y < (1ll << 31), "lgs_sort: bad tile grid");
+    LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews && tiles_x && tiles_y,
+                "lgs_sort: num_views must be 1..%d with tile grids", kMaxViews);
+    LGS_REQUIRE(n_per_view >= 0 && n_per_view * num_views < (int64_t)UINT32_MAX, "lgs_sort: n out of range");
+    const int64_t n = n_per_view * num_views;
+    TileGrids tg{};
+    tg.per_view = (uint32_t)(n_per_view > 0 ? n_per_view : 1);
+    tg.V = num_views;
+    int64_t total_tiles = 0;
+    for (int v = 0; v < num_views; ++v) {
+        LGS_REQUIRE(tiles_x[v] > 0 && tiles_y[v] > 0, "lgs_sort: bad tile grid of view %d", v);
+        tg.tile_off[v] = (int)total_tiles;
+        tg.tiles_x[v] = tiles_x[v];
+        total_tiles += (int64_t)tiles_x[v] * tiles_y[v];
+        LGS_REQUIRE(total_tiles < (1ll << 31), "lgs_sort: too many tiles");
+    }
     LGS_REQUIRE(capacity_pairs >= 0 && capacity_pairs < (int64_t)UINT32_MAX, "lgs_sort: capacity out of range");
     LGS_REQUIRE(num_pairs && overflow, "lgs_sort: null num_pairs/overflow");
     LGS_REQUIRE(n == 0 || (depth && rect), "lgs_sort: null input");
@@ -582,7 +629,7 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
     //    overflow check.  The number of tile-sort passes decides which buffer
     //    receives the pairs so that the sorted result ends in the caller's.
     int bits = 1;
-    while ((1ll << bits) < (int64_t)tiles_x * tiles_y) ++bits;
+    while ((1ll << bits) < total_tiles) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint32_t *k0 = (passes & 1) ? w.pk : tile_keys, *v0 = (passes & 1) ? w.pv : values;
     uint32_t *k1 = (passes & 1) ? tile_keys : w.pk, *v1 = (passes & 1) ? values : w.pv;
@@ -600,7 +647,7 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
     if (n > 0)
         hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order, rc,
                            (const uint32_t *)w.pair_off, (const uint64_t *)w.p_total, (uint64_t)capacity_pairs,
-                           tiles_x, n, k0, v0);
+                           tg, n, k0, v0);
     // 4. stable sort of the pairs by tile id, the key bits split evenly over
     //    the passes (longer digit runs per block than 8 + remainder)
     for (int pass = 0, shift = 0; pass < passes; ++pass) {
@@ -611,6 +658,14 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
     }
     LGS_LAUNCHED("lgs_sort");
     return LGS_OK;
+}
+
+extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
+                               uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs, int64_t *num_pairs,
+                               int32_t *overflow, void *workspace, size_t workspace_bytes, void *stream)
+{
+    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, tile_keys, values, capacity_pairs, num_pairs,
+                          overflow, workspace, workspace_bytes, stream);
 }
 
 extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, const int32_t *overflow,
@@ -628,5 +683,55 @@ extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *
                            reinterpret_cast<uint2 *>(ranges));
     }
     LGS_LAUNCHED("lgs_tile_ranges");
+    return LGS_OK;
+}
+
+namespace {
+struct OrderWorkspace {
+    uint32_t *keys, *keys_out, *hist, *digit_total;
+    size_t bytes;
+};
+
+OrderWorkspace plan_order(char *base, int64_t num_tiles)
+{
+    OrderWorkspace w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes > 0 ? bytes : 1);
+        return p;
+    };
+    w.keys = (uint32_t *)take(sizeof(uint32_t) * num_tiles);
+    w.keys_out = (uint32_t *)take(sizeof(uint32_t) * num_tiles);
+    w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * (radix_blocks(num_tiles) + 1));
+    w.digit_total = (uint32_t *)take(sizeof(uint32_t) * kRadixBins);
+    w.bytes = off;
+    return w;
+}
+}  // namespace
+
+extern "C" size_t lgs_tile_order_workspace_size(int32_t num_tiles)
+{
+    if (num_tiles <= 0) return 0;
+    return plan_order(nullptr, num_tiles).bytes;
+}
+
+extern "C" lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *order, void *workspace,
+                                     size_t workspace_bytes, void *stream)
+{
+    LGS_REQUIRE(num_tiles > 0 && ranges && order, "lgs_tile_order: bad arguments");
+    LGS_REQUIRE((uintptr_t)ranges % 8 == 0, "lgs_tile_order: ranges must be 8-byte aligned");
+    const OrderWorkspace need = plan_order(nullptr, num_tiles);
+    LGS_REQUIRE(workspace && workspace_bytes >= need.bytes && (uintptr_t)workspace % 256 == 0,
+                "lgs_tile_order: workspace must be 256-byte aligned and at least %zu bytes", need.bytes);
+    hipStream_t s = as_stream(stream);
+    const OrderWorkspace ow = plan_order(static_cast<char *>(workspace), num_tiles);
+    hipLaunchKernelGGL(lpt_key_kernel, dim3(grid_for(num_tiles, 256)), dim3(256), 0, s,
+                       reinterpret_cast<const uint2 *>(ranges), (int64_t)num_tiles, ow.keys);
+    SortWorkspace w{};
+    w.hist = ow.hist;
+    w.digit_total = ow.digit_total;
+    radix_pass(ow.keys, nullptr, ow.keys_out, order, num_tiles, nullptr, 0, 8, w, s);
+    LGS_LAUNCHED("lgs_tile_order");
     return LGS_OK;
 }

@@ -18,14 +18,17 @@ VARIANTS = {"plain": L.RENDER_PLAIN, "hoist": L.RENDER_HOIST, "hoist_cull": L.RE
 
 
 def variant_code(variant) -> int:
-    """'local' / 'plain' / ... with an optional '_fp32' suffix, or an int."""
+    """'local' / 'plain' / ... with optional '_q8' and '_fp32' suffixes (in
+    that order, e.g. 'local_q8_fp32'), or an int."""
     if isinstance(variant, int):
         return variant
     v = variant.lower()
-    fp32 = v.endswith("_fp32")
-    if fp32:
-        v = v[:-5]
-    return VARIANTS[v] | (L.RENDER_FP32 if fp32 else 0)
+    code = 0
+    if v.endswith("_fp32"):
+        v, code = v[:-5], code | L.RENDER_FP32
+    if v.endswith("_q8"):
+        v, code = v[:-3], code | L.RENDER_Q8
+    return VARIANTS[v] | code
 
 
 def _p(t):
@@ -204,7 +207,7 @@ class LocalGSFunction(torch.autograd.Function):
         means3d, log_scales, quats, opacity_logits, sh, T, nc = ctx.saved_tensors
         grad_img = grad_img.contiguous() if grad_img is not None else torch.zeros((3,) + T.shape, device=T.device)
         grad_T = grad_T.contiguous() if grad_T is not None else None
-        var = ctx.variant if variant_code(ctx.variant) & 0xF in (L.RENDER_PLAIN, L.RENDER_LOCAL) else "local"
+        var = "plain" if variant_code(ctx.variant) & 0xF == L.RENDER_PLAIN else "local"
         g = render_backward(var, ctx.cam, ctx.binned, ctx.proj, T, nc, grad_img, grad_T)
         d = project_backward(ctx.cam, means3d, log_scales, quats, opacity_logits, sh, ctx.proj.rect, g)
         return d["means3d"], d["log_scales"], d["quats"], d["opacity_logits"], d["sh"], None, None, None

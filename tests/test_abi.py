@@ -75,3 +75,45 @@ def test_variant_codes():
     assert R.variant_code("plain") == L.RENDER_PLAIN
     assert R.variant_code("local") == L.RENDER_LOCAL
     assert R.variant_code("hoist_cull_fp32") == L.RENDER_HOIST_CULL | L.RENDER_FP32
+
+
+def test_batch_and_graph_arguments_rejected_on_host():
+    L = _lib()
+    lb = L.lib()
+    cams = (L.LgsCamera * 17)()
+    for c in cams:
+        c.width, c.height, c.fx, c.fy = 16, 16, 100.0, 100.0
+    for nv in (0, 17):
+        assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 11)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_batch(3, cams, nv, *([None] * 9), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 14)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 16)) == L.LGS_ERR_INVALID_ARG
+    tx = (C.c_int32 * 2)(4, 0)
+    assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, 10, None, None, None, 0, None) == \
+        L.LGS_ERR_INVALID_ARG
+    assert lb.lgs_graph_begin(None) == L.LGS_ERR_INVALID_ARG
+    assert lb.lgs_graph_launch(None, None) == L.LGS_ERR_INVALID_ARG
+    assert lb.lgs_graph_destroy(None) == L.LGS_OK
+    assert lb.lgs_tile_order(None, 10, None, None, 0, None) == L.LGS_ERR_INVALID_ARG
+    assert lb.lgs_tile_order_workspace_size(0) == 0
+    assert lb.lgs_tile_order_workspace_size(1000) % 256 == 0
+
+
+def header_arity():
+    """Number of parameters of every function the header declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(lgs_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_signatures_match_header():
+    L = _lib()
+    ar = header_arity()
+    assert set(ar) == set(declared())
+    for name, n in ar.items():
+        assert name in L._SIG, name
+        assert len(L._SIG[name][1]) == n, (name, len(L._SIG[name][1]), n)
