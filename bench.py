@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--extra", action="store_true", help="also time every render variant")
     ap.add_argument("--no-fwdbwd", action="store_true", help="skip the forward+backward workload")
     ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view batch workload")
+    ap.add_argument("--only", choices=["forward", "fwdbwd", "multiview"], default=None,
+                    help="run one workload alone (profiling); prints its JSON section")
     ap.add_argument("--no-tune", action="store_true", help="default render settings instead of the autotuner")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default ~/.cache/localgs)")
     ap.add_argument("--retune", action="store_true", help="ignore cached autotuner results")
@@ -196,6 +198,15 @@ def main():
 
     from paper_2606_16566_amd import autotune, scenes
     from paper_2606_16566_amd.batch import ViewBatch
+
+    if args.only == "fwdbwd":
+        print(json.dumps({"fwd_bwd": fwdbwd_single(args, torch, np)}), flush=True)
+        return
+    if args.only == "multiview":
+        print(json.dumps({"multiview": multiview(args, torch, np)}), flush=True)
+        return
+    if args.only == "forward":
+        args.no_fwdbwd = args.no_multiview = args.no_cpu = True
 
     sc = scenes.make_config(args.config)
     cam = sc.cameras[0]

@@ -36,7 +36,7 @@ class ViewBatch:
     capacity       initial pair capacity; `fit()` grows it from a measured count
     """
 
-    def __init__(self, cams, n: int, sh_degree: int, variant="local", persistent: bool = True,
+    def __init__(self, cams, n: int, sh_degree: int, variant="local_q8", persistent: bool = False,
                  blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda"):
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_VIEWS:

@@ -13,9 +13,12 @@
 //
 // The LOCAL variant reuses the forward's hoisting and wavefront culling: each
 // wavefront visits, in reverse, only the entries whose strip bit is set.  The
-// nine per-Gaussian partial gradients are summed across the wavefront, then
-// across the four wavefronts in LDS, and flushed with one atomic per
-// (tile, Gaussian, component).
+// nine per-Gaussian partial gradients are summed over each 16-lane row with
+// DPP (no LDS traffic), the four row sums of all nine components are added to
+// the workgroup's LDS accumulators with one 36-lane LDS atomic, and the
+// accumulators are flushed with one global atomic per (tile, Gaussian,
+// component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
+// (hardware estimate refined by two Newton steps in double).
 #include "common.hpp"
 
 #include "render_common.hpp"
@@ -34,11 +37,32 @@ struct BwdArgs {
     float *g_means2d, *g_conic, *g_opacity, *g_rgb;
 };
 
-__device__ __forceinline__ float wave_sum(float v)
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// sum over the 16 lanes of each row, left in every lane of the row (all 64
+// lanes must be active): quad butterflies, then half-row and row mirrors
+__device__ __forceinline__ float row_sum16(float v)
+{
+    v += dpp_read<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_read<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_read<0x141>(v);   // row_half_mirror
+    v += dpp_read<0x140>(v);   // row_mirror
     return v;
+}
+
+// 1 / x for normal positive x (here 1 - alpha in [0.01, 1] and the opacity
+// in [1/255, 1]): hardware estimate and two Newton steps
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
 template <bool LOCAL>
@@ -145,12 +169,12 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 if (act) {
                     const bool clamped = !(raw < kAlphaMax);
                     const double al = clamped ? (double)kAlphaMax : (double)raw;
-                    const double om = 1.0 - al;
-                    T = T / om;                                  // T before this Gaussian
+                    const double inv = recip(1.0 - al);
+                    T = T * inv;                                 // T before this Gaussian
                     const double w = al * T;
                     const float4 f = s_c[k];
-                    double dLda = (double)gc0 * ((double)f.x * T - R0 / om) + (double)gc1 * ((double)f.y * T - R1 / om)
-                                  + (double)gc2 * ((double)f.z * T - R2 / om) - gt * Tf / om;
+                    double dLda = (double)gc0 * ((double)f.x * T - R0 * inv) + (double)gc1 * ((double)f.y * T - R1 * inv)
+                                  + (double)gc2 * ((double)f.z * T - R2 * inv) - gt * Tf * inv;
                     R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
                     g[6] = (float)(gc0 * w); g[7] = (float)(gc1 * w); g[8] = (float)(gc2 * w);
                     if (!clamped) {
@@ -161,15 +185,20 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                         g[2] = (float)(dLdq * dx * dx);
                         g[3] = (float)(dLdq * 2.0 * dx * dy);
                         g[4] = (float)(dLdq * dy * dy);
-                        g[5] = (float)(dLda * al / (double)co.w);
+                        g[5] = (float)(dLda * al * recip((double)co.w));
                     }
                 }
                 if (__ballot(act) != 0ull) {
+                    // row sums of the nine components; lane f of each row
+                    // (f < 9) adds component f
+                    const int lf = lane & 15;
+                    float mine = 0.f;
 #pragma unroll
                     for (int f = 0; f < kNG; ++f) {
-                        const float sum = wave_sum(g[f]);
-                        if (lane == 0 && sum != 0.f) atomicAdd(&s_g[f][k], sum);
+                        const float r = row_sum16(g[f]);
+                        mine = lf == f ? r : mine;
                     }
+                    if (lf < kNG && mine != 0.f) atomicAdd(&s_g[lf][k], mine);
                 }
             }
         }
