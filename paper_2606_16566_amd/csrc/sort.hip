@@ -18,8 +18,18 @@ namespace {
 
 constexpr int kScanItems = 8;                          // per thread
 constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
-constexpr int kRadixItems = 8;                         // per thread
+// Radix blocks hold 256 * ITEMS elements: 2048 (ITEMS = 8) for short inputs,
+// so that enough blocks exist to fill the chip, 4096 (ITEMS = 16) for long
+// ones, which halves the per-block histogram traffic and lengthens the digit
+// runs that the scatter writes contiguously (8192 per block measured slower:
+// its 70 KB of LDS leaves two workgroups per CU).
+constexpr int kRadixItems = 8;                         // small blocks
+#ifndef LGS_RADIX_ITEMS_LARGE
+#define LGS_RADIX_ITEMS_LARGE 16
+#endif
+constexpr int kRadixItemsLarge = LGS_RADIX_ITEMS_LARGE;  // large blocks (build-time tuning)
 constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
+constexpr int64_t kLargeRadixFrom = 1 << 22;           // elements
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kWaves = kBlock / 64;
@@ -284,11 +294,10 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__res
 // ---------------------------------------------------------------------------
 
 // lanes of this round of 64 whose digit equals this lane's (eight ballots)
-__device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d)
+__device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbits)
 {
     uint64_t match = __ballot(active);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < nbits; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t bb = __ballot(bit);
         match &= bit ? bb : ~bb;
@@ -298,23 +307,25 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d)
 
 // Per-block digit histogram (per-wavefront sub-histograms in LDS, so the
 // atomics of one wavefront never contend with another's).
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
                                                             const uint32_t *n_dev, int shift, uint32_t mask,
                                                             uint32_t *__restrict__ hist, int64_t nblocks)
 {
+    constexpr int kTileN = kBlock * ITEMS;
     __shared__ uint32_t s_h[kWaves][kRadixBins];
     const int wid = threadIdx.x >> 6, lane = __lane_id();
 #pragma unroll
     for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
     __syncthreads();
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t start = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t start = (int64_t)blockIdx.x * kTileN;
     if (start < n) {
-        const int cnt = (int)min((int64_t)kRadixTile, n - start);
+        const int cnt = (int)min((int64_t)kTileN, n - start);
         const uint32_t *k4 = keys + start;
-        if (cnt == kRadixTile && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
+        if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
 #pragma unroll
-            for (int r = 0; r < kRadixItems / 4; ++r) {
+            for (int r = 0; r < ITEMS / 4; ++r) {
                 const uint4 v = reinterpret_cast<const uint4 *>(k4)[r * kBlock + threadIdx.x];
                 atomicAdd(&s_h[wid][(v.x >> shift) & mask], 1u);
                 atomicAdd(&s_h[wid][(v.y >> shift) & mask], 1u);
@@ -336,14 +347,14 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__re
 // blocks that hold elements: chunks of 2048 (8 consecutive per lane), block
 // scan of the lane sums, running carry between chunks.
 __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t nblocks,
-                                                               int64_t n_max, const uint32_t *n_dev,
+                                                               int64_t n_max, const uint32_t *n_dev, int tile_n,
                                                                uint32_t *__restrict__ digit_total)
 {
     constexpr int kPer = 8;
     __shared__ uint32_t s_warp[kWaves];
     uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t live = (n + kRadixTile - 1) / kRadixTile;
+    const int64_t live = (n + tile_n - 1) / tile_n;
     uint32_t carry = 0;
     for (int64_t c = 0; c < live; c += kBlock * kPer) {
         const int64_t b0 = c + (int64_t)threadIdx.x * kPer;
@@ -372,26 +383,29 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
 // counting sort) and writes each digit run to its global offset with
 // consecutive lanes on consecutive addresses.  vals_in == nullptr means the
 // values are the element indices.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
                                                                const uint32_t *__restrict__ vals_in,
                                                                uint32_t *__restrict__ keys_out,
                                                                uint32_t *__restrict__ vals_out, int64_t n_max,
-                                                               const uint32_t *n_dev, int shift, uint32_t mask,
+                                                               const uint32_t *n_dev, int shift, int nbits,
                                                                const uint32_t *__restrict__ hist_scan,
                                                                const uint32_t *__restrict__ digit_total,
                                                                int64_t nblocks)
 {
-    constexpr int kPerWave = kRadixTile / kWaves;          // 512
+    constexpr int kTileN = kBlock * ITEMS;
+    constexpr int kPerWave = kTileN / kWaves;
+    const uint32_t mask = (1u << nbits) - 1u;
     __shared__ uint32_t s_wc[kWaves][kRadixBins];          // running, then exclusive-over-waves counts
     __shared__ uint32_t s_lbase[kRadixBins];               // block-local digit offsets
     __shared__ uint32_t s_gbase[kRadixBins];               // global digit offsets of this block
-    __shared__ uint32_t s_key[kRadixTile];
-    __shared__ uint32_t s_val[kRadixTile];
+    __shared__ uint32_t s_key[kTileN];
+    __shared__ uint32_t s_val[kTileN];
     __shared__ uint32_t s_tot[kWaves];
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t start = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t start = (int64_t)blockIdx.x * kTileN;
     if (start >= n) return;                                  // uniform across the block
-    const int count = (int)min((int64_t)kRadixTile, n - start);
+    const int count = (int)min((int64_t)kTileN, n - start);
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const uint64_t lt = lanemask_lt();
 #pragma unroll
@@ -404,15 +418,15 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *_
         s_gbase[threadIdx.x] = before + hist_scan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
     }
 
-    uint32_t key[kRadixItems], val[kRadixItems], rank[kRadixItems];
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
         const bool active = local < count;
         key[r] = active ? keys_in[start + local] : 0u;
         val[r] = active ? (vals_in ? vals_in[start + local] : (uint32_t)(start + local)) : 0u;
         const uint32_t d = (key[r] >> shift) & mask;
-        const uint64_t match = digit_match(active, d);
+        const uint64_t match = digit_match(active, d, nbits);
         const uint32_t before = active ? s_wc[wid][d] : 0u;
         const uint32_t within = (uint32_t)__popcll(match & lt);
         rank[r] = before + within;
@@ -435,7 +449,202 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *_
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
+        const int local = wid * kPerWave + r * 64 + lane;
+        if (local < count) {
+            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t lp = s_lbase[d] + s_wc[wid][d] + rank[r];
+            s_key[lp] = key[r];
+            s_val[lp] = val[r];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += kBlock) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
+        keys_out[pos] = k;
+        vals_out[pos] = s_val[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Single-sweep passes.  One up-front kernel counts the digits of every pass
+// at once (per-block counts, then a reduction to per-pass digit totals);
+// each pass is then one kernel: a block takes the next partition of the
+// input by ticket, ranks its elements as the scatter above does, publishes
+// its digit counts, and learns the counts of all earlier partitions by a
+// look-back over their published words (aggregate or inclusive prefix),
+// then writes its elements to their final places.
+// A block only ever waits for partitions with smaller tickets, which were
+// taken by blocks already running, so every wait ends; each wait is also
+// bounded, and a block that gives up flags the sort as failed (reported
+// through the overflow word) instead of spinning.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kFlagAgg = 1ull << 62;              // count of this partition only
+constexpr uint64_t kFlagInc = 2ull << 62;              // inclusive prefix through this partition
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint64_t kValueMask = ~kFlagMask;
+constexpr uint32_t kSpinLimit = 1u << 20;
+constexpr int kMaxPasses = 4;
+
+struct PassSet {
+    int passes;
+    int shift[kMaxPasses];
+    int bits[kMaxPasses];
+};
+
+// per-block digit counts of every pass, block-major: bh[(p * nb + b) * 256 + d]
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void multi_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
+                                                            const uint32_t *n_dev, PassSet ps,
+                                                            uint32_t *__restrict__ bh, int64_t nb)
+{
+    constexpr int kTileN = kBlock * ITEMS;
+    __shared__ uint32_t s_h[kMaxPasses][kWaves][kRadixBins];
+    const int wid = threadIdx.x >> 6, lane = __lane_id();
+    for (int p = 0; p < ps.passes; ++p)
+#pragma unroll
+        for (int k = 0; k < kRadixBins / 64; ++k) s_h[p][wid][lane + 64 * k] = 0u;
+    __syncthreads();
+    const int64_t n = live_count(n_max, n_dev);
+    const int64_t start = (int64_t)blockIdx.x * kTileN;
+    if (start < n) {
+        const int cnt = (int)min((int64_t)kTileN, n - start);
+        for (int e = threadIdx.x; e < cnt; e += kBlock) {
+            const uint32_t k = keys[start + e];
+            for (int p = 0; p < ps.passes; ++p)
+                atomicAdd(&s_h[p][wid][(k >> ps.shift[p]) & ((1u << ps.bits[p]) - 1u)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < ps.passes; ++p) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) c += s_h[p][w][threadIdx.x];
+        bh[((int64_t)p * nb + blockIdx.x) * kRadixBins + threadIdx.x] = c;
+    }
+}
+
+// digit totals of pass blockIdx.y: each block sums a stripe of the block
+// counts and adds it to the totals (zeroed beforehand)
+__global__ __launch_bounds__(kBlock) void hist_reduce_kernel(const uint32_t *__restrict__ bh, int64_t nb,
+                                                             uint32_t *__restrict__ totals)
+{
+    const int p = blockIdx.y;
+    const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(nb, b0 + per);
+    uint32_t c = 0;
+    for (int64_t b = b0; b < b1; ++b) c += bh[((int64_t)p * nb + b) * kRadixBins + threadIdx.x];
+    if (c) atomicAdd(&totals[p * kRadixBins + threadIdx.x], c);
+}
+
+__device__ __forceinline__ uint64_t load_status(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_status(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void onesweep_kernel(const uint32_t *__restrict__ keys_in,
+                                                          const uint32_t *__restrict__ vals_in,
+                                                          uint32_t *__restrict__ keys_out,
+                                                          uint32_t *__restrict__ vals_out, int64_t n_max,
+                                                          const uint32_t *n_dev, int shift, int nbits,
+                                                          const uint32_t *__restrict__ totals,
+                                                          uint64_t *__restrict__ status, uint32_t *ticket,
+                                                          uint32_t *err)
+{
+    constexpr int kTileN = kBlock * ITEMS;
+    constexpr int kPerWave = kTileN / kWaves;
+    const uint32_t mask = (1u << nbits) - 1u;
+    __shared__ uint32_t s_wc[kWaves][kRadixBins];
+    __shared__ uint32_t s_lbase[kRadixBins];
+    __shared__ uint32_t s_gbase[kRadixBins];
+    __shared__ uint32_t s_key[kTileN];
+    __shared__ uint32_t s_val[kTileN];
+    __shared__ uint32_t s_tot[kWaves];
+    __shared__ uint32_t s_ticket;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t part = s_ticket;
+    const int64_t n = live_count(n_max, n_dev);
+    const int64_t start = part * kTileN;
+    // partitions past the live count hold nothing and nobody waits for them
+    if (start >= n) return;
+    const int count = (int)min((int64_t)kTileN, n - start);
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
+    __syncthreads();
+
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int local = wid * kPerWave + r * 64 + lane;
+        const bool active = local < count;
+        key[r] = active ? keys_in[start + local] : 0u;
+        val[r] = active ? (vals_in ? vals_in[start + local] : (uint32_t)(start + local)) : 0u;
+        const uint32_t d = (key[r] >> shift) & mask;
+        const uint64_t match = digit_match(active, d, nbits);
+        const uint32_t before = active ? s_wc[wid][d] : 0u;
+        const uint32_t within = (uint32_t)__popcll(match & lt);
+        rank[r] = before + within;
+        if (active && within == 0) s_wc[wid][d] = before + (uint32_t)__popcll(match);
+        wave_sync_lds();
+    }
+    __syncthreads();
+    {
+        const int t = threadIdx.x;             // digit
+        uint32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_wc[w][t];
+            s_wc[w][t] = run;
+            run += c;
+        }
+        uint32_t tot;
+        s_lbase[t] = block_exclusive_scan<uint32_t, kWaves>(run, tot, s_tot);
+        // publish this partition's count of digit t, then look back
+        uint64_t *mine = status + part * kRadixBins + t;
+        uint64_t excl = 0;
+        if (part == 0) {
+            store_status(mine, kFlagInc | run);
+        } else {
+            store_status(mine, kFlagAgg | run);
+            int64_t j = part - 1;
+            uint32_t spins = 0;
+            while (j >= 0) {
+                const uint64_t w = load_status(status + j * kRadixBins + t);
+                const uint64_t f = w & kFlagMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & kValueMask;
+                if (f == kFlagInc) break;
+                --j;
+            }
+            store_status(mine, kFlagInc | (excl + run));
+        }
+        // global base of digit t: smaller digits overall + earlier partitions
+        const uint32_t dt = totals[t];
+        uint32_t all;
+        const uint32_t smaller = block_exclusive_scan<uint32_t, kWaves>(dt, all, s_tot);
+        s_gbase[t] = smaller + (uint32_t)excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
         if (local < count) {
             const uint32_t d = (key[r] >> shift) & mask;
@@ -519,6 +728,14 @@ struct SortWorkspace {
     uint64_t *partials;           // scan partials
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
+#ifdef LGS_SORT_ONESWEEP
+    uint64_t *status;             // [256 * nblocks_max] look-back words
+    uint32_t *bh;                 // [kMaxPasses * 256 * nblocks_max] per-block digit counts
+    uint32_t *totals;             // [kMaxPasses * 256]
+    uint32_t *tickets;            // [kMaxPasses]
+    uint32_t *err;
+    int64_t nbmax;
+#endif
     size_t bytes;
 };
 
@@ -547,25 +764,88 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.partials = (uint64_t *)take(sizeof(uint64_t) * ((nm + kScanTile - 1) / kScanTile + 1));
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
+#ifdef LGS_SORT_ONESWEEP
+    w.nbmax = nbmax;
+    w.status = (uint64_t *)take(sizeof(uint64_t) * kRadixBins * nbmax);
+    w.bh = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses * kRadixBins * nbmax);
+    w.totals = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses * kRadixBins);
+    w.tickets = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses);
+    w.err = (uint32_t *)take(sizeof(uint32_t));
+#endif
     w.bytes = off;
     return w;
 }
 
 // one stable radix pass over [0, min(n_max, *n_dev)) on key bits
 // [shift, shift + bits)
+template <int ITEMS>
+void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+                  const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s)
+{
+    constexpr int kTileN = kBlock * ITEMS;
+    const int64_t nb = (n_max + kTileN - 1) / kTileN;
+    if (nb == 0) return;
+    const uint32_t mask = (1u << bits) - 1u;
+    hipLaunchKernelGGL(radix_hist_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
+                       mask, w.hist, nb);
+    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, nb, n_max, n_dev, kTileN,
+                       w.digit_total);
+    hipLaunchKernelGGL(radix_scatter_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout,
+                       n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, nb);
+}
+
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s)
 {
-    const int64_t nb = radix_blocks(n_max);
-    if (nb == 0) return;
-    const uint32_t mask = (1u << bits) - 1u;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
-                       w.hist, nb);
-    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, nb, n_max, n_dev,
-                       w.digit_total);
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout, n_max,
-                       n_dev, shift, mask, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, nb);
+    if (n_max >= kLargeRadixFrom)
+        radix_pass_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s);
+    else
+        radix_pass_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s);
 }
+
+#ifdef LGS_SORT_ONESWEEP
+// all passes of ps over [0, live): pass p reads the input (p = 0) or the
+// output of pass p - 1 and writes buffer pair (p & 1)
+template <int ITEMS>
+void sweep_passes_t(const uint32_t *kin, const uint32_t *vin, uint32_t *const kout[2], uint32_t *const vout[2],
+                    int64_t n_max, const uint32_t *n_dev, const PassSet &ps, const SortWorkspace &w,
+                    hipStream_t s)
+{
+    constexpr int kTileN = kBlock * ITEMS;
+    const int64_t nb = (n_max + kTileN - 1) / kTileN;
+    if (nb == 0) return;
+    fill_async<uint32_t>(w.totals, 0u, (int64_t)kMaxPasses * kRadixBins, s);
+    fill_async<uint32_t>(w.tickets, 0u, kMaxPasses, s);
+    hipLaunchKernelGGL(multi_hist_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, ps,
+                       w.bh, nb);
+    const unsigned rb = (unsigned)(nb < 128 ? nb : 128);
+    hipLaunchKernelGGL(hist_reduce_kernel, dim3(rb, ps.passes), dim3(kBlock), 0, s, (const uint32_t *)w.bh, nb,
+                       w.totals);
+    for (int p = 0; p < ps.passes; ++p) {
+        const uint32_t *ki = p == 0 ? kin : kout[(p - 1) & 1];
+        const uint32_t *vi = p == 0 ? vin : vout[(p - 1) & 1];
+        fill_async<uint64_t>(w.status, 0ull, nb * kRadixBins, s);
+        hipLaunchKernelGGL(onesweep_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, kout[p & 1],
+                           vout[p & 1], n_max, n_dev, ps.shift[p], ps.bits[p],
+                           (const uint32_t *)(w.totals + p * kRadixBins), w.status, w.tickets + p, w.err);
+    }
+}
+
+void sweep_passes(const uint32_t *kin, const uint32_t *vin, uint32_t *const kout[2], uint32_t *const vout[2],
+                  int64_t n_max, const uint32_t *n_dev, const PassSet &ps, const SortWorkspace &w, hipStream_t s)
+{
+    if (n_max >= kLargeRadixFrom)
+        sweep_passes_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, ps, w, s);
+    else
+        sweep_passes_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, ps, w, s);
+}
+
+// flags a failed look-back in the overflow word (the pair lists are then invalid)
+__global__ void sweep_error_kernel(const uint32_t *err, int32_t *overflow)
+{
+    if (*err) *overflow |= 2;
+}
+#endif
 
 }  // namespace
 }  // namespace lgs
@@ -619,11 +899,21 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     //    like their bit patterns; culled ones hold +inf and end up last):
     //    four 8-bit passes, the first reading the depths and implicit ids
     const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
+#ifdef LGS_SORT_ONESWEEP
+    fill_async<uint32_t>(w.err, 0u, 1, s);
+    {
+        PassSet ps{4, {0, 8, 16, 24}, {8, 8, 8, 8}};
+        uint32_t *const ko[2] = {w.dk[0], w.dk[1]};
+        uint32_t *const vo[2] = {w.dv[0], w.dv[1]};
+        sweep_passes(dbits, nullptr, ko, vo, n, nullptr, ps, w, s);
+    }
+#else
     radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s);
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
         radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s);
     }
+#endif
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     // 2. pair counts in depth order, their exclusive scan (total P) and the
     //    overflow check.  The number of tile-sort passes decides which buffer
@@ -650,12 +940,29 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
                            tg, n, k0, v0);
     // 4. stable sort of the pairs by tile id, the key bits split evenly over
     //    the passes (longer digit runs per block than 8 + remainder)
+#ifdef LGS_SORT_ONESWEEP
+    {
+        PassSet ps{};
+        ps.passes = passes;
+        for (int pass = 0, shift = 0; pass < passes; ++pass) {
+            const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
+            ps.shift[pass] = shift;
+            ps.bits[pass] = b;
+            shift += b;
+        }
+        uint32_t *const ko[2] = {k1, k0};
+        uint32_t *const vo[2] = {v1, v0};
+        if (capacity_pairs > 0) sweep_passes(k0, v0, ko, vo, capacity_pairs, w.n_eff, ps, w, s);
+        hipLaunchKernelGGL(sweep_error_kernel, dim3(1), dim3(1), 0, s, (const uint32_t *)w.err, overflow);
+    }
+#else
     for (int pass = 0, shift = 0; pass < passes; ++pass) {
         const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
         if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, shift, b, w, s);
         else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, shift, b, w, s);
         shift += b;
     }
+#endif
     LGS_LAUNCHED("lgs_sort");
     return LGS_OK;
 }

@@ -77,7 +77,9 @@ def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True):
 
 
 @pytest.mark.parametrize("seed,n,tx,ty,ties", [(0, 5000, 13, 9, True), (1, 40000, 120, 68, False),
-                                              (2, 3, 1, 1, True), (3, 70000, 300, 260, True)])
+                                              (2, 3, 1, 1, True), (3, 70000, 300, 260, True),
+                                              # above 2^22 pairs: the large radix blocks
+                                              (4, 1000000, 120, 68, False), (5, 800000, 300, 260, True)])
 def test_sort_and_ranges_parity(seed, n, tx, ty, ties):
     vis, depth, rect = _synthetic_bins(seed, n, tx, ty, ties)
     print(f"sort seed={seed} n={n} tiles={tx}x{ty}", flush=True)
