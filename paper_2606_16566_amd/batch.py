@@ -239,8 +239,8 @@ class StepGraph:
 
     `fn` must only enqueue library work on the current stream (no host reads,
     no tensor allocation); it runs `warmup` times eagerly, then once under
-    capture on a private stream.  `replay()` orders the graph after the
-    caller's current stream and the caller's stream after the graph.
+    capture on a private stream.  `replay()` launches the whole sequence on
+    the caller's current stream.
     """
 
     def __init__(self, fn, warmup: int = 1):
@@ -264,12 +264,11 @@ class StepGraph:
         self.handle = h
 
     def replay(self):
+        """Launch the graph on the caller's current stream (ordered with the
+        caller's other work on that stream like any kernel launch)."""
         if self.handle is None:
             raise RuntimeError("graph destroyed")
-        cur = torch.cuda.current_stream()
-        self.stream.wait_stream(cur)
-        L.check(L.lib().lgs_graph_launch(self.handle, C.c_void_p(self.stream.cuda_stream)), "lgs_graph_launch")
-        cur.wait_stream(self.stream)
+        L.check(L.lib().lgs_graph_launch(self.handle, _stream()), "lgs_graph_launch")
 
     def close(self):
         if self.handle is not None:

@@ -142,12 +142,11 @@ __global__ __launch_bounds__(kBlock) void scan_final_kernel(L ld, S st, int64_t 
 // tiles touched by the r-th Gaussian in depth order; the reduce pass gathers
 // the rectangle and leaves the count in `cnt` for the final pass
 struct PairCountGather {
-    const uint32_t *order;
-    const int4 *rect;
+    const int4 *rect;           // rectangles in depth order
     uint32_t *cnt;
     __device__ uint64_t operator()(int64_t r) const
     {
-        const int4 q = rect[order[r]];
+        const int4 q = rect[r];
         const uint32_t c = (q.z > q.x && q.w > q.y) ? (uint32_t)((q.z - q.x) * (q.w - q.y)) : 0u;
         cnt[r] = c;
         return c;
@@ -230,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__res
         const uint32_t g = order[first + threadIdx.x];
         const int v = tg.V > 1 ? (int)(g / tg.per_view) : 0;
         s_id[threadIdx.x] = g;
-        s_rect[threadIdx.x] = rect[g];
+        s_rect[threadIdx.x] = rect[first + threadIdx.x];
         s_grid[threadIdx.x] = make_int2(tg.tile_off[v], tg.tiles_x[v]);
         s_off[threadIdx.x] = off[first + threadIdx.x];
     }
@@ -305,54 +304,68 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbi
     return match;
 }
 
-// Per-block digit histogram (per-wavefront sub-histograms in LDS, so the
-// atomics of one wavefront never contend with another's).
+// Per-block digit histograms (per-wavefront sub-histograms in LDS, so the
+// atomics of one wavefront never contend with another's).  One workgroup
+// counts kHistGroup consecutive blocks and writes their counts of each digit
+// as one 16-byte row segment: hist[digit * stride + block], stride a
+// multiple of kHistGroup (single 4-byte writes at a stride of a whole row
+// would each cost a partial cache-line write).
+constexpr int kHistGroup = 4;
+
+inline int64_t hist_stride(int64_t nblocks) { return (nblocks + kHistGroup - 1) / kHistGroup * kHistGroup; }
+
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
                                                             const uint32_t *n_dev, int shift, uint32_t mask,
-                                                            uint32_t *__restrict__ hist, int64_t nblocks)
+                                                            uint32_t *__restrict__ hist, int64_t stride)
 {
     constexpr int kTileN = kBlock * ITEMS;
     __shared__ uint32_t s_h[kWaves][kRadixBins];
     const int wid = threadIdx.x >> 6, lane = __lane_id();
-#pragma unroll
-    for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
-    __syncthreads();
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t start = (int64_t)blockIdx.x * kTileN;
-    if (start < n) {
-        const int cnt = (int)min((int64_t)kTileN, n - start);
-        const uint32_t *k4 = keys + start;
-        if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
+    uint32_t c[kHistGroup];
 #pragma unroll
-            for (int r = 0; r < ITEMS / 4; ++r) {
-                const uint4 v = reinterpret_cast<const uint4 *>(k4)[r * kBlock + threadIdx.x];
-                atomicAdd(&s_h[wid][(v.x >> shift) & mask], 1u);
-                atomicAdd(&s_h[wid][(v.y >> shift) & mask], 1u);
-                atomicAdd(&s_h[wid][(v.z >> shift) & mask], 1u);
-                atomicAdd(&s_h[wid][(v.w >> shift) & mask], 1u);
+    for (int j = 0; j < kHistGroup; ++j) {
+#pragma unroll
+        for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
+        __syncthreads();
+        const int64_t start = ((int64_t)blockIdx.x * kHistGroup + j) * kTileN;
+        if (start < n) {
+            const int cnt = (int)min((int64_t)kTileN, n - start);
+            const uint32_t *k4 = keys + start;
+            if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
+#pragma unroll
+                for (int r = 0; r < ITEMS / 4; ++r) {
+                    const uint4 v = reinterpret_cast<const uint4 *>(k4)[r * kBlock + threadIdx.x];
+                    atomicAdd(&s_h[wid][(v.x >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(v.y >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(v.z >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(v.w >> shift) & mask], 1u);
+                }
+            } else {
+                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(k4[e] >> shift) & mask], 1u);
             }
-        } else {
-            for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(k4[e] >> shift) & mask], 1u);
         }
-    }
-    __syncthreads();
-    uint32_t c = 0;
+        __syncthreads();
+        c[j] = 0u;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) c += s_h[w][threadIdx.x];
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = c;
+        for (int w = 0; w < kWaves; ++w) c[j] += s_h[w][threadIdx.x];
+        __syncthreads();                                       // before the next block re-zeroes
+    }
+    *reinterpret_cast<uint4 *>(hist + (int64_t)threadIdx.x * stride + (int64_t)blockIdx.x * kHistGroup) =
+        make_uint4(c[0], c[1], c[2], c[3]);
 }
 
 // Exclusive scan, in place, of one digit's row of per-block counts over the
 // blocks that hold elements: chunks of 2048 (8 consecutive per lane), block
 // scan of the lane sums, running carry between chunks.
-__global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t nblocks,
+__global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t stride,
                                                                int64_t n_max, const uint32_t *n_dev, int tile_n,
                                                                uint32_t *__restrict__ digit_total)
 {
     constexpr int kPer = 8;
     __shared__ uint32_t s_warp[kWaves];
-    uint32_t *row = hist + (int64_t)blockIdx.x * nblocks;
+    uint32_t *row = hist + (int64_t)blockIdx.x * stride;
     const int64_t n = live_count(n_max, n_dev);
     const int64_t live = (n + tile_n - 1) / tile_n;
     uint32_t carry = 0;
@@ -376,22 +389,30 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one 2048-element block.  Wavefront w owns the contiguous
-// elements [512 w, 512 (w+1)) of the block and ranks them in 8 rounds of 64
-// against its own running digit counts, so no workgroup barrier is needed
-// while ranking.  The block then orders its elements by digit in LDS (a local
+// Stable scatter of one block of 256 * ITEMS elements.  Wavefront w owns a
+// contiguous quarter of the block and ranks its keys in rounds of 64 against
+// its own running digit counts, so no workgroup barrier is needed while
+// ranking.  The block then orders its elements by digit in LDS (a local
 // counting sort) and writes each digit run to its global offset with
-// consecutive lanes on consecutive addresses.  vals_in == nullptr means the
-// values are the element indices.
+// consecutive lanes on consecutive addresses: first the keys, then the
+// values through the same LDS buffer, which halves the LDS footprint and
+// leaves room for more resident workgroups.  vals_in == nullptr means the
+// values are the element indices.  With gather_dst set, the 16-byte record
+// gather_src[value] of every element is also written to its sorted place.
+#ifndef LGS_SCATTER_MIN_WAVES
+#define LGS_SCATTER_MIN_WAVES 1
+#endif
 template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LGS_SCATTER_MIN_WAVES))) void
+radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
                                                                const uint32_t *__restrict__ vals_in,
                                                                uint32_t *__restrict__ keys_out,
                                                                uint32_t *__restrict__ vals_out, int64_t n_max,
                                                                const uint32_t *n_dev, int shift, int nbits,
                                                                const uint32_t *__restrict__ hist_scan,
                                                                const uint32_t *__restrict__ digit_total,
-                                                               int64_t nblocks)
+                                                               int64_t stride, const int4 *__restrict__ gather_src,
+                                                               int4 *__restrict__ gather_dst)
 {
     constexpr int kTileN = kBlock * ITEMS;
     constexpr int kPerWave = kTileN / kWaves;
@@ -399,8 +420,8 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *_
     __shared__ uint32_t s_wc[kWaves][kRadixBins];          // running, then exclusive-over-waves counts
     __shared__ uint32_t s_lbase[kRadixBins];               // block-local digit offsets
     __shared__ uint32_t s_gbase[kRadixBins];               // global digit offsets of this block
-    __shared__ uint32_t s_key[kTileN];
-    __shared__ uint32_t s_val[kTileN];
+    __shared__ uint32_t s_buf[kTileN];                     // keys, then values, in digit order
+    __shared__ uint8_t s_dig[kTileN];                      // digit of each slot of s_buf
     __shared__ uint32_t s_tot[kWaves];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t start = (int64_t)blockIdx.x * kTileN;
@@ -415,21 +436,26 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *_
         const uint32_t tot = digit_total[threadIdx.x];
         uint32_t all;
         const uint32_t before = block_exclusive_scan<uint32_t, kWaves>(tot, all, s_tot);
-        s_gbase[threadIdx.x] = before + hist_scan[(int64_t)threadIdx.x * nblocks + blockIdx.x];
+        s_gbase[threadIdx.x] = before + hist_scan[(int64_t)threadIdx.x * stride + blockIdx.x];
     }
 
-    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+    const uint32_t *kin = keys_in + start;                  // uniform bases, 32-bit offsets
+    const uint32_t *vin = vals_in ? vals_in + start : nullptr;
+    uint32_t key[ITEMS], lp[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int local = wid * kPerWave + r * 64 + lane;
+        key[r] = local < count ? kin[local] : 0u;
+    }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
         const bool active = local < count;
-        key[r] = active ? keys_in[start + local] : 0u;
-        val[r] = active ? (vals_in ? vals_in[start + local] : (uint32_t)(start + local)) : 0u;
         const uint32_t d = (key[r] >> shift) & mask;
         const uint64_t match = digit_match(active, d, nbits);
         const uint32_t before = active ? s_wc[wid][d] : 0u;
         const uint32_t within = (uint32_t)__popcll(match & lt);
-        rank[r] = before + within;
+        lp[r] = before + within;                             // rank within the wavefront's digit run
         if (active && within == 0) s_wc[wid][d] = before + (uint32_t)__popcll(match);
         wave_sync_lds();
     }
@@ -453,213 +479,46 @@ __global__ __launch_bounds__(kBlock) void radix_scatter_kernel(const uint32_t *_
         const int local = wid * kPerWave + r * 64 + lane;
         if (local < count) {
             const uint32_t d = (key[r] >> shift) & mask;
-            const uint32_t lp = s_lbase[d] + s_wc[wid][d] + rank[r];
-            s_key[lp] = key[r];
-            s_val[lp] = val[r];
+            lp[r] += s_lbase[d] + s_wc[wid][d];
+            s_buf[lp[r]] = key[r];
+            s_dig[lp[r]] = (uint8_t)d;
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < count; i += kBlock) {
-        const uint32_t k = s_key[i];
-        const uint32_t d = (k >> shift) & mask;
-        const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
-        keys_out[pos] = k;
-        vals_out[pos] = s_val[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Single-sweep passes.  One up-front kernel counts the digits of every pass
-// at once (per-block counts, then a reduction to per-pass digit totals);
-// each pass is then one kernel: a block takes the next partition of the
-// input by ticket, ranks its elements as the scatter above does, publishes
-// its digit counts, and learns the counts of all earlier partitions by a
-// look-back over their published words (aggregate or inclusive prefix),
-// then writes its elements to their final places.
-// A block only ever waits for partitions with smaller tickets, which were
-// taken by blocks already running, so every wait ends; each wait is also
-// bounded, and a block that gives up flags the sort as failed (reported
-// through the overflow word) instead of spinning.
-// ---------------------------------------------------------------------------
-constexpr uint64_t kFlagAgg = 1ull << 62;              // count of this partition only
-constexpr uint64_t kFlagInc = 2ull << 62;              // inclusive prefix through this partition
-constexpr uint64_t kFlagMask = 3ull << 62;
-constexpr uint64_t kValueMask = ~kFlagMask;
-constexpr uint32_t kSpinLimit = 1u << 20;
-constexpr int kMaxPasses = 4;
-
-struct PassSet {
-    int passes;
-    int shift[kMaxPasses];
-    int bits[kMaxPasses];
-};
-
-// per-block digit counts of every pass, block-major: bh[(p * nb + b) * 256 + d]
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void multi_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
-                                                            const uint32_t *n_dev, PassSet ps,
-                                                            uint32_t *__restrict__ bh, int64_t nb)
-{
-    constexpr int kTileN = kBlock * ITEMS;
-    __shared__ uint32_t s_h[kMaxPasses][kWaves][kRadixBins];
-    const int wid = threadIdx.x >> 6, lane = __lane_id();
-    for (int p = 0; p < ps.passes; ++p)
-#pragma unroll
-        for (int k = 0; k < kRadixBins / 64; ++k) s_h[p][wid][lane + 64 * k] = 0u;
-    __syncthreads();
-    const int64_t n = live_count(n_max, n_dev);
-    const int64_t start = (int64_t)blockIdx.x * kTileN;
-    if (start < n) {
-        const int cnt = (int)min((int64_t)kTileN, n - start);
-        for (int e = threadIdx.x; e < cnt; e += kBlock) {
-            const uint32_t k = keys[start + e];
-            for (int p = 0; p < ps.passes; ++p)
-                atomicAdd(&s_h[p][wid][(k >> ps.shift[p]) & ((1u << ps.bits[p]) - 1u)], 1u);
-        }
-    }
-    __syncthreads();
-    for (int p = 0; p < ps.passes; ++p) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) c += s_h[p][w][threadIdx.x];
-        bh[((int64_t)p * nb + blockIdx.x) * kRadixBins + threadIdx.x] = c;
-    }
-}
-
-// digit totals of pass blockIdx.y: each block sums a stripe of the block
-// counts and adds it to the totals (zeroed beforehand)
-__global__ __launch_bounds__(kBlock) void hist_reduce_kernel(const uint32_t *__restrict__ bh, int64_t nb,
-                                                             uint32_t *__restrict__ totals)
-{
-    const int p = blockIdx.y;
-    const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
-    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(nb, b0 + per);
-    uint32_t c = 0;
-    for (int64_t b = b0; b < b1; ++b) c += bh[((int64_t)p * nb + b) * kRadixBins + threadIdx.x];
-    if (c) atomicAdd(&totals[p * kRadixBins + threadIdx.x], c);
-}
-
-__device__ __forceinline__ uint64_t load_status(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_status(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void onesweep_kernel(const uint32_t *__restrict__ keys_in,
-                                                          const uint32_t *__restrict__ vals_in,
-                                                          uint32_t *__restrict__ keys_out,
-                                                          uint32_t *__restrict__ vals_out, int64_t n_max,
-                                                          const uint32_t *n_dev, int shift, int nbits,
-                                                          const uint32_t *__restrict__ totals,
-                                                          uint64_t *__restrict__ status, uint32_t *ticket,
-                                                          uint32_t *err)
-{
-    constexpr int kTileN = kBlock * ITEMS;
-    constexpr int kPerWave = kTileN / kWaves;
-    const uint32_t mask = (1u << nbits) - 1u;
-    __shared__ uint32_t s_wc[kWaves][kRadixBins];
-    __shared__ uint32_t s_lbase[kRadixBins];
-    __shared__ uint32_t s_gbase[kRadixBins];
-    __shared__ uint32_t s_key[kTileN];
-    __shared__ uint32_t s_val[kTileN];
-    __shared__ uint32_t s_tot[kWaves];
-    __shared__ uint32_t s_ticket;
-    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const int64_t part = s_ticket;
-    const int64_t n = live_count(n_max, n_dev);
-    const int64_t start = part * kTileN;
-    // partitions past the live count hold nothing and nobody waits for them
-    if (start >= n) return;
-    const int count = (int)min((int64_t)kTileN, n - start);
-    const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
-    __syncthreads();
-
-    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+    // values travel in the second half: load them now, while the keys are
+    // written out
+    uint32_t val[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
-        const bool active = local < count;
-        key[r] = active ? keys_in[start + local] : 0u;
-        val[r] = active ? (vals_in ? vals_in[start + local] : (uint32_t)(start + local)) : 0u;
-        const uint32_t d = (key[r] >> shift) & mask;
-        const uint64_t match = digit_match(active, d, nbits);
-        const uint32_t before = active ? s_wc[wid][d] : 0u;
-        const uint32_t within = (uint32_t)__popcll(match & lt);
-        rank[r] = before + within;
-        if (active && within == 0) s_wc[wid][d] = before + (uint32_t)__popcll(match);
-        wave_sync_lds();
+        val[r] = local < count ? (vin ? vin[local] : (uint32_t)(start + local)) : 0u;
     }
     __syncthreads();
-    {
-        const int t = threadIdx.x;             // digit
-        uint32_t run = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = s_wc[w][t];
-            s_wc[w][t] = run;
-            run += c;
+    for (int r = 0; r < ITEMS; ++r) {
+        const int i = threadIdx.x + r * kBlock;
+        if (i < count) {
+            const uint32_t d = s_dig[i];
+            keys_out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = s_buf[i];
         }
-        uint32_t tot;
-        s_lbase[t] = block_exclusive_scan<uint32_t, kWaves>(run, tot, s_tot);
-        // publish this partition's count of digit t, then look back
-        uint64_t *mine = status + part * kRadixBins + t;
-        uint64_t excl = 0;
-        if (part == 0) {
-            store_status(mine, kFlagInc | run);
-        } else {
-            store_status(mine, kFlagAgg | run);
-            int64_t j = part - 1;
-            uint32_t spins = 0;
-            while (j >= 0) {
-                const uint64_t w = load_status(status + j * kRadixBins + t);
-                const uint64_t f = w & kFlagMask;
-                if (f == 0) {
-                    if (++spins > kSpinLimit) {
-                        atomicOr(err, 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += w & kValueMask;
-                if (f == kFlagInc) break;
-                --j;
-            }
-            store_status(mine, kFlagInc | (excl + run));
-        }
-        // global base of digit t: smaller digits overall + earlier partitions
-        const uint32_t dt = totals[t];
-        uint32_t all;
-        const uint32_t smaller = block_exclusive_scan<uint32_t, kWaves>(dt, all, s_tot);
-        s_gbase[t] = smaller + (uint32_t)excl;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
-        if (local < count) {
-            const uint32_t d = (key[r] >> shift) & mask;
-            const uint32_t lp = s_lbase[d] + s_wc[wid][d] + rank[r];
-            s_key[lp] = key[r];
-            s_val[lp] = val[r];
-        }
+        if (local < count) s_buf[lp[r]] = val[r];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < count; i += kBlock) {
-        const uint32_t k = s_key[i];
-        const uint32_t d = (k >> shift) & mask;
-        const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
-        keys_out[pos] = k;
-        vals_out[pos] = s_val[i];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const int i = threadIdx.x + r * kBlock;
+        if (i < count) {
+            const uint32_t d = s_dig[i];
+            const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
+            const uint32_t v = s_buf[i];
+            vals_out[pos] = v;
+            // optional: carry the 16-byte record of element v to its sorted place
+            if (gather_dst) gather_dst[pos] = gather_src[v];
+        }
     }
 }
 
@@ -725,17 +584,10 @@ struct SortWorkspace {
     uint32_t *hist;               // [256 * nblocks_max]
     uint32_t *digit_total;        // [256]
     uint32_t *pair_off;           // [n] pair counts, then exclusive offsets
+    int4 *rect_sorted;            // [n] tile rectangles in depth order
     uint64_t *partials;           // scan partials
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
-#ifdef LGS_SORT_ONESWEEP
-    uint64_t *status;             // [256 * nblocks_max] look-back words
-    uint32_t *bh;                 // [kMaxPasses * 256 * nblocks_max] per-block digit counts
-    uint32_t *totals;             // [kMaxPasses * 256]
-    uint32_t *tickets;            // [kMaxPasses]
-    uint32_t *err;
-    int64_t nbmax;
-#endif
     size_t bytes;
 };
 
@@ -757,21 +609,14 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     }
     w.pk = (uint32_t *)take(sizeof(uint32_t) * (cap > 0 ? cap : 1));
     w.pv = (uint32_t *)take(sizeof(uint32_t) * (cap > 0 ? cap : 1));
-    const int64_t nbmax = radix_blocks(n > cap ? n : cap) + 1;
+    const int64_t nbmax = hist_stride(radix_blocks(n > cap ? n : cap) + 1);
     w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * nbmax);
     w.digit_total = (uint32_t *)take(sizeof(uint32_t) * kRadixBins);
     w.pair_off = (uint32_t *)take(sizeof(uint32_t) * nm);
+    w.rect_sorted = (int4 *)take(sizeof(int4) * nm);
     w.partials = (uint64_t *)take(sizeof(uint64_t) * ((nm + kScanTile - 1) / kScanTile + 1));
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
-#ifdef LGS_SORT_ONESWEEP
-    w.nbmax = nbmax;
-    w.status = (uint64_t *)take(sizeof(uint64_t) * kRadixBins * nbmax);
-    w.bh = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses * kRadixBins * nbmax);
-    w.totals = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses * kRadixBins);
-    w.tickets = (uint32_t *)take(sizeof(uint32_t) * kMaxPasses);
-    w.err = (uint32_t *)take(sizeof(uint32_t));
-#endif
     w.bytes = off;
     return w;
 }
@@ -780,72 +625,34 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 // [shift, shift + bits)
 template <int ITEMS>
 void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                  const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s)
+                  const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
+                  const int4 *gather_src, int4 *gather_dst)
 {
     constexpr int kTileN = kBlock * ITEMS;
     const int64_t nb = (n_max + kTileN - 1) / kTileN;
     if (nb == 0) return;
     const uint32_t mask = (1u << bits) - 1u;
-    hipLaunchKernelGGL(radix_hist_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
-                       mask, w.hist, nb);
-    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, nb, n_max, n_dev, kTileN,
-                       w.digit_total);
+    const int64_t stride = hist_stride(nb);
+    hipLaunchKernelGGL(radix_hist_kernel<ITEMS>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s, kin,
+                       n_max, n_dev, shift, mask, w.hist, stride);
+    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
+                       kTileN, w.digit_total);
     hipLaunchKernelGGL(radix_scatter_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout,
-                       n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, nb);
+                       n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
+                       stride, gather_src, gather_dst);
 }
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
-                const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s)
+                const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
+                const int4 *gather_src = nullptr, int4 *gather_dst = nullptr)
 {
     if (n_max >= kLargeRadixFrom)
-        radix_pass_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s);
+        radix_pass_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
+                                       gather_dst);
     else
-        radix_pass_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s);
+        radix_pass_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
 }
 
-#ifdef LGS_SORT_ONESWEEP
-// all passes of ps over [0, live): pass p reads the input (p = 0) or the
-// output of pass p - 1 and writes buffer pair (p & 1)
-template <int ITEMS>
-void sweep_passes_t(const uint32_t *kin, const uint32_t *vin, uint32_t *const kout[2], uint32_t *const vout[2],
-                    int64_t n_max, const uint32_t *n_dev, const PassSet &ps, const SortWorkspace &w,
-                    hipStream_t s)
-{
-    constexpr int kTileN = kBlock * ITEMS;
-    const int64_t nb = (n_max + kTileN - 1) / kTileN;
-    if (nb == 0) return;
-    fill_async<uint32_t>(w.totals, 0u, (int64_t)kMaxPasses * kRadixBins, s);
-    fill_async<uint32_t>(w.tickets, 0u, kMaxPasses, s);
-    hipLaunchKernelGGL(multi_hist_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, n_max, n_dev, ps,
-                       w.bh, nb);
-    const unsigned rb = (unsigned)(nb < 128 ? nb : 128);
-    hipLaunchKernelGGL(hist_reduce_kernel, dim3(rb, ps.passes), dim3(kBlock), 0, s, (const uint32_t *)w.bh, nb,
-                       w.totals);
-    for (int p = 0; p < ps.passes; ++p) {
-        const uint32_t *ki = p == 0 ? kin : kout[(p - 1) & 1];
-        const uint32_t *vi = p == 0 ? vin : vout[(p - 1) & 1];
-        fill_async<uint64_t>(w.status, 0ull, nb * kRadixBins, s);
-        hipLaunchKernelGGL(onesweep_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, kout[p & 1],
-                           vout[p & 1], n_max, n_dev, ps.shift[p], ps.bits[p],
-                           (const uint32_t *)(w.totals + p * kRadixBins), w.status, w.tickets + p, w.err);
-    }
-}
-
-void sweep_passes(const uint32_t *kin, const uint32_t *vin, uint32_t *const kout[2], uint32_t *const vout[2],
-                  int64_t n_max, const uint32_t *n_dev, const PassSet &ps, const SortWorkspace &w, hipStream_t s)
-{
-    if (n_max >= kLargeRadixFrom)
-        sweep_passes_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, ps, w, s);
-    else
-        sweep_passes_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, ps, w, s);
-}
-
-// flags a failed look-back in the overflow word (the pair lists are then invalid)
-__global__ void sweep_error_kernel(const uint32_t *err, int32_t *overflow)
-{
-    if (*err) *overflow |= 2;
-}
-#endif
 
 }  // namespace
 }  // namespace lgs
@@ -899,21 +706,13 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     //    like their bit patterns; culled ones hold +inf and end up last):
     //    four 8-bit passes, the first reading the depths and implicit ids
     const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
-#ifdef LGS_SORT_ONESWEEP
-    fill_async<uint32_t>(w.err, 0u, 1, s);
-    {
-        PassSet ps{4, {0, 8, 16, 24}, {8, 8, 8, 8}};
-        uint32_t *const ko[2] = {w.dk[0], w.dk[1]};
-        uint32_t *const vo[2] = {w.dv[0], w.dv[1]};
-        sweep_passes(dbits, nullptr, ko, vo, n, nullptr, ps, w, s);
-    }
-#else
     radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s);
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
-        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s);
+        // the last pass also moves every rectangle into depth order
+        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
+                   pass == 3 ? rc : nullptr, pass == 3 ? w.rect_sorted : nullptr);
     }
-#endif
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     // 2. pair counts in depth order, their exclusive scan (total P) and the
     //    overflow check.  The number of tile-sort passes decides which buffer
@@ -926,7 +725,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     const int64_t nb = (n + kScanTile - 1) / kScanTile;
     if (nb > 0)
         hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, PairCountGather>), dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           PairCountGather{order, rc, w.pair_off}, n, (const uint32_t *)nullptr, w.partials);
+                           PairCountGather{w.rect_sorted, w.pair_off}, n, (const uint32_t *)nullptr, w.partials);
     hipLaunchKernelGGL(pair_partials_kernel, dim3(1), dim3(1024), 0, s, w.partials, nb, w.p_total,
                        (uint64_t)capacity_pairs, num_pairs, overflow, w.n_eff);
     if (nb > 0)
@@ -935,34 +734,18 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
                            (const uint32_t *)nullptr, (const uint64_t *)w.partials);
     // 3. duplication in depth order
     if (n > 0)
-        hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order, rc,
+        hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order,
+                           (const int4 *)w.rect_sorted,
                            (const uint32_t *)w.pair_off, (const uint64_t *)w.p_total, (uint64_t)capacity_pairs,
                            tg, n, k0, v0);
     // 4. stable sort of the pairs by tile id, the key bits split evenly over
     //    the passes (longer digit runs per block than 8 + remainder)
-#ifdef LGS_SORT_ONESWEEP
-    {
-        PassSet ps{};
-        ps.passes = passes;
-        for (int pass = 0, shift = 0; pass < passes; ++pass) {
-            const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
-            ps.shift[pass] = shift;
-            ps.bits[pass] = b;
-            shift += b;
-        }
-        uint32_t *const ko[2] = {k1, k0};
-        uint32_t *const vo[2] = {v1, v0};
-        if (capacity_pairs > 0) sweep_passes(k0, v0, ko, vo, capacity_pairs, w.n_eff, ps, w, s);
-        hipLaunchKernelGGL(sweep_error_kernel, dim3(1), dim3(1), 0, s, (const uint32_t *)w.err, overflow);
-    }
-#else
     for (int pass = 0, shift = 0; pass < passes; ++pass) {
         const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
         if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, shift, b, w, s);
         else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, shift, b, w, s);
         shift += b;
     }
-#endif
     LGS_LAUNCHED("lgs_sort");
     return LGS_OK;
 }
@@ -1010,7 +793,7 @@ OrderWorkspace plan_order(char *base, int64_t num_tiles)
     };
     w.keys = (uint32_t *)take(sizeof(uint32_t) * num_tiles);
     w.keys_out = (uint32_t *)take(sizeof(uint32_t) * num_tiles);
-    w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * (radix_blocks(num_tiles) + 1));
+    w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * hist_stride(radix_blocks(num_tiles) + 1));
     w.digit_total = (uint32_t *)take(sizeof(uint32_t) * kRadixBins);
     w.bytes = off;
     return w;
