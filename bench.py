@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-multiview", action="store_true", help="skip the 16-view batch workload")
     ap.add_argument("--only", choices=["forward", "fwdbwd", "multiview"], default=None,
                     help="run one workload alone (profiling); prints its JSON section")
+    ap.add_argument("--render", default=None,
+                    help="render variant for the Local pipeline instead of the autotuner's choice (e.g. local_q8_v4)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     ap.add_argument("--no-tune", action="store_true", help="default render settings instead of the autotuner")
@@ -223,9 +225,9 @@ def main():
     sc = scenes.make_config(args.config)
     cam = sc.cameras[0]
     params = tensors(sc, torch)
-    vb = ViewBatch([cam], sc.n, sc.sh_degree, variant="local", persistent=False)
+    vb = ViewBatch([cam], sc.n, sc.sh_degree, variant=args.render or "local", persistent=False)
     tuned = None
-    if not args.no_tune:
+    if not args.no_tune and not args.render:
         tuned = autotune.tune(vb, params, cache_path=args.tune_cache, use_cache=not args.retune)
     vb.fit(params)
     torch.cuda.synchronize()
@@ -264,7 +266,7 @@ def main():
     st = st.cpu().numpy()
     lane_evals = int(st[3])
     achieved = lane_evals * OPS_PER_PAIR / (res["render_ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "render_wave_kernel (tuned settings)", "achieved": achieved,
+    roofline = {"bound": "alu", "kernel": f"render_wave_kernel (variant code {vb.variant})", "achieved": achieved,
                 "peak": PEAK_VALU_TOPS, "unit": "Tops/s (full-rate VALU lane ops)",
                 "frac": achieved / PEAK_VALU_TOPS, "traffic": None, "ops_per_pair": OPS_PER_PAIR,
                 "lane_evaluations": lane_evals, "launch_ms": res["render_ms"],
@@ -300,7 +302,7 @@ def main():
         "dtype": "f32" if (local_settings[0] & 0x10) else "f32 (exponent of alpha in f64)", "data": "synthetic",
         "config": {"workload": f"{scenes.CONFIG_NAMES[args.config]} forward", "gaussians": sc.n,
                    "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
-                   "render": tuned["best"] if tuned else "local, one workgroup per tile",
+                   "render": tuned["best"] if tuned else f"{args.render or 'local'}, one workgroup per tile",
                    "pairs": res["num_pairs"]},
         "plain_value": mpix_base, "local_over_plain": mpix / mpix_base,
         "eager_ms_per_step": {"local": res["wall_ms"], "plain": base["wall_ms"]},

@@ -73,16 +73,19 @@ typedef struct lgs_camera {
  * the gfx950 vector ALU issues at the single-precision rate, and alpha, T and
  * the colour are float with the fused update T <- fma(-alpha, T, T) in every
  * variant.  OR with LGS_RENDER_FP32 for the paper's single-precision
- * arithmetic throughout, and with LGS_RENDER_Q8 to change the wavefront
- * sub-tile shape of the culling variants. */
+ * arithmetic throughout, with LGS_RENDER_Q8 to change the wavefront
+ * sub-tile shape of the culling variants, and with LGS_RENDER_VOTE4 to space
+ * out the termination vote of LOCAL. */
 typedef enum {
     LGS_RENDER_PLAIN = 0,       /* baseline per-pixel loop (Alg. 1, baseline column) */
     LGS_RENDER_HOIST = 1,       /* + tile-local hoisted dot product (Sec. III-B) */
     LGS_RENDER_HOIST_CULL = 2,  /* + wavefront-level tight-box culling (Sec. III-C) */
     LGS_RENDER_LOCAL = 3,       /* + uniform blend, wave-wide termination vote (Sec. III-D) */
     LGS_RENDER_FP32 = 0x10,
-    LGS_RENDER_Q8 = 0x20        /* HOIST_CULL / LOCAL: each wavefront owns an 8x8 quadrant of
+    LGS_RENDER_Q8 = 0x20,       /* HOIST_CULL / LOCAL: each wavefront owns an 8x8 quadrant of
                                    the tile instead of a 16x4 row strip (same results) */
+    LGS_RENDER_VOTE4 = 0x40     /* LOCAL: the wave-wide termination vote runs once per 4
+                                   Gaussians instead of after each one (same results) */
 } lgs_render_variant;
 
 /* Message for the last non-OK status on the calling host thread. */

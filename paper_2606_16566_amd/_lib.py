@@ -24,6 +24,7 @@ RENDER_HOIST_CULL = 2
 RENDER_LOCAL = 3
 RENDER_FP32 = 0x10
 RENDER_Q8 = 0x20
+RENDER_VOTE4 = 0x40
 
 MAX_VIEWS = 16
 

@@ -4,6 +4,7 @@ Search space (every point computes the same blend; only the schedule, the
 wavefront sub-tile and the exponent precision change):
 
   shape          16x4 row strips or 8x8 quadrants per wavefront
+  vote           termination vote after every Gaussian, or once per four
   precision      exponent in double, or single precision throughout
   schedule       one workgroup per tile, or a persistent queue of
                  blocks_per_cu workgroups per compute unit (2, 4, 8) handing
@@ -32,17 +33,19 @@ import torch
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "localgs", "autotune.json")
 
-REFERENCE = dict(shape="16x4", precision="fp64", persistent=False, blocks_per_cu=0, lpt=False)
+REFERENCE = dict(shape="16x4", vote=1, precision="fp64", persistent=False, blocks_per_cu=0, lpt=False)
+KEYS = ("family", "shape", "vote", "precision", "persistent", "blocks_per_cu", "lpt")
 
 
 def space(family: str = "local"):
     """All candidate settings of one variant family ('local' or 'hoist_cull')."""
+    votes = (1, 4) if family == "local" else (1,)
     pts = []
-    for shape, prec in itertools.product(("16x4", "8x8"), ("fp64", "fp32")):
-        pts.append(dict(family=family, shape=shape, precision=prec, persistent=False, blocks_per_cu=0, lpt=False))
+    for shape, vote, prec in itertools.product(("16x4", "8x8"), votes, ("fp64", "fp32")):
+        base = dict(family=family, shape=shape, vote=vote, precision=prec)
+        pts.append(dict(base, persistent=False, blocks_per_cu=0, lpt=False))
         for bpc, lpt in itertools.product((2, 4, 8), (False, True)):
-            pts.append(dict(family=family, shape=shape, precision=prec, persistent=True, blocks_per_cu=bpc,
-                            lpt=lpt))
+            pts.append(dict(base, persistent=True, blocks_per_cu=bpc, lpt=lpt))
     return pts
 
 
@@ -50,6 +53,8 @@ def variant_name(cfg) -> str:
     name = cfg.get("family", "local")
     if cfg.get("shape") == "8x8":
         name += "_q8"
+    if cfg.get("vote", 1) == 4:
+        name += "_v4"
     if cfg.get("precision") == "fp32":
         name += "_fp32"
     return name
@@ -131,7 +136,7 @@ def tune(vb, params, family: str = "local", reps: int = 9, warmup: int = 2, tol:
                             max_diff=float(diff.max()), bad_frac=bad, admissible=ok))
     adm = [r for r in results if r["admissible"]]
     best = min(adm, key=lambda r: r["median_ms"])
-    best_cfg = {k: best[k] for k in ("family", "shape", "precision", "persistent", "blocks_per_cu", "lpt")}
+    best_cfg = {k: best[k] for k in KEYS}
     apply(vb, best_cfg)
     if use_cache:
         cache = load_cache(cache_path)

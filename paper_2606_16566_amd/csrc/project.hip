@@ -189,19 +189,35 @@ __device__ bool footprint(const Cam &cam, const Proj &P, int4 &rect)
     return true;
 }
 
+// LDS row stride of one Gaussian's 3K SH floats: odd, so that the 64 lanes
+// reading "their" coefficient k hit distinct banks (a stride of 48 words
+// would put all lanes on two banks).
+constexpr int sh_stride(int K3) { return K3 | 1; }
+
 // Wavefront-cooperative copy of the SH coefficients of this wavefront's 64
-// Gaussians (one contiguous run of 64 * 3K floats) into LDS with 16-byte
-// loads, so that no lane reads its own strided 12K-byte record from HBM.
+// Gaussians (one contiguous run of 64 * 3K floats) into LDS rows of
+// sh_stride(3K) floats, with 16-byte loads, so that no lane reads its own
+// strided record from HBM.
 template <int K3>
 __device__ __forceinline__ void stage_sh(const float *__restrict__ sh, int64_t g0, int cnt, float *s_sh)
 {
+    constexpr int P = sh_stride(K3);
     const float *src = sh + g0 * K3;
     const int total = cnt * K3;
     const int nv = total >> 2;
     const float4 *src4 = reinterpret_cast<const float4 *>(src);
-    float4 *dst4 = reinterpret_cast<float4 *>(s_sh);
-    for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
-    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) s_sh[i] = src[i];
+    if constexpr (P == K3) {
+        float4 *dst4 = reinterpret_cast<float4 *>(s_sh);
+        for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
+    } else {
+        for (int i = __lane_id(); i < nv; i += 64) {
+            const float4 v = src4[i];
+            const int e = 4 * i, g = e / K3, k = e - g * K3;      // K3 % 4 == 0: one row
+            float *d = s_sh + g * P + k;
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+    }
+    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) s_sh[(i / K3) * P + i % K3] = src[i];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
                                                           float *__restrict__ depth, int4 *__restrict__ rect)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ float s_sh[4][64 * 3 * K];
+    __shared__ float s_sh[4][64 * sh_stride(3 * K)];
     const int wid = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
     if (g0 >= n) return;                                   // whole wavefront past the end
@@ -238,7 +254,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
     const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
     const float logit = logits[i];
-    const float *shi = s_sh[wid] + __lane_id() * (3 * K);
+    const float *shi = s_sh[wid] + __lane_id() * sh_stride(3 * K);
     const bool sh_ok = all_finite(shi, 3 * K);
     for (int v = 0; v < cb.V; ++v) {
         const Cam &cam = cb.cam[v];
@@ -397,6 +413,7 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
 template <int K3>
 __device__ __forceinline__ void unstage_sh(float *__restrict__ dst_all, int64_t g0, int cnt, const float *s_sh)
 {
+    constexpr int P = sh_stride(K3);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -404,9 +421,17 @@ __device__ __forceinline__ void unstage_sh(float *__restrict__ dst_all, int64_t 
     const int total = cnt * K3;
     const int nv = total >> 2;
     float4 *dst4 = reinterpret_cast<float4 *>(dst);
-    const float4 *src4 = reinterpret_cast<const float4 *>(s_sh);
-    for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
-    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) dst[i] = s_sh[i];
+    if constexpr (P == K3) {
+        const float4 *src4 = reinterpret_cast<const float4 *>(s_sh);
+        for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
+    } else {
+        for (int i = __lane_id(); i < nv; i += 64) {
+            const int e = 4 * i, g = e / K3, k = e - g * K3;
+            const float *q = s_sh + g * P + k;
+            dst4[i] = make_float4(q[0], q[1], q[2], q[3]);
+        }
+    }
+    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) dst[i] = s_sh[(i / K3) * P + i % K3];
 }
 
 template <int DEG>
@@ -423,15 +448,16 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
                                                           float *__restrict__ d_logits, float *__restrict__ d_sh)
 {
     constexpr int K3 = 3 * (DEG + 1) * (DEG + 1);
-    __shared__ float s_sh[2][64 * K3];
-    __shared__ float s_dsh[2][64 * K3];
+    constexpr int P = sh_stride(K3);
+    __shared__ float s_sh[2][64 * P];
+    __shared__ float s_dsh[2][64 * P];
     const int wid = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
     if (g0 >= n) return;                                   // whole wavefront past the end
     const int cnt = (int)min((int64_t)64, n - g0);
     stage_sh<K3>(sh, g0, cnt, s_sh[wid]);
     const int64_t i = g0 + __lane_id();
-    float *dslot = s_dsh[wid] + __lane_id() * K3;
+    float *dslot = s_dsh[wid] + __lane_id() * P;
     for (int k = 0; k < K3; ++k) dslot[k] = 0.f;
     if (i < n) {
         const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
@@ -439,7 +465,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
         const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
         const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
         const float logit = logits[i];
-        const float *shi = s_sh[wid] + __lane_id() * K3;
+        const float *shi = s_sh[wid] + __lane_id() * P;
         RawGrad acc = {};
         for (int v = 0; v < cb.V; ++v) {
             const int64_t o = (int64_t)v * n + i;

@@ -148,7 +148,7 @@ struct WaveStats {
 
 // One 16x4 strip of one tile, processed by one wavefront with its own LDS
 // slots (no workgroup barrier).
-template <bool UNIFORM, typename R, bool STATS>
+template <bool UNIFORM, typename R, bool STATS, int VP>
 __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileCtx<R> &tc, Hoisted<R> *s_e,
                                              float4 *s_c, WaveStats &st)
 {
@@ -193,7 +193,16 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
         const int chunk = (int)min((uint32_t)64, range.y - base);
         int consumed = chunk;
         if constexpr (UNIFORM) {
-            for (int k = 0; k < cnt; ++k) {
+            // the wave-wide vote runs once per VP Gaussians; steps after the
+            // last lane has stopped change nothing (every update is masked by
+            // the lane's live predicate)
+            for (int k0 = 0; k0 < cnt; k0 += VP) {
+                int kdone = k0;
+#pragma unroll
+                for (int u = 0; u < VP; ++u) {
+                const int k = k0 + u;
+                if (VP > 1 && k >= cnt) break;
+                kdone = k;
                 const float4 f = s_c[k];
                 const float s32 = (float)dot_exponent(s_e[k], tc);
                 const bool keep = s32 >= kLog2AlphaMin;
@@ -209,9 +218,10 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
                 last = (lv && keep) ? __float_as_int(f.w) : last;
                 live = lv;
                 if (STATS) st.eval++;
+                }
                 if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
                     wave_live = false;
-                    if (STATS) consumed = __float_as_int(f.w) - (int)(base - range.x);
+                    if (STATS) consumed = __float_as_int(s_c[kdone].w) - (int)(base - range.x);
                     break;
                 }
             }
@@ -255,7 +265,7 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
 // (args.queue != null): every wavefront pops (tile, strip) units from the
 // device counter until all 4 * num_tiles units are taken, so no wavefront
 // waits for the others of its workgroup and the tail is balanced.
-template <bool UNIFORM, typename R, bool STATS, bool Q8>
+template <bool UNIFORM, typename R, bool STATS, bool Q8, int VP>
 __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
 {
     __shared__ Hoisted<R> s_e[kBlock / 64][64];
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
     WaveStats st;
     if (args.queue == nullptr) {
         const TileCtx<R> tc(args, xcd_tile(blockIdx.x, args.num_tiles), wid, Q8);
-        render_strip<UNIFORM, R, STATS>(args, tc, s_e[wid], s_c[wid], st);
+        render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
     } else {
         const uint32_t units = 4u * (uint32_t)args.num_tiles;
         for (;;) {
@@ -274,21 +284,21 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
             if (u >= units) break;
             const int tile = args.order ? (int)args.order[u >> 2] : (int)(u >> 2);
             const TileCtx<R> tc(args, tile, (int)(u & 3u), Q8);
-            render_strip<UNIFORM, R, STATS>(args, tc, s_e[wid], s_c[wid], st);
+            render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
         }
     }
     if (STATS) flush_stats<true>(args, st.seen, st.eval, st.staged);
 }
 
-template <bool UNIFORM, typename R, bool Q8>
+template <bool UNIFORM, typename R, bool Q8, int VP>
 void launch_wave(bool stats, dim3 g, dim3 block, hipStream_t s, const RenderArgs &a)
 {
-    if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8>), g, block, 0, s, a);
-    else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8>), g, block, 0, s, a);
+    if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8, VP>), g, block, 0, s, a);
+    else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8, VP>), g, block, 0, s, a);
 }
 
 template <int V, typename R>
-void launch_render(const RenderArgs &a, bool stats, bool q8, unsigned grid, hipStream_t s)
+void launch_render(const RenderArgs &a, bool stats, bool q8, bool vote4, unsigned grid, hipStream_t s)
 {
     const dim3 g(grid), block(kBlock);
     switch (V) {
@@ -301,12 +311,17 @@ void launch_render(const RenderArgs &a, bool stats, bool q8, unsigned grid, hipS
         else hipLaunchKernelGGL((render_block_kernel<true, R, false>), g, block, 0, s, a);
         break;
     case LGS_RENDER_HOIST_CULL:
-        if (q8) launch_wave<false, R, true>(stats, g, block, s, a);
-        else launch_wave<false, R, false>(stats, g, block, s, a);
+        if (q8) launch_wave<false, R, true, 1>(stats, g, block, s, a);
+        else launch_wave<false, R, false, 1>(stats, g, block, s, a);
         break;
     default:
-        if (q8) launch_wave<true, R, true>(stats, g, block, s, a);
-        else launch_wave<true, R, false>(stats, g, block, s, a);
+        if (vote4) {
+            if (q8) launch_wave<true, R, true, 4>(stats, g, block, s, a);
+            else launch_wave<true, R, false, 4>(stats, g, block, s, a);
+        } else {
+            if (q8) launch_wave<true, R, true, 1>(stats, g, block, s, a);
+            else launch_wave<true, R, false, 1>(stats, g, block, s, a);
+        }
         break;
     }
 }
@@ -345,7 +360,8 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     const int v = variant & 0xF;
     const bool fp32 = (variant & LGS_RENDER_FP32) != 0;
     const bool q8 = (variant & LGS_RENDER_Q8) != 0;
-    LGS_REQUIRE(v >= 0 && v <= 3 && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8)) == 0,
+    const bool vote4 = (variant & LGS_RENDER_VOTE4) != 0;
+    LGS_REQUIRE(v >= 0 && v <= 3 && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8 | LGS_RENDER_VOTE4)) == 0,
                 "lgs_render: unknown variant %d", variant);
     LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
     LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && (means2d == nullptr || (uintptr_t)means2d % 8 == 0)
@@ -366,17 +382,17 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     const bool st = stats != nullptr;
     if (fp32) {
         switch (v) {
-        case 0: launch_render<0, float>(a, st, q8, grid, s); break;
-        case 1: launch_render<1, float>(a, st, q8, grid, s); break;
-        case 2: launch_render<2, float>(a, st, q8, grid, s); break;
-        default: launch_render<3, float>(a, st, q8, grid, s); break;
+        case 0: launch_render<0, float>(a, st, q8, vote4, grid, s); break;
+        case 1: launch_render<1, float>(a, st, q8, vote4, grid, s); break;
+        case 2: launch_render<2, float>(a, st, q8, vote4, grid, s); break;
+        default: launch_render<3, float>(a, st, q8, vote4, grid, s); break;
         }
     } else {
         switch (v) {
-        case 0: launch_render<0, double>(a, st, q8, grid, s); break;
-        case 1: launch_render<1, double>(a, st, q8, grid, s); break;
-        case 2: launch_render<2, double>(a, st, q8, grid, s); break;
-        default: launch_render<3, double>(a, st, q8, grid, s); break;
+        case 0: launch_render<0, double>(a, st, q8, vote4, grid, s); break;
+        case 1: launch_render<1, double>(a, st, q8, vote4, grid, s); break;
+        case 2: launch_render<2, double>(a, st, q8, vote4, grid, s); break;
+        default: launch_render<3, double>(a, st, q8, vote4, grid, s); break;
         }
     }
     LGS_LAUNCHED("lgs_render");

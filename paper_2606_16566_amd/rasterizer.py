@@ -18,14 +18,16 @@ VARIANTS = {"plain": L.RENDER_PLAIN, "hoist": L.RENDER_HOIST, "hoist_cull": L.RE
 
 
 def variant_code(variant) -> int:
-    """'local' / 'plain' / ... with optional '_q8' and '_fp32' suffixes (in
-    that order, e.g. 'local_q8_fp32'), or an int."""
+    """'local' / 'plain' / ... with optional '_q8', '_v4' and '_fp32'
+    suffixes (in that order, e.g. 'local_q8_v4_fp32'), or an int."""
     if isinstance(variant, int):
         return variant
     v = variant.lower()
     code = 0
     if v.endswith("_fp32"):
         v, code = v[:-5], code | L.RENDER_FP32
+    if v.endswith("_v4"):
+        v, code = v[:-3], code | L.RENDER_VOTE4
     if v.endswith("_q8"):
         v, code = v[:-3], code | L.RENDER_Q8
     return VARIANTS[v] | code

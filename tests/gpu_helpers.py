@@ -5,7 +5,7 @@ import torch
 from paper_2606_16566_amd import rasterizer as R
 from paper_2606_16566_amd import scenes
 
-VARIANTS = ["plain", "hoist", "hoist_cull", "local", "hoist_cull_q8", "local_q8"]
+VARIANTS = ["plain", "hoist", "hoist_cull", "local", "hoist_cull_q8", "local_q8", "local_v4", "local_q8_v4"]
 
 
 def to_dev(a, dtype=None):

@@ -51,7 +51,7 @@ def _close_scaled(got, want, name, tol=SUM_TOL):
     assert err <= tol, (name, err)
 
 
-@pytest.mark.parametrize("variant", ["local", "plain", "hoist_cull", "local_fp32"])
+@pytest.mark.parametrize("variant", ["local", "plain", "hoist_cull", "local_fp32", "local_q8_v4"])
 def test_batch_forward_bitwise_small(variant):
     sc = scenes.make_config(5, n=20000)
     cams = ring_cameras([(160, 120), (203, 150), (96, 64), (33, 47)])

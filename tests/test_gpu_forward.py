@@ -155,8 +155,9 @@ def test_render_only_ladder(seed, W, H, n):
         for k in range(3):
             assert np.array_equal(outs["hoist"][k], outs[v][k]), v
     for k in range(3):
-        assert np.array_equal(outs["local"][k], outs["local_q8"][k])
-        assert np.array_equal(outs["local_fp32"][k], outs["local_q8_fp32"][k])
+        for v in ("local_q8", "local_v4", "local_q8_v4"):
+            assert np.array_equal(outs["local"][k], outs[v][k]), v
+            assert np.array_equal(outs["local_fp32"][k], outs[v + "_fp32"][k]), v
     for v in ("hoist", "hoist_cull", "local", "hoist_cull_q8", "local_q8"):
         d = np.abs(outs[v][0] - outs["plain"][0])[:, ok].max()
         assert d <= TOL_LADDER, (v, d)
@@ -214,7 +215,7 @@ def test_render_stats_culled_fraction():
         R.render(v, cam, b, proj, stats=s)
         st[v] = _sync_np(s)
     # the culling variants evaluate strictly fewer wavefront steps than they meet
-    for v in ("hoist_cull", "local", "hoist_cull_q8", "local_q8"):
+    for v in ("hoist_cull", "local", "hoist_cull_q8", "local_q8", "local_v4", "local_q8_v4"):
         assert 0 < st[v][1] < st[v][0]
     assert st["plain"][1] == st["plain"][0] and st["hoist"][1] == st["hoist"][0]
     # every variant stages the same batches up to its own termination point
@@ -233,7 +234,7 @@ def test_end_to_end_parity(cfg, n, view):
     ok = ~O.flagged(ref["margin"], GUARD_E2E)
     assert ok.mean() > 0.98
     imgs = {}
-    for v in ("plain", "local", "local_q8"):
+    for v in ("plain", "local", "local_q8", "local_q8_v4"):
         img, T, nc, (proj, b) = R.rasterize(cam, *scene_tensors(sc), variant=v)
         imgs[v] = _sync_np(img)
         assert np.abs(imgs[v] - ref["image"])[:, ok].max() <= TOL_ORACLE, v
@@ -241,6 +242,7 @@ def test_end_to_end_parity(cfg, n, view):
         assert np.array_equal(last_ids(b, nc, cam)[ok], ref["last_id"][ok]), v
     assert np.abs(imgs["local"] - imgs["plain"]).max() <= TOL_LADDER
     assert np.array_equal(imgs["local"], imgs["local_q8"])
+    assert np.array_equal(imgs["local"], imgs["local_q8_v4"])
 
 
 @pytest.mark.slow
