@@ -18,7 +18,8 @@
 // the workgroup's LDS accumulators with one 36-lane LDS atomic, and the
 // accumulators are flushed with one global atomic per (tile, Gaussian,
 // component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
-// (hardware estimate refined by two Newton steps in double).
+// (hardware estimate refined by two Newton steps in double); T and the
+// running colour sums stay in double, the per-pixel partials are float.
 #include "common.hpp"
 
 #include "render_common.hpp"
@@ -54,8 +55,8 @@ __device__ __forceinline__ float row_sum16(float v)
     return v;
 }
 
-// 1 / x for normal positive x (here 1 - alpha in [0.01, 1] and the opacity
-// in [1/255, 1]): hardware estimate and two Newton steps
+// 1 / x for normal positive x (here 1 - alpha in [0.01, 1]): hardware
+// estimate and two Newton steps
 __device__ __forceinline__ double recip(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -152,14 +153,16 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 const int pos1 = (int)(bstart + k - range.x) + 1;
                 const float4 co = s_co[k];
                 const float2 m = s_mu[k];
-                const double dx = (double)px - (double)m.x, dy = (double)py - (double)m.y;
                 double s;
                 if (LOCAL) {
                     s = dot_exponent(s_v[k], tc);
                 } else {
-                    const double q = (double)co.x * dx * dx + 2.0 * (double)co.y * dx * dy + (double)co.z * dy * dy;
+                    const double dxd = (double)px - (double)m.x, dyd = (double)py - (double)m.y;
+                    const double q = (double)co.x * dxd * dxd + 2.0 * (double)co.y * dxd * dyd
+                                     + (double)co.z * dyd * dyd;
                     s = s_v[k].v[5] - 0.5 * kLog2e * q;
                 }
+                const float dx = (float)px - m.x, dy = (float)py - m.y;
                 const float s32 = (float)s;
                 const float raw = __builtin_amdgcn_exp2f(s32);
                 const bool act = pos1 <= last && s32 >= kLog2AlphaMin;
@@ -176,16 +179,20 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                     double dLda = (double)gc0 * ((double)f.x * T - R0 * inv) + (double)gc1 * ((double)f.y * T - R1 * inv)
                                   + (double)gc2 * ((double)f.z * T - R2 * inv) - gt * Tf * inv;
                     R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
-                    g[6] = (float)(gc0 * w); g[7] = (float)(gc1 * w); g[8] = (float)(gc2 * w);
+                    // the per-pixel partials are single terms (no long sums):
+                    // float is enough for them
+                    const float wf = (float)w;
+                    g[6] = gc0 * wf; g[7] = gc1 * wf; g[8] = gc2 * wf;
                     if (!clamped) {
-                        const double dLdq = -0.5 * al * dLda;
-                        const double ca = co.x, cb = co.y, cc = co.z;
-                        g[0] = (float)(-2.0 * dLdq * (ca * dx + cb * dy));
-                        g[1] = (float)(-2.0 * dLdq * (cb * dx + cc * dy));
-                        g[2] = (float)(dLdq * dx * dx);
-                        g[3] = (float)(dLdq * 2.0 * dx * dy);
-                        g[4] = (float)(dLdq * dy * dy);
-                        g[5] = (float)(dLda * al * recip((double)co.w));
+                        const float alf = (float)al, dLdaf = (float)dLda;
+                        const float dLdq = -0.5f * alf * dLdaf;
+                        const float m2 = -2.0f * dLdq;
+                        g[0] = m2 * fmaf(co.x, dx, co.y * dy);
+                        g[1] = m2 * fmaf(co.y, dx, co.z * dy);
+                        g[2] = dLdq * dx * dx;
+                        g[3] = 2.0f * dLdq * dx * dy;
+                        g[4] = dLdq * dy * dy;
+                        g[5] = dLdaf * raw * __builtin_amdgcn_rcpf(co.w);
                     }
                 }
                 if (__ballot(act) != 0ull) {

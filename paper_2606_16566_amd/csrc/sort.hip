@@ -18,18 +18,18 @@ namespace {
 
 constexpr int kScanItems = 8;                          // per thread
 constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
-// Radix blocks hold 256 * ITEMS elements: 2048 (ITEMS = 8) for short inputs,
-// so that enough blocks exist to fill the chip, 4096 (ITEMS = 16) for long
-// ones, which halves the per-block histogram traffic and lengthens the digit
-// runs that the scatter writes contiguously (8192 per block measured slower:
-// its 70 KB of LDS leaves two workgroups per CU).
-constexpr int kRadixItems = 8;                         // small blocks
-#ifndef LGS_RADIX_ITEMS_LARGE
-#define LGS_RADIX_ITEMS_LARGE 16
-#endif
-constexpr int kRadixItemsLarge = LGS_RADIX_ITEMS_LARGE;  // large blocks (build-time tuning)
+// Radix blocks (one histogram partition each) hold 256 * ITEMS elements, in
+// three tiers by input length: 2048 below 2^22 elements, so that enough
+// blocks exist to fill the chip; 4096 up to 2^25; 8192 beyond, which cuts
+// the per-block histogram traffic and lengthens the digit runs that the
+// scatter writes contiguously.  The two larger tiers scatter with 512-thread
+// workgroups (8 elements per thread in the middle tier, 16 in the top one),
+// which keeps registers and LDS low enough for 8 and 4 waves per SIMD.
+// Each tier was the fastest measured at its size.
+constexpr int kRadixItems = 8;                         // smallest tier
 constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
-constexpr int64_t kLargeRadixFrom = 1 << 22;           // elements
+constexpr int64_t kMidRadixFrom = 1 << 22;             // elements
+constexpr int64_t kLargeRadixFrom = 1 << 25;           // elements
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kWaves = kBlock / 64;
@@ -399,44 +399,42 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
 // leaves room for more resident workgroups.  vals_in == nullptr means the
 // values are the element indices.  With gather_dst set, the 16-byte record
 // gather_src[value] of every element is also written to its sorted place.
-#ifndef LGS_SCATTER_MIN_WAVES
-#define LGS_SCATTER_MIN_WAVES 1
-#endif
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LGS_SCATTER_MIN_WAVES))) void
-radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
-                                                               const uint32_t *__restrict__ vals_in,
-                                                               uint32_t *__restrict__ keys_out,
-                                                               uint32_t *__restrict__ vals_out, int64_t n_max,
-                                                               const uint32_t *n_dev, int shift, int nbits,
-                                                               const uint32_t *__restrict__ hist_scan,
-                                                               const uint32_t *__restrict__ digit_total,
-                                                               int64_t stride, const int4 *__restrict__ gather_src,
-                                                               int4 *__restrict__ gather_dst)
+template <int ITEMS, int NT>
+__global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
+                                                           const uint32_t *__restrict__ vals_in,
+                                                           uint32_t *__restrict__ keys_out,
+                                                           uint32_t *__restrict__ vals_out, int64_t n_max,
+                                                           const uint32_t *n_dev, int shift, int nbits,
+                                                           const uint32_t *__restrict__ hist_scan,
+                                                           const uint32_t *__restrict__ digit_total,
+                                                           int64_t stride, const int4 *__restrict__ gather_src,
+                                                           int4 *__restrict__ gather_dst)
 {
-    constexpr int kTileN = kBlock * ITEMS;
-    constexpr int kPerWave = kTileN / kWaves;
+    constexpr int kW = NT / 64;                             // wavefronts per workgroup
+    constexpr int kTileN = NT * ITEMS;
+    constexpr int kPerWave = kTileN / kW;
     const uint32_t mask = (1u << nbits) - 1u;
-    __shared__ uint32_t s_wc[kWaves][kRadixBins];          // running, then exclusive-over-waves counts
+    __shared__ uint32_t s_wc[kW][kRadixBins];              // running, then exclusive-over-waves counts
     __shared__ uint32_t s_lbase[kRadixBins];               // block-local digit offsets
     __shared__ uint32_t s_gbase[kRadixBins];               // global digit offsets of this block
     __shared__ uint32_t s_buf[kTileN];                     // keys, then values, in digit order
     __shared__ uint8_t s_dig[kTileN];                      // digit of each slot of s_buf
-    __shared__ uint32_t s_tot[kWaves];
+    __shared__ uint32_t s_tot[kW];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t start = (int64_t)blockIdx.x * kTileN;
     if (start >= n) return;                                  // uniform across the block
     const int count = (int)min((int64_t)kTileN, n - start);
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int t = threadIdx.x;                               // digit of the per-digit phases (t < 256)
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
     {
         // global base of digit t: all smaller digits + this digit in earlier blocks
-        const uint32_t tot = digit_total[threadIdx.x];
+        const uint32_t tot = t < kRadixBins ? digit_total[t] : 0u;
         uint32_t all;
-        const uint32_t before = block_exclusive_scan<uint32_t, kWaves>(tot, all, s_tot);
-        s_gbase[threadIdx.x] = before + hist_scan[(int64_t)threadIdx.x * stride + blockIdx.x];
+        const uint32_t before = block_exclusive_scan<uint32_t, kW>(tot, all, s_tot);
+        if (t < kRadixBins) s_gbase[t] = before + hist_scan[(int64_t)t * stride + blockIdx.x];
     }
 
     const uint32_t *kin = keys_in + start;                  // uniform bases, 32-bit offsets
@@ -462,16 +460,18 @@ radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
     __syncthreads();
     // digit t: prefix over wavefronts, block total, exclusive scan over digits
     {
-        const int t = threadIdx.x;
         uint32_t run = 0;
+        if (t < kRadixBins) {
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            const uint32_t c = s_wc[w][t];
-            s_wc[w][t] = run;
-            run += c;
+            for (int w = 0; w < kW; ++w) {
+                const uint32_t c = s_wc[w][t];
+                s_wc[w][t] = run;
+                run += c;
+            }
         }
         uint32_t tot;
-        s_lbase[t] = block_exclusive_scan<uint32_t, kWaves>(run, tot, s_tot);
+        const uint32_t ex = block_exclusive_scan<uint32_t, kW>(run, tot, s_tot);
+        if (t < kRadixBins) s_lbase[t] = ex;
     }
     __syncthreads();
 #pragma unroll
@@ -495,7 +495,7 @@ radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int i = threadIdx.x + r * kBlock;
+        const int i = threadIdx.x + r * NT;
         if (i < count) {
             const uint32_t d = s_dig[i];
             keys_out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = s_buf[i];
@@ -510,7 +510,7 @@ radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int i = threadIdx.x + r * kBlock;
+        const int i = threadIdx.x + r * NT;
         if (i < count) {
             const uint32_t d = s_dig[i];
             const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
@@ -623,7 +623,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 
 // one stable radix pass over [0, min(n_max, *n_dev)) on key bits
 // [shift, shift + bits)
-template <int ITEMS>
+template <int ITEMS, int SCATTER_THREADS>
 void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
                   const int4 *gather_src, int4 *gather_dst)
@@ -637,7 +637,9 @@ void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint
                        n_max, n_dev, shift, mask, w.hist, stride);
     hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
                        kTileN, w.digit_total);
-    hipLaunchKernelGGL(radix_scatter_kernel<ITEMS>, dim3((unsigned)nb), dim3(kBlock), 0, s, kin, vin, kout, vout,
+    constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
+    hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS>), dim3((unsigned)nb),
+                       dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
                        n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
                        stride, gather_src, gather_dst);
 }
@@ -647,10 +649,12 @@ void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32
                 const int4 *gather_src = nullptr, int4 *gather_dst = nullptr)
 {
     if (n_max >= kLargeRadixFrom)
-        radix_pass_t<kRadixItemsLarge>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                       gather_dst);
+        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
+    else if (n_max >= kMidRadixFrom)
+        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
     else
-        radix_pass_t<kRadixItems>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
+        radix_pass_t<kRadixItems, kBlock>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
+                                          gather_dst);
 }
 
 

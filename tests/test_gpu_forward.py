@@ -78,8 +78,9 @@ def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True):
 
 @pytest.mark.parametrize("seed,n,tx,ty,ties", [(0, 5000, 13, 9, True), (1, 40000, 120, 68, False),
                                               (2, 3, 1, 1, True), (3, 70000, 300, 260, True),
-                                              # above 2^22 pairs: the large radix blocks
-                                              (4, 1000000, 120, 68, False), (5, 800000, 300, 260, True)])
+                                              # above 2^22 and 2^25 pairs: the larger radix tiers
+                                              (4, 1000000, 120, 68, False), (5, 800000, 300, 260, True),
+                                              pytest.param(6, 6000000, 300, 260, False, marks=pytest.mark.slow)])
 def test_sort_and_ranges_parity(seed, n, tx, ty, ties):
     vis, depth, rect = _synthetic_bins(seed, n, tx, ty, ties)
     print(f"sort seed={seed} n={n} tiles={tx}x{ty}", flush=True)
