@@ -36,6 +36,27 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 # colour, T update, termination compare
 OPS_PER_PAIR = 14
 
+# HBM bytes per launch of the blend kernel, from the rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs summarised in profiles/forward_uniform-1M-1920x1080-sh3_
+# hbm_counters.md (24.7 MiB read, 41.3 MiB written, after the copy-kernel
+# calibration), valid for the variant, workload and kernel sources they were
+# taken with; anything else reports null.
+RENDER_TRAFFIC = {"variant": 0x63, "sources_sha": "011c771dcc12e0ce", "bytes": (24.7 + 41.3) * 2 ** 20,
+                  "workload": 2}
+RENDER_SOURCES = ("paper_2606_16566_amd/csrc/render.hip", "paper_2606_16566_amd/csrc/render_common.hpp",
+                  "paper_2606_16566_amd/csrc/common.hpp")
+
+
+def render_traffic(variant: int, config: int):
+    import hashlib
+    h = hashlib.sha256()
+    for f in RENDER_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    ok = (h.hexdigest()[:16] == RENDER_TRAFFIC["sources_sha"] and variant == RENDER_TRAFFIC["variant"]
+          and config == RENDER_TRAFFIC["workload"])
+    return RENDER_TRAFFIC["bytes"] if ok else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -268,7 +289,9 @@ def main():
     achieved = lane_evals * OPS_PER_PAIR / (res["render_ms"] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": f"render_wave_kernel (variant code {vb.variant})", "achieved": achieved,
                 "peak": PEAK_VALU_TOPS, "unit": "Tops/s (full-rate VALU lane ops)",
-                "frac": achieved / PEAK_VALU_TOPS, "traffic": None, "ops_per_pair": OPS_PER_PAIR,
+                "frac": achieved / PEAK_VALU_TOPS, "traffic": render_traffic(vb.variant, args.config),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE, calibrated "
+                                "on a 512 MiB copy)", "ops_per_pair": OPS_PER_PAIR,
                 "lane_evaluations": lane_evals, "launch_ms": res["render_ms"],
                 "culled_wave_fraction": float(1.0 - st[1] / max(st[0], 1))}
 
