@@ -183,7 +183,10 @@ lgs_status lgs_render(int32_t variant, const lgs_camera *cam, const uint32_t *ra
  * recovering T from the stored final T.  Writes (overwrites) dL/d means2d
  * [n,2], dL/d conic (a, b, c) [n,3], dL/d opacity [n], dL/d rgb [n,3];
  * the clamp at 0.99 and all skip / stop decisions are held fixed.
- * `variant` is LGS_RENDER_PLAIN or LGS_RENDER_LOCAL (hoisted, culled).
+ * `variant` is LGS_RENDER_PLAIN or LGS_RENDER_LOCAL (hoisted, culled), the
+ * latter optionally with LGS_RENDER_Q8 (8x8 wavefront quadrants for the
+ * culling); the other flag bits are ignored.  Gradients agree across these
+ * choices up to the order of floating-point summation.
  */
 lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam, int64_t n, const uint32_t *ranges,
                                const uint32_t *values, const float *means2d, const float *conic_opacity,

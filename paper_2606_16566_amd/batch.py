@@ -211,7 +211,7 @@ class ViewBatch:
         lb, s = L.lib(), _stream()
         means3d, log_scales, quats, logits, sh = params
         g = self.grad_rgb if grad_rgb is None else _req(grad_rgb, torch.float32, "grad_rgb")
-        bv = L.RENDER_PLAIN if (self.variant & 0xF) == L.RENDER_PLAIN else L.RENDER_LOCAL
+        bv = L.RENDER_PLAIN if (self.variant & 0xF) == L.RENDER_PLAIN else L.RENDER_LOCAL | (self.variant & L.RENDER_Q8)
         L.check(lb.lgs_render_backward_batch(bv, self.cam_arr, self.V, self.V * self.n, _p(self.ranges),
                                              _p(self.vals), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
                                              _p(self.out_T), _p(self.out_nc), _p(g), _p(grad_T), _p(self.g_means2d),

@@ -66,7 +66,7 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, e, r);
 }
 
-template <bool LOCAL>
+template <bool LOCAL, bool Q8>
 __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
 {
     __shared__ Hoisted<double> s_v[kBlock];  // hoisted exponent coefficients
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     __shared__ int s_max[kBlock / 64];
 
     const RenderArgs &a = ba.r;
-    const TileCtx<double> tc(a, xcd_tile(blockIdx.x, a.num_tiles), threadIdx.x >> 6);
+    const TileCtx<double> tc(a, xcd_tile(blockIdx.x, a.num_tiles), threadIdx.x >> 6, Q8);
     const int lane = __lane_id(), wid = tc.wid;
     const int px = tc.px, py = tc.py;
     const bool inside = tc.inside;
@@ -121,14 +121,33 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             const float lo = __builtin_amdgcn_logf(co.w);
             if (LOCAL) {
                 s_v[k] = hoist<double>(m, co, lo, tc.ox, tc.oy);
-                // strip bits of the four wavefronts (same test as the forward)
+                // strip bits of the four wavefronts (the forward's test; the
+                // strips share their columns, so the ellipse's vertical span
+                // over them is computed once)
                 uint32_t mk = 0;
-                const float x0 = (float)(tx * kTile) - m.x, x1 = (float)(tx * kTile + kTile - 1) - m.x;
-                for (int w = 0; w < 4; ++w) {
-                    const int r0 = ty * kTile + 4 * w;
-                    if (r0 > tc.H - 1) break;
-                    const int r1 = min(r0 + 3, tc.H - 1);
-                    if (strip_hit(co.x, co.y, co.z, lo, x0, x1, (float)r0 - m.y, (float)r1 - m.y)) mk |= 1u << w;
+                float ymin, ymax;
+                if constexpr (Q8) {
+                    // quadrant w: columns half (w & 1), rows half (w >> 1)
+                    for (int hx = 0; hx < 2; ++hx) {
+                        const float x0 = (float)(tx * kTile + 8 * hx) - m.x, x1 = x0 + 7.0f;
+                        if (!column_span(co.x, co.y, co.z, lo, x0, x1, ymin, ymax)) continue;
+                        for (int hy = 0; hy < 2; ++hy) {
+                            const int r0 = ty * kTile + 8 * hy;
+                            if (r0 > tc.H - 1) break;
+                            const int r1 = min(r0 + 7, tc.H - 1);
+                            if (span_meets(ymin, ymax, (float)r0 - m.y, (float)r1 - m.y)) mk |= 1u << (2 * hy + hx);
+                        }
+                    }
+                } else {
+                    const float x0 = (float)(tx * kTile) - m.x, x1 = (float)(tx * kTile + kTile - 1) - m.x;
+                    if (column_span(co.x, co.y, co.z, lo, x0, x1, ymin, ymax)) {
+                        for (int w = 0; w < 4; ++w) {
+                            const int r0 = ty * kTile + 4 * w;
+                            if (r0 > tc.H - 1) break;
+                            const int r1 = min(r0 + 3, tc.H - 1);
+                            if (span_meets(ymin, ymax, (float)r0 - m.y, (float)r1 - m.y)) mk |= 1u << w;
+                        }
+                    }
                 }
                 s_m[k] = (uint8_t)mk;
             } else {
@@ -264,9 +283,12 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
     a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
     if (a.r.num_tiles > 0) {
         if (v == LGS_RENDER_LOCAL)
-            hipLaunchKernelGGL(render_bwd_kernel<true>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+            if (variant & LGS_RENDER_Q8)
+                hipLaunchKernelGGL((render_bwd_kernel<true, true>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+            else
+                hipLaunchKernelGGL((render_bwd_kernel<true, false>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
         else
-            hipLaunchKernelGGL(render_bwd_kernel<false>, dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+            hipLaunchKernelGGL((render_bwd_kernel<false, false>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
     }
     LGS_LAUNCHED("lgs_render_backward");
     return LGS_OK;

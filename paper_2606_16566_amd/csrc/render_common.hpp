@@ -186,8 +186,11 @@ __device__ __forceinline__ R dot_exponent(const Hoisted<R> &h, const TileCtx<R> 
 // square-root arguments stay >= c (tau' - tau) at the true tangent points),
 // so a Gaussian that can reach alpha >= 1/255 at a pixel of the strip is
 // never culled.
-__device__ __forceinline__ bool strip_hit(float a, float b, float c, float lo, float x0, float x1, float y0,
-                                          float y1)
+// Vertical extent [ymin, ymax] of that enlarged ellipse over the columns
+// [x0, x1]; false when it misses the columns entirely.  A degenerate conic
+// (not positive definite) gives the whole line.
+__device__ __forceinline__ bool column_span(float a, float b, float c, float lo, float x0, float x1, float &ymin,
+                                            float &ymax)
 {
     float tau = 2.0f * kLn2f * (lo - kLog2AlphaMin);
     if (!(tau > 0.0f)) return false;
@@ -195,10 +198,13 @@ __device__ __forceinline__ bool strip_hit(float a, float b, float c, float lo, f
     const float p = b * b;
     const float pe = fmaf(b, b, -p);
     const float det = fmaf(a, c, -p) - pe;
-    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return true;
+    if (!(det > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) {
+        ymin = -INFINITY;
+        ymax = INFINITY;
+        return true;
+    }
     const float dy = sqrtf(a * tau / det);
     const float bdy = b * dy;
-    float ymax, ymin;
     if (-bdy < a * x0) {                       // case A: peak left of the columns
         const float arg = c * tau - det * x0 * x0;
         if (arg < 0.0f) return false;
@@ -221,7 +227,21 @@ __device__ __forceinline__ bool strip_hit(float a, float b, float c, float lo, f
     } else {
         ymin = -dy;
     }
+    return true;
+}
+
+// does the span meet the rows [y0, y1]?
+__device__ __forceinline__ bool span_meets(float ymin, float ymax, float y0, float y1)
+{
     return ymax >= y0 - 1e-3f && ymin <= y1 + 1e-3f;
+}
+
+// the whole test for one rectangle
+__device__ __forceinline__ bool strip_hit(float a, float b, float c, float lo, float x0, float x1, float y0,
+                                          float y1)
+{
+    float ymin, ymax;
+    return column_span(a, b, c, lo, x0, x1, ymin, ymax) && span_meets(ymin, ymax, y0, y1);
 }
 
 template <typename R>

@@ -90,11 +90,13 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(L ld, int64_t n_max
 {
     __shared__ T s_warp[kWaves];
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    // only the block total is needed here, so lanes read consecutive
+    // elements (coalesced) rather than the per-thread runs of the final pass
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     T sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) sum += ld(base + k);
+        if (base + k * kBlock < n) sum += ld(base + k * kBlock);
     T total;
     block_exclusive_scan<T, kWaves>(sum, total, s_warp);
     if (threadIdx.x == 0) partials[blockIdx.x] = total;

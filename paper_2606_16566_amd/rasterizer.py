@@ -209,7 +209,8 @@ class LocalGSFunction(torch.autograd.Function):
         means3d, log_scales, quats, opacity_logits, sh, T, nc = ctx.saved_tensors
         grad_img = grad_img.contiguous() if grad_img is not None else torch.zeros((3,) + T.shape, device=T.device)
         grad_T = grad_T.contiguous() if grad_T is not None else None
-        var = "plain" if variant_code(ctx.variant) & 0xF == L.RENDER_PLAIN else "local"
+        code = variant_code(ctx.variant)
+        var = L.RENDER_PLAIN if code & 0xF == L.RENDER_PLAIN else L.RENDER_LOCAL | (code & L.RENDER_Q8)
         g = render_backward(var, ctx.cam, ctx.binned, ctx.proj, T, nc, grad_img, grad_T)
         d = project_backward(ctx.cam, means3d, log_scales, quats, opacity_logits, sh, ctx.proj.rect, g)
         return d["means3d"], d["log_scales"], d["quats"], d["opacity_logits"], d["sh"], None, None, None

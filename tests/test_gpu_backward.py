@@ -38,7 +38,7 @@ def assert_grad_close(got, want, name, tol=GRAD_TOL):
 
 
 @pytest.mark.parametrize("seed,W,H,n", [(0, 96, 64, 2000), (1, 160, 128, 12000), (2, 33, 47, 300)])
-@pytest.mark.parametrize("variant", ["plain", "local"])
+@pytest.mark.parametrize("variant", ["plain", "local", "local_q8"])
 def test_render_backward_parity(seed, W, H, n, variant):
     cam, cen, con, op, col, dep = render_only_case(100 + seed, W, H, n, sigma=(0.4, 10.0))
     vis, rect = O.footprint(W, H, cen, con, op)
@@ -145,7 +145,7 @@ def test_autograd_vs_oracle_and_fd_small(degree):
     _scene_grad_check(sc, fd_params=60, seed=degree)
 
 
-@pytest.mark.parametrize("variant", ["plain", "local"])
+@pytest.mark.parametrize("variant", ["plain", "local", "local_q8"])
 def test_autograd_vs_oracle_medium(variant):
     sc = scenes.make_config(4, n=100000)
     sc.cameras = [scenes.look_at_camera((0, 0, 0), (0, 0, 1), 480, 270)]
