@@ -322,30 +322,42 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__re
                                                             uint32_t *__restrict__ hist, int64_t stride)
 {
     constexpr int kTileN = kBlock * ITEMS;
+    constexpr int kV = ITEMS / 4;                              // 16-byte loads per thread and block
     __shared__ uint32_t s_h[kWaves][kRadixBins];
     const int wid = threadIdx.x >> 6, lane = __lane_id();
     const int64_t n = live_count(n_max, n_dev);
+    const int64_t g0 = (int64_t)blockIdx.x * kHistGroup * kTileN;
+    // the keys of block j + 1 are in flight while block j is counted
+    auto load = [&](int j, uint4 *v) {
+        const int64_t start = g0 + (int64_t)j * kTileN;
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + start);
+        const bool full = start + kTileN <= n && ((reinterpret_cast<uintptr_t>(keys + start) & 15) == 0);
+#pragma unroll
+        for (int r = 0; r < kV; ++r) v[r] = full ? k4[r * kBlock + threadIdx.x] : make_uint4(0u, 0u, 0u, 0u);
+    };
+    uint4 cur[kV], nxt[kV];
+    load(0, cur);
     uint32_t c[kHistGroup];
 #pragma unroll
     for (int j = 0; j < kHistGroup; ++j) {
+        if (j + 1 < kHistGroup) load(j + 1, nxt);
 #pragma unroll
         for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
         __syncthreads();
-        const int64_t start = ((int64_t)blockIdx.x * kHistGroup + j) * kTileN;
+        const int64_t start = g0 + (int64_t)j * kTileN;
         if (start < n) {
             const int cnt = (int)min((int64_t)kTileN, n - start);
-            const uint32_t *k4 = keys + start;
-            if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(k4) & 15) == 0)) {
+            if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(keys + start) & 15) == 0)) {
 #pragma unroll
-                for (int r = 0; r < ITEMS / 4; ++r) {
-                    const uint4 v = reinterpret_cast<const uint4 *>(k4)[r * kBlock + threadIdx.x];
-                    atomicAdd(&s_h[wid][(v.x >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(v.y >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(v.z >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(v.w >> shift) & mask], 1u);
+                for (int r = 0; r < kV; ++r) {
+                    atomicAdd(&s_h[wid][(cur[r].x >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(cur[r].y >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(cur[r].z >> shift) & mask], 1u);
+                    atomicAdd(&s_h[wid][(cur[r].w >> shift) & mask], 1u);
                 }
             } else {
-                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(k4[e] >> shift) & mask], 1u);
+                const uint32_t *kp = keys + start;
+                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(kp[e] >> shift) & mask], 1u);
             }
         }
         __syncthreads();
@@ -353,6 +365,8 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__re
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) c[j] += s_h[w][threadIdx.x];
         __syncthreads();                                       // before the next block re-zeroes
+#pragma unroll
+        for (int r = 0; r < kV; ++r) cur[r] = nxt[r];
     }
     *reinterpret_cast<uint4 *>(hist + (int64_t)threadIdx.x * stride + (int64_t)blockIdx.x * kHistGroup) =
         make_uint4(c[0], c[1], c[2], c[3]);
