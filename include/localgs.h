@@ -125,10 +125,13 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * per touched tile and a stable sort so that each tile's pairs are in
  * ascending (depth, id) order (Sec. II-A: prefix scan, key duplication,
  * radix sort).  Implemented as a stable radix sort of all n depth keys
- * (culled ones hold +inf and sort last), a scan of their tile counts in that
- * order, duplication in depth order and a stable radix sort on the tile id
- * alone; the result equals a stable sort of 64-bit (tile << 32 | depth bits)
- * keys emitted in id order.
+ * (culled ones hold +inf and sort last) and a scan of their tile counts in
+ * that order; then, for grids at most 256 tiles wide, a column pass that
+ * generates the pairs from the rectangles straight into tile-column order
+ * (depth order kept within a column) and a stable radix sort on the tile row,
+ * or, for wider grids, duplication in depth order and a stable radix sort on
+ * the tile id.  Either way the result equals a stable sort of 64-bit
+ * (tile << 32 | depth bits) keys emitted in id order.
  *
  * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
  * Outputs (device):
@@ -225,6 +228,7 @@ lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_deg
  * Each *_batch call with num_views = 1 is exactly its single-view form.
  */
 #define LGS_MAX_VIEWS 16
+#define LGS_QUEUE_WORDS 256   /* size of the persistent render's counter block */
 
 /* lgs_project for num_views cameras; the raw parameters are read once.
  * Outputs [num_views * n, ...], view-major. */
@@ -245,12 +249,12 @@ lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32
 
 /* lgs_render over the global tiles of num_views cameras (ranges [total,2]
  * from lgs_tile_ranges with num_tiles = total tiles).
- * queue: NULL for one workgroup per tile; else a device uint32 work counter
- *   (cleared by the call itself) that turns the culling variants
- *   (HOIST_CULL, LOCAL) into a persistent kernel of blocks_per_cu workgroups
- *   per compute unit (<= 0: 8) whose wavefronts take 16x4 strips from the
- *   counter until none is left.  Other variants ignore it.  Concurrent calls
- *   must not share a queue.
+ * queue: NULL for one workgroup per tile; else LGS_QUEUE_WORDS device
+ *   uint32 words of work counters (cleared by the call itself) that turn the
+ *   culling variants (HOIST_CULL, LOCAL) into a persistent kernel of
+ *   blocks_per_cu workgroups per compute unit (<= 0: 8) whose wavefronts
+ *   take wavefront sub-tiles from the counters until none is left.  Other
+ *   variants ignore it.  Concurrent calls must not share a queue.
  * tile_order: NULL to hand out tiles in index order, else a device
  *   permutation [total tiles] (e.g. from lgs_tile_order) giving the tile of
  *   each queue position.  Outputs do not depend on the order. */

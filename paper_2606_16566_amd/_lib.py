@@ -27,6 +27,7 @@ RENDER_Q8 = 0x20
 RENDER_VOTE4 = 0x40
 
 MAX_VIEWS = 16
+QUEUE_WORDS = 256
 
 EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort",
            "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_loss",

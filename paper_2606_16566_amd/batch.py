@@ -77,7 +77,7 @@ class ViewBatch:
         self.num_pairs = z(1, dtype=torch.int64)
         self.overflow = z(1, dtype=i32)
         self.ranges = z(self.num_tiles, 2, dtype=i32)
-        self.queue = z(1, dtype=i32)
+        self.queue = z(L.QUEUE_WORDS, dtype=i32)
         self.order = z(self.num_tiles, dtype=i32)
         self.order_ws = torch.empty(L.lib().lgs_tile_order_workspace_size(self.num_tiles) + 256, dtype=torch.uint8,
                                     device=dev)

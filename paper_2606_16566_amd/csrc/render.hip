@@ -262,9 +262,14 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
 }
 
 // Grid mode: workgroup = tile, wavefront = strip.  Persistent mode
-// (args.queue != null): every wavefront pops (tile, strip) units from the
+// (args.queue != null): every wavefront pops (tile, strip) units from a
 // device counter until all 4 * num_tiles units are taken, so no wavefront
-// waits for the others of its workgroup and the tail is balanced.
+// waits for the others of its workgroup and the tail is balanced.  There is
+// one counter per XCD (workgroups are dispatched round-robin over the 8
+// XCDs, so workgroup b draws from counter b % 8, each on its own cache
+// line): counter x hands out the four strips of queue positions x, x + 8,
+// x + 16, ..., which spreads the atomics over eight addresses and keeps the
+// strips of one tile within one XCD's L2.
 template <bool UNIFORM, typename R, bool STATS, bool Q8, int VP>
 __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
 {
@@ -277,11 +282,15 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
         render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
     } else {
         const uint32_t units = 4u * (uint32_t)args.num_tiles;
+        const uint32_t x = blockIdx.x & (kQueues - 1);
+        uint32_t *counter = args.queue + x * kQueueStride;
         for (;;) {
-            uint32_t u = 0;
-            if (__lane_id() == 0) u = atomicAdd(args.queue, 1u);
-            u = __builtin_amdgcn_readfirstlane(u);
-            if (u >= units) break;
+            uint32_t j = 0;
+            if (__lane_id() == 0) j = atomicAdd(counter, 1u);
+            j = __builtin_amdgcn_readfirstlane(j);
+            const uint64_t u64 = (uint64_t)(j >> 2) * (4u * kQueues) + 4u * x + (j & 3u);
+            if (u64 >= units) break;
+            const uint32_t u = (uint32_t)u64;
             const int tile = args.order ? (int)args.order[u >> 2] : (int)(u >> 2);
             const TileCtx<R> tc(args, tile, (int)(u & 3u), Q8);
             render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
@@ -373,11 +382,13 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
     unsigned grid = (unsigned)a.num_tiles;
     if (persistent) {
-        fill_async<uint32_t>(queue, 0u, 1, s);
+        static_assert(kQueues * kQueueStride == LGS_QUEUE_WORDS, "queue block size");
+        fill_async<uint32_t>(queue, 0u, kQueues * kQueueStride, s);
         a.queue = queue;
         a.order = tile_order;
         const int per = blocks_per_cu > 0 ? blocks_per_cu : 8;
-        grid = (unsigned)(device_cus() * per);
+        // a multiple of kQueues, so that every counter has workgroups taking from it
+        grid = (unsigned)((device_cus() * per + kQueues - 1) / kQueues * kQueues);
     }
     const bool st = stats != nullptr;
     if (fp32) {

@@ -25,6 +25,10 @@ struct ViewTable {
     float bg[kMaxViews][3];
 };
 
+// persistent mode: one work counter per XCD, each on its own 128-byte line
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;                 // uint32 words between counters
+
 struct RenderArgs {
     const uint2 *ranges;
     const uint32_t *values;
@@ -35,7 +39,7 @@ struct RenderArgs {
     float *out_T;
     int32_t *out_nc;
     unsigned long long *stats;
-    uint32_t *queue;            // persistent mode: work counter (zeroed before launch), else null
+    uint32_t *queue;            // persistent mode: kQueues counters (zeroed before launch), else null
     const uint32_t *order;      // persistent mode: tile of each queue position, or null for index order
     int num_tiles;              // all views
     ViewTable vt;

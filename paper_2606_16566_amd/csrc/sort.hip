@@ -209,6 +209,7 @@ struct TileGrids {
     int V;
     int tile_off[kMaxViews];
     int tiles_x[kMaxViews];
+    int row_off[kMaxViews];     // first global tile row of each view (rows of all views stacked)
 };
 
 __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__restrict__ order,
@@ -415,7 +416,41 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
 // leaves room for more resident workgroups.  vals_in == nullptr means the
 // values are the element indices.  With gather_dst set, the 16-byte record
 // gather_src[value] of every element is also written to its sorted place.
-template <int ITEMS, int NT>
+// Keys of the column-first binning (below) are (global tile row << 8) |
+// tile column; the last pass over them writes tile ids instead.  For view v,
+// whose rows start at global row row_off[v], the tile id of global row g and
+// column c is base[v] + g * tiles_x[v] + c with base[v] = tile_off[v] -
+// row_off[v] * tiles_x[v].  V == 0: keys pass through unchanged (the
+// scatter without the mapping is a separate instantiation).
+struct RowMap {
+    int V;
+    int row_off[kMaxViews];
+    int base[kMaxViews];
+    int tiles_x[kMaxViews];
+    // copy of the tables in LDS (s[0..3 * kMaxViews)), by one thread
+    __device__ __forceinline__ void stage(int *s) const
+    {
+#pragma unroll
+        for (int v = 0; v < kMaxViews; ++v) {
+            s[v] = row_off[v];
+            s[kMaxViews + v] = base[v];
+            s[2 * kMaxViews + v] = tiles_x[v];
+        }
+    }
+    // tile id of a key; the view by binary search over the staged row offsets
+    __device__ __forceinline__ uint32_t tile_of(uint32_t key, const int *s) const
+    {
+        const uint32_t g = key >> 8, c = key & 255u;
+        if (V == 1) return g * (uint32_t)tiles_x[0] + c;
+        int v = 0;
+#pragma unroll
+        for (int step = kMaxViews / 2; step > 0; step >>= 1)
+            if (v + step < V && (int)g >= s[v + step]) v += step;
+        return (uint32_t)s[kMaxViews + v] + g * (uint32_t)s[2 * kMaxViews + v] + c;
+    }
+};
+
+template <int ITEMS, int NT, bool MAP>
 __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
                                                            const uint32_t *__restrict__ vals_in,
                                                            uint32_t *__restrict__ keys_out,
@@ -424,7 +459,7 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
                                                            const uint32_t *__restrict__ hist_scan,
                                                            const uint32_t *__restrict__ digit_total,
                                                            int64_t stride, const int4 *__restrict__ gather_src,
-                                                           int4 *__restrict__ gather_dst)
+                                                           int4 *__restrict__ gather_dst, RowMap rows)
 {
     constexpr int kW = NT / 64;                             // wavefronts per workgroup
     constexpr int kTileN = NT * ITEMS;
@@ -436,6 +471,7 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
     __shared__ uint32_t s_buf[kTileN];                     // keys, then values, in digit order
     __shared__ uint8_t s_dig[kTileN];                      // digit of each slot of s_buf
     __shared__ uint32_t s_tot[kW];
+    __shared__ int s_map[MAP ? 3 * kMaxViews : 1];
     const int64_t n = live_count(n_max, n_dev);
     const int64_t start = (int64_t)blockIdx.x * kTileN;
     if (start >= n) return;                                  // uniform across the block
@@ -443,6 +479,9 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int t = threadIdx.x;                               // digit of the per-digit phases (t < 256)
     const uint64_t lt = lanemask_lt();
+    if constexpr (MAP) {
+        if (t == 0) rows.stage(s_map);                       // read after the barriers below
+    }
 #pragma unroll
     for (int k = 0; k < kRadixBins / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
     {
@@ -514,7 +553,8 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
         const int i = threadIdx.x + r * NT;
         if (i < count) {
             const uint32_t d = s_dig[i];
-            keys_out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = s_buf[i];
+            const uint32_t k = s_buf[i];
+            keys_out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = MAP ? rows.tile_of(k, s_map) : k;
         }
     }
     __syncthreads();
@@ -539,10 +579,254 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
 }
 
 // ---------------------------------------------------------------------------
+// Column-first binning (views at most 256 tiles wide).  Tile ids are ordered
+// by (view, tile row, tile column), so a stable pass by tile column followed
+// by a stable sort by global tile row (the rows of all views stacked) leaves
+// every tile's pairs in depth order.  The column pass needs no pair list in
+// memory: the pairs a block of Gaussians puts into column c number the sum
+// of the row spans of its rectangles that cover c (a difference array over
+// the columns), and the pairs themselves are generated from the rectangles
+// while they are placed.  This replaces the duplication and the first radix
+// pass over the pairs.  Keys in between: (global row << 8) | column.
+// ---------------------------------------------------------------------------
+constexpr int kColBits = 8;
+constexpr int kMaxCols = 1 << kColBits;            // tiles per view row
+constexpr int kColBlock = 512;                     // Gaussians per column block (= scatter threads)
+constexpr int kColItems = 4;                       // pairs per thread and chunk
+static_assert(kMaxCols == kRadixBins && kMaxCols == kBlock, "one column per digit and per thread");
+
+// rectangle columns clamped to [0, kMaxCols] (a no-op for projected
+// rectangles, which lie inside their view's grid)
+__device__ __forceinline__ int4 col_rect(int4 q)
+{
+    q.x = min(max(q.x, 0), kMaxCols);
+    q.z = min(max(q.z, q.x), kMaxCols);
+    return q;
+}
+
+// Per-block column counts: hist[c * stride + b] = pairs of column c among the
+// Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order.  One
+// workgroup counts kHistGroup consecutive blocks (one 16-byte write per
+// column).
+__global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict__ rect, int64_t n, int ncols,
+                                                          uint32_t *__restrict__ hist, int64_t stride)
+{
+    __shared__ uint32_t s_d[kMaxCols + 1];
+    __shared__ uint32_t s_warp[kWaves];
+    const int t = threadIdx.x;
+    uint32_t c[kHistGroup];
+#pragma unroll
+    for (int j = 0; j < kHistGroup; ++j) {
+        s_d[t] = 0u;
+        if (t == 0) s_d[kMaxCols] = 0u;
+        __syncthreads();
+        const int64_t r0 = ((int64_t)blockIdx.x * kHistGroup + j) * kColBlock;
+#pragma unroll
+        for (int i = 0; i < kColBlock / kBlock; ++i) {
+            const int64_t r = r0 + i * kBlock + t;
+            if (r < n) {
+                const int4 q = col_rect(rect[r]);
+                if (q.z > q.x && q.w > q.y) {
+                    const uint32_t h = (uint32_t)(q.w - q.y);
+                    atomicAdd(&s_d[q.x], h);
+                    atomicAdd(&s_d[q.z], 0u - h);
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t tot;
+        const uint32_t d = s_d[t];
+        c[j] = block_exclusive_scan<uint32_t, kWaves>(d, tot, s_warp) + d;
+    }
+    if (t < ncols)
+        *reinterpret_cast<uint4 *>(hist + (int64_t)t * stride + (int64_t)blockIdx.x * kHistGroup) =
+            make_uint4(c[0], c[1], c[2], c[3]);
+}
+
+// Generation and column placement of the pairs of one block of kColBlock
+// Gaussians, in chunks of kColBlock * ITEMS pairs.  Per chunk: every thread
+// generates ITEMS consecutive pairs of the block's depth-ordered, row-major
+// enumeration (one binary search over the block's pair offsets, then
+// stepping through the rectangle) into LDS; the wavefronts rank them by
+// column in that enumeration order (so a column keeps depth order, and row
+// order within a Gaussian); the chunk is then ordered by column in LDS (key
+// and owning Gaussian) and each column run is written to its place: the
+// column's global start plus the column's pairs in earlier blocks and in
+// earlier chunks of this one.  Only the pairs at r-major positions below the
+// capacity are generated, and only places below it are written.
+template <int ITEMS>
+__global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
+    const uint32_t *__restrict__ order, const int4 *__restrict__ rect, const uint32_t *__restrict__ off,
+    const uint64_t *p_total, uint64_t cap, TileGrids tg, int64_t n, const uint32_t *__restrict__ hist_scan,
+    const uint32_t *__restrict__ col_total, int64_t stride, int ncols, int nbits, uint32_t *__restrict__ keys_out,
+    uint32_t *__restrict__ vals_out)
+{
+    constexpr int NT = kColBlock;
+    constexpr int kW = NT / 64;
+    constexpr int kTileN = NT * ITEMS;
+    constexpr int kPerWave = kTileN / kW;
+    static_assert(ITEMS % 4 == 0, "16-byte staging writes");
+    __shared__ uint32_t s_xw[NT];                          // first column | width << 16
+    __shared__ uint32_t s_id[NT];
+    __shared__ uint32_t s_row[NT];                         // global tile row of the rectangle's first row
+    __shared__ uint32_t s_off[NT + 1];                     // block-local r-major pair offsets
+    __shared__ uint32_t s_gb[2][kMaxCols];                 // per chunk parity: global place of its column runs
+    __shared__ uint32_t s_wc[kW][kMaxCols];
+    __shared__ uint32_t s_lbase[kMaxCols];
+    __shared__ __align__(16) uint32_t s_buf[kTileN];       // generated keys, then keys by column
+    __shared__ __align__(16) uint16_t s_own[kTileN];       // block-local Gaussian of each generated pair
+    __shared__ uint16_t s_osort[kTileN];                   // the same, by column
+    __shared__ uint32_t s_tot[kW];
+    const int64_t first = (int64_t)blockIdx.x * NT;
+    if (first >= n) return;
+    const int cnt = (int)min((int64_t)NT, n - first);
+    const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
+    const uint64_t lt = lanemask_lt();
+    const uint32_t dmask = (1u << nbits) - 1u;              // columns < 2^nbits
+    const uint64_t total = *p_total;
+    const uint32_t lim = (uint32_t)(total < cap ? total : cap);
+    const uint32_t base = off[first];
+    if (t < cnt) {
+        const uint32_t g = order[first + t];
+        const int v = tg.V > 1 ? (int)(g / tg.per_view) : 0;
+        const int4 q = col_rect(rect[first + t]);
+        s_xw[t] = (uint32_t)q.x | ((uint32_t)(q.z - q.x) << 16);
+        s_id[t] = g;
+        s_row[t] = (uint32_t)(tg.row_off[v] + q.y);
+        s_off[t] = off[first + t] - base;
+    }
+    if (t == 0) s_off[cnt] = (first + cnt < n ? off[first + cnt] : lim) - base;
+    {
+        // global start of column t (exclusive scan of the column totals) plus
+        // the column's pairs in earlier blocks
+        const uint32_t tot = t < ncols ? col_total[t] : 0u;
+        uint32_t all;
+        const uint32_t before = block_exclusive_scan<uint32_t, kW>(tot, all, s_tot);
+        if (t < kMaxCols) s_gb[0][t] = before + (t < ncols ? hist_scan[(int64_t)t * stride + blockIdx.x] : 0u);
+    }
+    __syncthreads();
+    const uint32_t m = s_off[cnt];                          // pairs of this block
+    int par = 0;
+    for (uint32_t q0 = 0; q0 < m; q0 += kTileN, par ^= 1) {
+        const int count = (int)min((uint32_t)kTileN, m - q0);
+        // 1. generate ITEMS consecutive pairs per thread (blocked layout)
+        {
+            const uint32_t p0 = q0 + (uint32_t)t * ITEMS;
+            uint32_t kk[ITEMS], ow[ITEMS];
+#pragma unroll
+            for (int e = 0; e < ITEMS; ++e) { kk[e] = 0u; ow[e] = 0u; }
+            if (p0 < m) {
+                int lo = 0, hi = cnt - 1;                   // last k with s_off[k] <= p0
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[mid] <= p0) lo = mid; else hi = mid - 1;
+                }
+                int k = lo;
+                uint32_t nx = s_off[k + 1];                 // end of Gaussian k's pairs
+                uint32_t xw = s_xw[k], row = s_row[k];
+                uint32_t w = xw >> 16;
+                const uint32_t i = p0 - s_off[k];
+                uint32_t ty = w ? i / w : 0u, tx = i - ty * w;
+#pragma unroll
+                for (int e = 0; e < ITEMS; ++e) {
+                    const uint32_t p = p0 + e;
+                    if (p < m) {
+                        while (p >= nx) {                   // next Gaussian that has pairs
+                            ++k;
+                            nx = s_off[k + 1];
+                            xw = s_xw[k];
+                            row = s_row[k];
+                            w = xw >> 16;
+                            tx = 0;
+                            ty = 0;
+                        }
+                        kk[e] = ((row + ty) << kColBits) | ((xw & 0xFFFFu) + tx);
+                        ow[e] = (uint32_t)k;
+                        if (++tx == w) { tx = 0; ++ty; }
+                    }
+                }
+            }
+            uint4 *b4 = reinterpret_cast<uint4 *>(s_buf + t * ITEMS);
+#pragma unroll
+            for (int e = 0; e < ITEMS; e += 4) b4[e / 4] = make_uint4(kk[e], kk[e + 1], kk[e + 2], kk[e + 3]);
+            uint2 *o2 = reinterpret_cast<uint2 *>(s_own + t * ITEMS);
+#pragma unroll
+            for (int e = 0; e < ITEMS; e += 4)
+                o2[e / 4] = make_uint2(ow[e] | (ow[e + 1] << 16), ow[e + 2] | (ow[e + 3] << 16));
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxCols / 64; ++k) s_wc[wid][lane + 64 * k] = 0u;
+        __syncthreads();
+        // 2. rank by column, rounds of 64 consecutive pairs per wavefront
+        uint32_t key[ITEMS], lp[ITEMS];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) key[r] = s_buf[wid * kPerWave + r * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int local = wid * kPerWave + r * 64 + lane;
+            const bool active = local < count;
+            const uint32_t d = key[r] & dmask;
+            const uint64_t match = digit_match(active, d, nbits);
+            const uint32_t before = active ? s_wc[wid][d] : 0u;
+            const uint32_t within = (uint32_t)__popcll(match & lt);
+            lp[r] = before + within;
+            if (active && within == 0) s_wc[wid][d] = before + (uint32_t)__popcll(match);
+            wave_sync_lds();
+        }
+        __syncthreads();
+        // 3. per column: prefix over wavefronts, chunk offsets, next chunk's bases
+        {
+            uint32_t ccount = 0;
+            if (t < kMaxCols) {
+#pragma unroll
+                for (int w = 0; w < kW; ++w) {
+                    const uint32_t c = s_wc[w][t];
+                    s_wc[w][t] = ccount;
+                    ccount += c;
+                }
+                s_gb[par ^ 1][t] = s_gb[par][t] + ccount;
+            }
+            uint32_t tot;
+            const uint32_t ex = block_exclusive_scan<uint32_t, kW>(ccount, tot, s_tot);
+            if (t < kMaxCols) s_lbase[t] = ex;
+        }
+        __syncthreads();
+        // 4. order the chunk by column in LDS
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int local = wid * kPerWave + r * 64 + lane;
+            if (local < count) {
+                const uint32_t d = key[r] & dmask;
+                const uint32_t at = lp[r] + s_lbase[d] + s_wc[wid][d];
+                s_buf[at] = key[r];
+                s_osort[at] = s_own[local];
+            }
+        }
+        __syncthreads();
+        // 5. write the column runs (consecutive lanes, consecutive places)
+        const uint32_t *gb = s_gb[par];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int i = t + r * NT;
+            if (i < count) {
+                const uint32_t k = s_buf[i];
+                const uint32_t d = k & dmask;
+                const uint32_t pos = gb[d] + (uint32_t)i - s_lbase[d];
+                if (pos < cap) {
+                    keys_out[pos] = k;
+                    vals_out[pos] = s_id[s_osort[i]];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // tile ranges: 4 sorted keys per lane, vector loads
 // ---------------------------------------------------------------------------
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *num_pairs, const int32_t *overflow,
-                              int64_t cap, uint2 *__restrict__ ranges)
+                              int64_t cap, uint32_t num_tiles, uint2 *__restrict__ ranges)
 {
     if (overflow && *overflow) return;
     int64_t n = *num_pairs;
@@ -561,7 +845,7 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t i = i0 + e;
-            if (i < n) {
+            if (i < n && k[e] < num_tiles) {                  // keys of valid input always are
                 if (prev != k[e]) ranges[k[e]].x = (uint32_t)i;
                 if (i + 1 >= n || k[e + 1] != k[e]) ranges[k[e]].y = (uint32_t)(i + 1);
             }
@@ -625,7 +909,10 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     }
     w.pk = (uint32_t *)take(sizeof(uint32_t) * (cap > 0 ? cap : 1));
     w.pv = (uint32_t *)take(sizeof(uint32_t) * (cap > 0 ? cap : 1));
-    const int64_t nbmax = hist_stride(radix_blocks(n > cap ? n : cap) + 1);
+    // per-block counts of the radix passes and of the column pass
+    const int64_t nb_radix = hist_stride(radix_blocks(n > cap ? n : cap) + 1);
+    const int64_t nb_col = hist_stride((nm + kColBlock - 1) / kColBlock + 1);
+    const int64_t nbmax = nb_radix > nb_col ? nb_radix : nb_col;
     w.hist = (uint32_t *)take(sizeof(uint32_t) * kRadixBins * nbmax);
     w.digit_total = (uint32_t *)take(sizeof(uint32_t) * kRadixBins);
     w.pair_off = (uint32_t *)take(sizeof(uint32_t) * nm);
@@ -642,7 +929,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 template <int ITEMS, int SCATTER_THREADS>
 void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                  const int4 *gather_src, int4 *gather_dst)
+                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows)
 {
     constexpr int kTileN = kBlock * ITEMS;
     const int64_t nb = (n_max + kTileN - 1) / kTileN;
@@ -654,23 +941,29 @@ void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint
     hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
                        kTileN, w.digit_total);
     constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
-    hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS>), dim3((unsigned)nb),
-                       dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
-                       n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
-                       stride, gather_src, gather_dst);
+    if (rows.V)
+        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true>), dim3((unsigned)nb),
+                           dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
+                           n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
+                           stride, gather_src, gather_dst, rows);
+    else
+        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false>), dim3((unsigned)nb),
+                           dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
+                           n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
+                           stride, gather_src, gather_dst, rows);
 }
 
 void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                const int4 *gather_src = nullptr, int4 *gather_dst = nullptr)
+                const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{})
 {
     if (n_max >= kLargeRadixFrom)
-        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
+        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows);
     else if (n_max >= kMidRadixFrom)
-        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst);
+        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows);
     else
         radix_pass_t<kRadixItems, kBlock>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                          gather_dst);
+                                          gather_dst, rows);
 }
 
 
@@ -699,12 +992,21 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     TileGrids tg{};
     tg.per_view = (uint32_t)(n_per_view > 0 ? n_per_view : 1);
     tg.V = num_views;
-    int64_t total_tiles = 0;
+    int64_t total_tiles = 0, total_rows = 0;
+    int ncols = 0;
+    RowMap rows{};
+    rows.V = num_views;
     for (int v = 0; v < num_views; ++v) {
         LGS_REQUIRE(tiles_x[v] > 0 && tiles_y[v] > 0, "lgs_sort: bad tile grid of view %d", v);
         tg.tile_off[v] = (int)total_tiles;
         tg.tiles_x[v] = tiles_x[v];
+        tg.row_off[v] = (int)total_rows;
+        rows.row_off[v] = (int)total_rows;
+        rows.tiles_x[v] = tiles_x[v];
+        rows.base[v] = (int)(total_tiles - total_rows * tiles_x[v]);
         total_tiles += (int64_t)tiles_x[v] * tiles_y[v];
+        total_rows += tiles_y[v];
+        ncols = tiles_x[v] > ncols ? tiles_x[v] : ncols;
         LGS_REQUIRE(total_tiles < (1ll << 31), "lgs_sort: too many tiles");
     }
     LGS_REQUIRE(capacity_pairs >= 0 && capacity_pairs < (int64_t)UINT32_MAX, "lgs_sort: capacity out of range");
@@ -737,8 +1039,12 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     // 2. pair counts in depth order, their exclusive scan (total P) and the
     //    overflow check.  The number of tile-sort passes decides which buffer
     //    receives the pairs so that the sorted result ends in the caller's.
+    //    Column-first binning (views up to kMaxCols tiles wide) sorts by the
+    //    global tile row after its column pass; otherwise the pairs are
+    //    duplicated and sorted by tile id.
+    const bool by_column = ncols <= kMaxCols;
     int bits = 1;
-    while ((1ll << bits) < total_tiles) ++bits;
+    while ((1ll << bits) < (by_column ? total_rows : total_tiles)) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint32_t *k0 = (passes & 1) ? w.pk : tile_keys, *v0 = (passes & 1) ? w.pv : values;
     uint32_t *k1 = (passes & 1) ? tile_keys : w.pk, *v1 = (passes & 1) ? values : w.pv;
@@ -752,18 +1058,40 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         hipLaunchKernelGGL((scan_final_kernel<uint64_t, U32Load, OffsetStore>), dim3((unsigned)nb), dim3(kBlock), 0, s,
                            U32Load{w.pair_off}, OffsetStore{w.pair_off, (uint64_t)capacity_pairs}, n,
                            (const uint32_t *)nullptr, (const uint64_t *)w.partials);
-    // 3. duplication in depth order
-    if (n > 0)
+    if (by_column) {
+        // 3. column pass: per-block column counts, their scan per column, and
+        //    generation + placement of the pairs
+        const int64_t nbc = (n + kColBlock - 1) / kColBlock;
+        const int64_t stride = hist_stride(nbc);
+        int cbits = 1;
+        while ((1 << cbits) < ncols) ++cbits;
+        if (n > 0) {
+            hipLaunchKernelGGL(col_hist_kernel, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s,
+                               (const int4 *)w.rect_sorted, n, ncols, w.hist, stride);
+            hipLaunchKernelGGL(radix_rowscan_kernel, dim3(ncols), dim3(kBlock), 0, s, w.hist, stride, n,
+                               (const uint32_t *)nullptr, kColBlock, w.digit_total);
+            hipLaunchKernelGGL(col_scatter_kernel<kColItems>, dim3((unsigned)nbc), dim3(kColBlock), 0, s, order,
+                               (const int4 *)w.rect_sorted, (const uint32_t *)w.pair_off,
+                               (const uint64_t *)w.p_total, (uint64_t)capacity_pairs, tg, n,
+                               (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
+                               k0, v0);
+        }
+    } else if (n > 0) {
+        // 3. duplication in depth order
         hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order,
                            (const int4 *)w.rect_sorted,
                            (const uint32_t *)w.pair_off, (const uint64_t *)w.p_total, (uint64_t)capacity_pairs,
                            tg, n, k0, v0);
-    // 4. stable sort of the pairs by tile id, the key bits split evenly over
-    //    the passes (longer digit runs per block than 8 + remainder)
+    }
+    // 4. stable sort of the pairs by global tile row (above the column bits,
+    //    the last pass writing tile ids) or by tile id, the key bits split
+    //    evenly over the passes (longer digit runs per block than 8 + remainder)
+    const int base_shift = by_column ? kColBits : 0;
     for (int pass = 0, shift = 0; pass < passes; ++pass) {
         const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
-        if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, shift, b, w, s);
-        else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, shift, b, w, s);
+        const RowMap map = by_column && pass == passes - 1 ? rows : RowMap{};
+        if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
+        else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
         shift += b;
     }
     LGS_LAUNCHED("lgs_sort");
@@ -790,7 +1118,7 @@ extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *
         unsigned g = grid_for(capacity_pairs, 256 * 4);
         if (g > 4096) g = 4096;
         hipLaunchKernelGGL(ranges_kernel, dim3(g), dim3(256), 0, s, tile_keys, num_pairs, overflow, capacity_pairs,
-                           reinterpret_cast<uint2 *>(ranges));
+                           (uint32_t)num_tiles, reinterpret_cast<uint2 *>(ranges));
     }
     LGS_LAUNCHED("lgs_tile_ranges");
     return LGS_OK;

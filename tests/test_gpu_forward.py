@@ -63,27 +63,35 @@ def test_project_parity(cfg, n, view):
 # ---------------------------------------------------------------------------
 # binning
 # ---------------------------------------------------------------------------
-def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True):
+def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True, wide=False):
     rng = np.random.default_rng(seed)
     vis = rng.uniform(size=n) < 0.85
     depth = (rng.choice(np.float32([1.5, 2.0, 2.25, 3.0]), n) if ties
              else rng.uniform(0.5, 20, n).astype(np.float32))
     x0 = rng.integers(0, tiles_x, n); y0 = rng.integers(0, tiles_y, n)
-    w = rng.integers(1, 6, n); h = rng.integers(1, 5, n)
+    if wide:                      # splats spanning up to the whole grid width
+        w = rng.integers(1, tiles_x + 1, n); h = rng.integers(1, 12, n)
+        x0 = np.where(rng.uniform(size=n) < 0.3, 0, x0)
+    else:
+        w = rng.integers(1, 6, n); h = rng.integers(1, 5, n)
     rect = np.stack([x0, y0, np.minimum(x0 + w, tiles_x), np.minimum(y0 + h, tiles_y)], 1).astype(np.int32)
     rect[~vis] = 0
     depth = np.where(vis, depth, np.float32(np.inf)).astype(np.float32)
     return vis.astype(np.int32), depth, rect
 
 
-@pytest.mark.parametrize("seed,n,tx,ty,ties", [(0, 5000, 13, 9, True), (1, 40000, 120, 68, False),
-                                              (2, 3, 1, 1, True), (3, 70000, 300, 260, True),
-                                              # above 2^22 and 2^25 pairs: the larger radix tiers
-                                              (4, 1000000, 120, 68, False), (5, 800000, 300, 260, True),
-                                              pytest.param(6, 6000000, 300, 260, False, marks=pytest.mark.slow)])
-def test_sort_and_ranges_parity(seed, n, tx, ty, ties):
-    vis, depth, rect = _synthetic_bins(seed, n, tx, ty, ties)
-    print(f"sort seed={seed} n={n} tiles={tx}x{ty}", flush=True)
+@pytest.mark.parametrize("seed,n,tx,ty,ties,wide", [
+    (0, 5000, 13, 9, True, False), (1, 40000, 120, 68, False, False), (2, 3, 1, 1, True, False),
+    # grids wider than 256 tiles take the duplicate-then-sort path
+    (3, 70000, 300, 260, True, False), (9, 3000, 257, 20, True, True),
+    # the widest grid of the column-first path, splats over many columns
+    (8, 3000, 256, 30, False, True), (10, 20000, 37, 200, True, True),
+    # above 2^22 and 2^25 pairs: the larger radix tiers
+    (4, 1000000, 120, 68, False, False), (5, 800000, 300, 260, True, False),
+    pytest.param(6, 6000000, 300, 260, False, False, marks=pytest.mark.slow)])
+def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
+    vis, depth, rect = _synthetic_bins(seed, n, tx, ty, ties, wide)
+    print(f"sort seed={seed} n={n} tiles={tx}x{ty} wide={wide}", flush=True)
     W, H = 16 * tx, 16 * ty
     cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), W, H)
     off, ids = O.tile_lists(vis, depth, rect, W, H)
