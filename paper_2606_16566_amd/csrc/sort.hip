@@ -295,14 +295,18 @@ __global__ __launch_bounds__(kBlock) void duplicate_kernel(const uint32_t *__res
 // scatter (each block derives its digit bases from the totals).
 // ---------------------------------------------------------------------------
 
-// lanes of this round of 64 whose digit equals this lane's (eight ballots)
+// active lanes of this round of 64 whose digit (nbits <= 8 bits) equals this
+// lane's: one ballot per digit bit (unrolled), each keeping the lanes whose
+// bit agrees with this lane's: match &= ~(ballot ^ (bit ? ~0 : 0))
 __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbits)
 {
     uint64_t match = __ballot(active);
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        match &= bit ? bb : ~bb;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        if (b >= nbits) break;
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);   // all ones iff the bit is set
+        const uint64_t bb = __ballot(m != 0u);
+        match &= ~(bb ^ (((uint64_t)m << 32) | m));
     }
     return match;
 }
