@@ -827,16 +827,28 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// tile ranges: 4 sorted keys per lane, vector loads
+// tile ranges: 4 sorted keys per lane, vector loads.  Every tile is written
+// once: a run's start and end at the key changes, and the tiles between two
+// runs (and before the first and after the last) as empty (0, 0), so no
+// clearing pass is needed.  With an overflow or no pairs all tiles are empty.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void zero_tiles(uint2 *ranges, uint32_t a, uint32_t b)
+{
+    for (uint32_t t = a; t < b; ++t) ranges[t] = make_uint2(0u, 0u);
+}
+
 __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *num_pairs, const int32_t *overflow,
                               int64_t cap, uint32_t num_tiles, uint2 *__restrict__ ranges)
 {
-    if (overflow && *overflow) return;
     int64_t n = *num_pairs;
     if (n > cap) n = cap;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((overflow && *overflow) || n <= 0) {
+        for (int64_t t = tid; t < num_tiles; t += (int64_t)gridDim.x * blockDim.x) ranges[t] = make_uint2(0u, 0u);
+        return;
+    }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-    for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < n; i0 += stride) {
+    for (int64_t i0 = tid * 4; i0 < n; i0 += stride) {
         uint32_t k[5];
         if (i0 + 3 < n && ((reinterpret_cast<uintptr_t>(keys + i0) & 15) == 0)) {
             const uint4 v = *reinterpret_cast<const uint4 *>(keys + i0);
@@ -850,8 +862,19 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ keys, const int64_t *
         for (int e = 0; e < 4; ++e) {
             const int64_t i = i0 + e;
             if (i < n && k[e] < num_tiles) {                  // keys of valid input always are
-                if (prev != k[e]) ranges[k[e]].x = (uint32_t)i;
-                if (i + 1 >= n || k[e + 1] != k[e]) ranges[k[e]].y = (uint32_t)(i + 1);
+                if (i == 0) {
+                    zero_tiles(ranges, 0u, k[e]);
+                    ranges[k[e]].x = 0u;
+                } else if (prev != k[e]) {
+                    ranges[k[e]].x = (uint32_t)i;
+                    if (prev < k[e]) zero_tiles(ranges, prev + 1u, k[e]);
+                }
+                if (i + 1 >= n) {
+                    ranges[k[e]].y = (uint32_t)n;
+                    zero_tiles(ranges, k[e] + 1u, num_tiles);
+                } else if (k[e + 1] != k[e]) {
+                    ranges[k[e]].y = (uint32_t)(i + 1);
+                }
             }
             prev = k[e];
         }
@@ -1117,13 +1140,11 @@ extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *
     LGS_REQUIRE(capacity_pairs >= 0 && (capacity_pairs == 0 || tile_keys), "lgs_tile_ranges: bad pair buffer");
     LGS_REQUIRE((uintptr_t)ranges % 8 == 0, "lgs_tile_ranges: ranges must be 8-byte aligned");
     hipStream_t s = as_stream(stream);
-    fill_async<uint64_t>(reinterpret_cast<uint64_t *>(ranges), 0ull, num_tiles, s);
-    if (capacity_pairs > 0) {
-        unsigned g = grid_for(capacity_pairs, 256 * 4);
-        if (g > 4096) g = 4096;
-        hipLaunchKernelGGL(ranges_kernel, dim3(g), dim3(256), 0, s, tile_keys, num_pairs, overflow, capacity_pairs,
-                           (uint32_t)num_tiles, reinterpret_cast<uint2 *>(ranges));
-    }
+    const int64_t work = capacity_pairs / 4 > num_tiles ? capacity_pairs / 4 : num_tiles;
+    unsigned g = grid_for(work, 256);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(ranges_kernel, dim3(g), dim3(256), 0, s, tile_keys, num_pairs, overflow, capacity_pairs,
+                       (uint32_t)num_tiles, reinterpret_cast<uint2 *>(ranges));
     LGS_LAUNCHED("lgs_tile_ranges");
     return LGS_OK;
 }

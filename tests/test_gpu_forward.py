@@ -111,6 +111,40 @@ def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
     assert np.all(rg[~nonempty] == 0)
 
 
+@pytest.mark.parametrize("case", ["gaps", "one", "none", "overflow", "first_last"])
+def test_tile_ranges_write_every_tile(case):
+    """lgs_tile_ranges over a buffer holding garbage: runs get [start, end),
+    every other tile (0, 0), with or without pairs, and on overflow."""
+    import ctypes as C
+    from paper_2606_16566_amd import _lib as L
+    rng = np.random.default_rng(3)
+    tiles = 700
+    if case == "gaps":
+        keys = np.sort(rng.choice(np.arange(3, 650), 5000))
+    elif case == "one":
+        keys = np.array([417])
+    elif case == "first_last":
+        keys = np.sort(np.concatenate([np.zeros(7, int), np.full(5, tiles - 1), rng.choice(tiles, 300)]))
+    else:
+        keys = np.sort(rng.choice(tiles, 900))
+    n = 0 if case == "none" else len(keys)
+    cap = max(len(keys), 1) - (1 if case == "overflow" else 0)
+    k_dev = to_dev(np.resize(keys.astype(np.uint32), max(cap, 1)).view(np.int32))
+    npairs = to_dev(np.array([n if case != "overflow" else len(keys)], np.int64))
+    ovf = to_dev(np.array([1 if case == "overflow" else 0], np.int32))
+    ranges = torch.full((tiles, 2), -1, dtype=torch.int32, device="cuda")
+    p = lambda t: C.c_void_p(t.data_ptr())
+    L.check(L.lib().lgs_tile_ranges(p(k_dev), p(npairs), p(ovf), cap, tiles, p(ranges),
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream)), "lgs_tile_ranges")
+    got = _sync_np(ranges).astype(np.int64)
+    want = np.zeros((tiles, 2), np.int64)
+    if case not in ("none", "overflow"):
+        for t in np.unique(keys):
+            idx = np.nonzero(keys == t)[0]
+            want[t] = (idx[0], idx[-1] + 1)
+    assert np.array_equal(got, want)
+
+
 def test_sort_overflow_flag_and_empty():
     vis, depth, rect = _synthetic_bins(7, 2000, 20, 10)
     cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), 320, 160)
