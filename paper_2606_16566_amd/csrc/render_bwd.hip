@@ -13,8 +13,9 @@
 //
 // The LOCAL variant reuses the forward's hoisting and wavefront culling: each
 // wavefront visits, in reverse, only the entries whose strip bit is set.  The
-// nine per-Gaussian partial gradients are summed over each 16-lane row with
-// DPP (no LDS traffic), the four row sums of all nine components are added to
+// nine per-Gaussian partial gradients are summed over each 16-lane row with a
+// DPP reduce-scatter (no LDS traffic; each of nine lanes of a row ends with
+// one component's sum), the four row sums of all nine components are added to
 // the workgroup's LDS accumulators with one 36-lane LDS atomic, and the
 // accumulators are flushed with one global atomic per (tile, Gaussian,
 // component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
@@ -44,15 +45,36 @@ __device__ __forceinline__ float dpp_read(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// sum over the 16 lanes of each row, left in every lane of the row (all 64
-// lanes must be active): quad butterflies, then half-row and row mirrors
-__device__ __forceinline__ float row_sum16(float v)
+// One reduce-scatter step over the lane pairs of a DPP permutation: of the
+// pair (x, y) the lane whose key bit is clear keeps x, the other keeps y, and
+// each adds its partner's copy of the kept value.
+template <int CTRL>
+__device__ __forceinline__ float rs_step(float x, float y, bool hi)
 {
-    v += dpp_read<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_read<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp_read<0x141>(v);   // row_half_mirror
-    v += dpp_read<0x140>(v);   // row_mirror
-    return v;
+    const float keep = hi ? y : x, send = hi ? x : y;
+    return keep + dpp_read<CTRL>(send);
+}
+
+// Row sums of nine values over the 16 lanes of each row (all 64 lanes
+// active), scattered: lane l of a row ends with the sum of component
+// (l >> 1) when l is even and of component 8 when l is odd.  Components
+// 0..7 halve over the row mirror (partner l ^ 15, key bit 3), the half-row
+// mirror (l ^ 7, bit 2) and the quad swaps l ^ 2 (bit 1) and l ^ 1 (bit 0,
+// paired with component 8, which is butterfly-summed until then): 27
+// instructions instead of four butterfly adds per component.
+__device__ __forceinline__ float row_sums9(const float *g)
+{
+    const int l = __lane_id() & 15;
+    const bool b3 = l & 8, b2 = l & 4, b1 = l & 2, b0 = l & 1;
+    float h[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = rs_step<0x140>(g[j], g[j + 4], b3);   // row_mirror
+    float g8 = g[8] + dpp_read<0x140>(g[8]);
+    const float k0 = rs_step<0x141>(h[0], h[2], b2), k1 = rs_step<0x141>(h[1], h[3], b2);   // row_half_mirror
+    g8 += dpp_read<0x141>(g8);
+    const float m = rs_step<0x4E>(k0, k1, b1);                              // quad_perm [2,3,0,1]
+    g8 += dpp_read<0x4E>(g8);
+    return rs_step<0xB1>(m, g8, b0);                                        // quad_perm [1,0,3,2]
 }
 
 // 1 / x for normal positive x (here 1 - alpha in [0.01, 1]): hardware
@@ -215,16 +237,13 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                     }
                 }
                 if (__ballot(act) != 0ull) {
-                    // row sums of the nine components; lane f of each row
-                    // (f < 9) adds component f
-                    const int lf = lane & 15;
-                    float mine = 0.f;
-#pragma unroll
-                    for (int f = 0; f < kNG; ++f) {
-                        const float r = row_sum16(g[f]);
-                        mine = lf == f ? r : mine;
-                    }
-                    if (lf < kNG && mine != 0.f) atomicAdd(&s_g[lf][k], mine);
+                    // row sums of the nine components: even lane 2f of each
+                    // row holds component f < 8, lane 1 component 8
+                    static_assert(kNG == 9, "row_sums9 handles nine components");
+                    const int l = lane & 15;
+                    const float mine = row_sums9(g);
+                    const int f = (l & 1) ? 8 : (l >> 1);
+                    if (((l & 1) == 0 || l == 1) && mine != 0.f) atomicAdd(&s_g[f][k], mine);
                 }
             }
         }
