@@ -609,15 +609,18 @@ __device__ __forceinline__ int4 col_rect(int4 q)
 }
 
 // Per-block column counts: hist[c * stride + b] = pairs of column c among the
-// Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order.  One
-// workgroup counts kHistGroup consecutive blocks (one 16-byte write per
-// column).
+// Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order, and the
+// block's pair total in block_pairs[b].  One workgroup counts kHistGroup
+// consecutive blocks (one 16-byte write per column).
 __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict__ rect, int64_t n, int ncols,
-                                                          uint32_t *__restrict__ hist, int64_t stride)
+                                                          uint32_t *__restrict__ hist, int64_t stride,
+                                                          uint64_t *__restrict__ block_pairs)
 {
     __shared__ uint32_t s_d[kMaxCols + 1];
     __shared__ uint32_t s_warp[kWaves];
+    __shared__ uint64_t s_pairs[kHistGroup];
     const int t = threadIdx.x;
+    if (t < kHistGroup) s_pairs[t] = 0ull;
     uint32_t c[kHistGroup];
 #pragma unroll
     for (int j = 0; j < kHistGroup; ++j) {
@@ -625,6 +628,7 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
         if (t == 0) s_d[kMaxCols] = 0u;
         __syncthreads();
         const int64_t r0 = ((int64_t)blockIdx.x * kHistGroup + j) * kColBlock;
+        uint64_t pairs = 0;
 #pragma unroll
         for (int i = 0; i < kColBlock / kBlock; ++i) {
             const int64_t r = r0 + i * kBlock + t;
@@ -634,9 +638,13 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
                     const uint32_t h = (uint32_t)(q.w - q.y);
                     atomicAdd(&s_d[q.x], h);
                     atomicAdd(&s_d[q.z], 0u - h);
+                    pairs += (uint64_t)h * (uint64_t)(q.z - q.x);
                 }
             }
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) pairs += __shfl_xor(pairs, off, 64);
+        if (__lane_id() == 0) atomicAdd(&s_pairs[j], pairs);
         __syncthreads();
         uint32_t tot;
         const uint32_t d = s_d[t];
@@ -645,6 +653,26 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
     if (t < ncols)
         *reinterpret_cast<uint4 *>(hist + (int64_t)t * stride + (int64_t)blockIdx.x * kHistGroup) =
             make_uint4(c[0], c[1], c[2], c[3]);
+    if (t < kHistGroup) block_pairs[(int64_t)blockIdx.x * kHistGroup + t] = s_pairs[t];
+}
+
+// Total pair count P (64-bit sum of the block totals), the overflow flag and
+// min(P, capacity).
+__global__ __launch_bounds__(1024) void pair_total_kernel(const uint64_t *__restrict__ block_pairs, int64_t nb,
+                                                          uint64_t cap, uint64_t *total_out, int64_t *num_pairs,
+                                                          int32_t *overflow, uint32_t *n_eff)
+{
+    __shared__ uint64_t s_warp[16];
+    uint64_t sum = 0;
+    for (int64_t i = threadIdx.x; i < nb; i += 1024) sum += block_pairs[i];
+    uint64_t total;
+    block_exclusive_scan<uint64_t, 16>(sum, total, s_warp);
+    if (threadIdx.x == 0) {
+        *total_out = total;
+        *num_pairs = (int64_t)total;
+        *overflow = total > cap ? 1 : 0;
+        *n_eff = (uint32_t)(total > cap ? cap : total);
+    }
 }
 
 // Generation and column placement of the pairs of one block of kColBlock
@@ -656,14 +684,13 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
 // order within a Gaussian); the chunk is then ordered by column in LDS (key
 // and owning Gaussian) and each column run is written to its place: the
 // column's global start plus the column's pairs in earlier blocks and in
-// earlier chunks of this one.  Only the pairs at r-major positions below the
-// capacity are generated, and only places below it are written.
+// earlier chunks of this one.  Places at or past the capacity are not
+// written.
 template <int ITEMS>
 __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
-    const uint32_t *__restrict__ order, const int4 *__restrict__ rect, const uint32_t *__restrict__ off,
-    const uint64_t *p_total, uint64_t cap, TileGrids tg, int64_t n, const uint32_t *__restrict__ hist_scan,
-    const uint32_t *__restrict__ col_total, int64_t stride, int ncols, int nbits, uint32_t *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out)
+    const uint32_t *__restrict__ order, const int4 *__restrict__ rect, uint64_t cap, TileGrids tg, int64_t n,
+    const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ col_total, int64_t stride, int ncols,
+    int nbits, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
     constexpr int NT = kColBlock;
     constexpr int kW = NT / 64;
@@ -687,19 +714,24 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
     const uint64_t lt = lanemask_lt();
     const uint32_t dmask = (1u << nbits) - 1u;              // columns < 2^nbits
-    const uint64_t total = *p_total;
-    const uint32_t lim = (uint32_t)(total < cap ? total : cap);
-    const uint32_t base = off[first];
+    uint32_t npairs = 0;
     if (t < cnt) {
         const uint32_t g = order[first + t];
         const int v = tg.V > 1 ? (int)(g / tg.per_view) : 0;
         const int4 q = col_rect(rect[first + t]);
+        const bool has = q.z > q.x && q.w > q.y;
         s_xw[t] = (uint32_t)q.x | ((uint32_t)(q.z - q.x) << 16);
         s_id[t] = g;
         s_row[t] = (uint32_t)(tg.row_off[v] + q.y);
-        s_off[t] = off[first + t] - base;
+        npairs = has ? (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y) : 0u;
     }
-    if (t == 0) s_off[cnt] = (first + cnt < n ? off[first + cnt] : lim) - base;
+    {
+        // block-local r-major offsets of the Gaussians' pairs
+        uint32_t all;
+        const uint32_t ex = block_exclusive_scan<uint32_t, kW>(npairs, all, s_tot);
+        s_off[t] = ex;
+        if (t == NT - 1) s_off[NT] = all;
+    }
     {
         // global start of column t (exclusive scan of the column totals) plus
         // the column's pairs in earlier blocks
@@ -709,7 +741,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
         if (t < kMaxCols) s_gb[0][t] = before + (t < ncols ? hist_scan[(int64_t)t * stride + blockIdx.x] : 0u);
     }
     __syncthreads();
-    const uint32_t m = s_off[cnt];                          // pairs of this block
+    const uint32_t m = s_off[NT];                           // pairs of this block
     int par = 0;
     for (uint32_t q0 = 0; q0 < m; q0 += kTileN, par ^= 1) {
         const int count = (int)min((uint32_t)kTileN, m - q0);
@@ -913,6 +945,7 @@ struct SortWorkspace {
     uint32_t *pair_off;           // [n] pair counts, then exclusive offsets
     int4 *rect_sorted;            // [n] tile rectangles in depth order
     uint64_t *partials;           // scan partials
+    uint64_t *col_pairs;          // pair total of each column block
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
     size_t bytes;
@@ -945,6 +978,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.pair_off = (uint32_t *)take(sizeof(uint32_t) * nm);
     w.rect_sorted = (int4 *)take(sizeof(int4) * nm);
     w.partials = (uint64_t *)take(sizeof(uint64_t) * ((nm + kScanTile - 1) / kScanTile + 1));
+    w.col_pairs = (uint64_t *)take(sizeof(uint64_t) * nb_col);
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
     w.bytes = off;
@@ -1063,52 +1097,56 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
                    pass == 3 ? rc : nullptr, pass == 3 ? w.rect_sorted : nullptr);
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
-    // 2. pair counts in depth order, their exclusive scan (total P) and the
-    //    overflow check.  The number of tile-sort passes decides which buffer
-    //    receives the pairs so that the sorted result ends in the caller's.
-    //    Column-first binning (views up to kMaxCols tiles wide) sorts by the
+    // 2. Column-first binning (views up to kMaxCols tiles wide) sorts by the
     //    global tile row after its column pass; otherwise the pairs are
-    //    duplicated and sorted by tile id.
+    //    duplicated and sorted by tile id.  The number of tile-sort passes
+    //    decides which buffer receives the pairs so that the sorted result
+    //    ends in the caller's.
     const bool by_column = ncols <= kMaxCols;
     int bits = 1;
     while ((1ll << bits) < (by_column ? total_rows : total_tiles)) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
     uint32_t *k0 = (passes & 1) ? w.pk : tile_keys, *v0 = (passes & 1) ? w.pv : values;
     uint32_t *k1 = (passes & 1) ? tile_keys : w.pk, *v1 = (passes & 1) ? values : w.pv;
-    const int64_t nb = (n + kScanTile - 1) / kScanTile;
-    if (nb > 0)
-        hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, PairCountGather>), dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           PairCountGather{w.rect_sorted, w.pair_off}, n, (const uint32_t *)nullptr, w.partials);
-    hipLaunchKernelGGL(pair_partials_kernel, dim3(1), dim3(1024), 0, s, w.partials, nb, w.p_total,
-                       (uint64_t)capacity_pairs, num_pairs, overflow, w.n_eff);
-    if (nb > 0)
-        hipLaunchKernelGGL((scan_final_kernel<uint64_t, U32Load, OffsetStore>), dim3((unsigned)nb), dim3(kBlock), 0, s,
-                           U32Load{w.pair_off}, OffsetStore{w.pair_off, (uint64_t)capacity_pairs}, n,
-                           (const uint32_t *)nullptr, (const uint64_t *)w.partials);
     if (by_column) {
-        // 3. column pass: per-block column counts, their scan per column, and
-        //    generation + placement of the pairs
+        // 3. column pass: per-block column counts (and pair totals, whose sum
+        //    is P), their scan per column, and generation + placement of the
+        //    pairs
         const int64_t nbc = (n + kColBlock - 1) / kColBlock;
         const int64_t stride = hist_stride(nbc);
         int cbits = 1;
         while ((1 << cbits) < ncols) ++cbits;
         if (n > 0) {
             hipLaunchKernelGGL(col_hist_kernel, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s,
-                               (const int4 *)w.rect_sorted, n, ncols, w.hist, stride);
+                               (const int4 *)w.rect_sorted, n, ncols, w.hist, stride, w.col_pairs);
             hipLaunchKernelGGL(radix_rowscan_kernel, dim3(ncols), dim3(kBlock), 0, s, w.hist, stride, n,
                                (const uint32_t *)nullptr, kColBlock, w.digit_total);
+        }
+        hipLaunchKernelGGL(pair_total_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)w.col_pairs, nbc,
+                           (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff);
+        if (n > 0)
             hipLaunchKernelGGL(col_scatter_kernel<kColItems>, dim3((unsigned)nbc), dim3(kColBlock), 0, s, order,
-                               (const int4 *)w.rect_sorted, (const uint32_t *)w.pair_off,
-                               (const uint64_t *)w.p_total, (uint64_t)capacity_pairs, tg, n,
+                               (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
                                (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
                                k0, v0);
-        }
-    } else if (n > 0) {
-        // 3. duplication in depth order
-        hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order,
-                           (const int4 *)w.rect_sorted,
-                           (const uint32_t *)w.pair_off, (const uint64_t *)w.p_total, (uint64_t)capacity_pairs,
-                           tg, n, k0, v0);
+    } else {
+        // 3. pair counts in depth order, their exclusive scan (total P,
+        //    overflow) and duplication in depth order
+        const int64_t nb = (n + kScanTile - 1) / kScanTile;
+        if (nb > 0)
+            hipLaunchKernelGGL((scan_reduce_kernel<uint64_t, PairCountGather>), dim3((unsigned)nb), dim3(kBlock), 0,
+                               s, PairCountGather{w.rect_sorted, w.pair_off}, n, (const uint32_t *)nullptr,
+                               w.partials);
+        hipLaunchKernelGGL(pair_partials_kernel, dim3(1), dim3(1024), 0, s, w.partials, nb, w.p_total,
+                           (uint64_t)capacity_pairs, num_pairs, overflow, w.n_eff);
+        if (nb > 0)
+            hipLaunchKernelGGL((scan_final_kernel<uint64_t, U32Load, OffsetStore>), dim3((unsigned)nb), dim3(kBlock),
+                               0, s, U32Load{w.pair_off}, OffsetStore{w.pair_off, (uint64_t)capacity_pairs}, n,
+                               (const uint32_t *)nullptr, (const uint64_t *)w.partials);
+        if (n > 0)
+            hipLaunchKernelGGL(duplicate_kernel, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, order,
+                               (const int4 *)w.rect_sorted, (const uint32_t *)w.pair_off,
+                               (const uint64_t *)w.p_total, (uint64_t)capacity_pairs, tg, n, k0, v0);
     }
     // 4. stable sort of the pairs by global tile row (above the column bits,
     //    the last pass writing tile ids) or by tile id, the key bits split
