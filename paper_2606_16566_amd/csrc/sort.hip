@@ -380,9 +380,9 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__re
 // Exclusive scan, in place, of one digit's row of per-block counts over the
 // blocks that hold elements: chunks of 2048 (8 consecutive per lane), block
 // scan of the lane sums, running carry between chunks.
-__global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t stride,
-                                                               int64_t n_max, const uint32_t *n_dev, int tile_n,
-                                                               uint32_t *__restrict__ digit_total)
+__device__ __forceinline__ void radix_rowscan_body(uint32_t *__restrict__ hist, int64_t stride, int64_t n_max,
+                                                   const uint32_t *n_dev, int tile_n,
+                                                   uint32_t *__restrict__ digit_total)
 {
     constexpr int kPer = 8;
     __shared__ uint32_t s_warp[kWaves];
@@ -408,6 +408,13 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
         carry += tot;
     }
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restrict__ hist, int64_t stride,
+                                                               int64_t n_max, const uint32_t *n_dev, int tile_n,
+                                                               uint32_t *__restrict__ digit_total)
+{
+    radix_rowscan_body(hist, stride, n_max, n_dev, tile_n, digit_total);
 }
 
 // Stable scatter of one block of 256 * ITEMS elements.  Wavefront w owns a
@@ -656,22 +663,37 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
     if (t < kHistGroup) block_pairs[(int64_t)blockIdx.x * kHistGroup + t] = s_pairs[t];
 }
 
-// Total pair count P (64-bit sum of the block totals), the overflow flag and
-// min(P, capacity).
-__global__ __launch_bounds__(1024) void pair_total_kernel(const uint64_t *__restrict__ block_pairs, int64_t nb,
-                                                          uint64_t cap, uint64_t *total_out, int64_t *num_pairs,
-                                                          int32_t *overflow, uint32_t *n_eff)
+// Scan of the per-block column counts (workgroup c < ncols: column c, as a
+// radix row scan) and, in the extra last workgroup, the total pair count P
+// (64-bit sum of the block totals), the overflow flag and min(P, capacity).
+struct PairTotal {
+    const uint64_t *block_pairs;
+    int64_t nb;
+    uint64_t cap;
+    uint64_t *total_out;
+    int64_t *num_pairs;
+    int32_t *overflow;
+    uint32_t *n_eff;
+};
+
+__global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restrict__ hist, int64_t stride, int64_t n,
+                                                             int ncols, uint32_t *__restrict__ col_total,
+                                                             PairTotal pt)
 {
-    __shared__ uint64_t s_warp[16];
+    if ((int)blockIdx.x < ncols) {
+        radix_rowscan_body(hist, stride, n, nullptr, kColBlock, col_total);
+        return;
+    }
+    __shared__ uint64_t s_warp[kWaves];
     uint64_t sum = 0;
-    for (int64_t i = threadIdx.x; i < nb; i += 1024) sum += block_pairs[i];
+    for (int64_t i = threadIdx.x; i < pt.nb; i += kBlock) sum += pt.block_pairs[i];
     uint64_t total;
-    block_exclusive_scan<uint64_t, 16>(sum, total, s_warp);
+    block_exclusive_scan<uint64_t, kWaves>(sum, total, s_warp);
     if (threadIdx.x == 0) {
-        *total_out = total;
-        *num_pairs = (int64_t)total;
-        *overflow = total > cap ? 1 : 0;
-        *n_eff = (uint32_t)(total > cap ? cap : total);
+        *pt.total_out = total;
+        *pt.num_pairs = (int64_t)total;
+        *pt.overflow = total > pt.cap ? 1 : 0;
+        *pt.n_eff = (uint32_t)(total > pt.cap ? pt.cap : total);
     }
 }
 
@@ -1119,11 +1141,10 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         if (n > 0) {
             hipLaunchKernelGGL(col_hist_kernel, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s,
                                (const int4 *)w.rect_sorted, n, ncols, w.hist, stride, w.col_pairs);
-            hipLaunchKernelGGL(radix_rowscan_kernel, dim3(ncols), dim3(kBlock), 0, s, w.hist, stride, n,
-                               (const uint32_t *)nullptr, kColBlock, w.digit_total);
         }
-        hipLaunchKernelGGL(pair_total_kernel, dim3(1), dim3(1024), 0, s, (const uint64_t *)w.col_pairs, nbc,
-                           (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff);
+        const PairTotal pt{w.col_pairs, nbc, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
+        hipLaunchKernelGGL(col_rowscan_kernel, dim3(n > 0 ? ncols + 1 : 1), dim3(kBlock), 0, s, w.hist, stride, n,
+                           n > 0 ? ncols : 0, w.digit_total, pt);
         if (n > 0)
             hipLaunchKernelGGL(col_scatter_kernel<kColItems>, dim3((unsigned)nbc), dim3(kColBlock), 0, s, order,
                                (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
