@@ -276,13 +276,16 @@ lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *o
                           size_t workspace_bytes, void *stream);
 
 /* lgs_render_backward of a batch: n_elem = num_views * n elements of the
- * view-major gradient outputs. */
+ * view-major gradient outputs.  tile_order: NULL, or a permutation of the
+ * batch's global tile ids (as from lgs_tile_order) in which the tiles are
+ * launched, e.g. longest list first so that the longest tiles do not run
+ * last; the gradients do not depend on it beyond float summation order. */
 lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, int32_t num_views, int64_t n_elem,
                                      const uint32_t *ranges, const uint32_t *values, const float *means2d,
                                      const float *conic_opacity, const float *rgb, const float *out_T,
                                      const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
                                      float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
-                                     void *stream);
+                                     const uint32_t *tile_order, void *stream);
 
 /* lgs_project_backward of a batch: the view-major gradients of the projected
  * attributes are summed over the views into the raw-parameter gradients

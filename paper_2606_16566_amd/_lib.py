@@ -66,7 +66,7 @@ _SIG = {
     "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9 + [_P, _P, _I32, _P]),
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
-    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 14),
+    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 15),
     "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 16),
     "lgs_graph_begin": (C.c_int, [_P]),
     "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),

@@ -34,10 +34,11 @@ class ViewBatch:
     blocks_per_cu  workgroups per compute unit of the persistent render (0: 8)
     lpt            hand out tiles longest first (persistent render only)
     capacity       initial pair capacity; `fit()` grows it from a measured count
+    bwd_lpt        launch the backward's tiles longest first
     """
 
     def __init__(self, cams, n: int, sh_degree: int, variant="local_q8", persistent: bool = False,
-                 blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda"):
+                 blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda", bwd_lpt: bool = True):
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_VIEWS:
             raise ValueError(f"a batch holds 1..{L.MAX_VIEWS} cameras, got {len(cams)}")
@@ -79,6 +80,7 @@ class ViewBatch:
         self.ranges = z(self.num_tiles, 2, dtype=i32)
         self.queue = z(L.QUEUE_WORDS, dtype=i32)
         self.order = z(self.num_tiles, dtype=i32)
+        self.bwd_lpt = bool(bwd_lpt)
         self.order_ws = torch.empty(L.lib().lgs_tile_order_workspace_size(self.num_tiles) + 256, dtype=torch.uint8,
                                     device=dev)
         self.capacity = 0
@@ -178,9 +180,12 @@ class ViewBatch:
         self.tile_order()
         self.blend(stats)
 
-    def tile_order(self):
+    def _fwd_lpt(self):
+        return self.persistent and self.lpt
+
+    def tile_order(self, force: bool = False):
         """Enqueue the longest-first tile order (when the settings use it)."""
-        if self.persistent and self.lpt:
+        if force or self._fwd_lpt():
             ows, owsb = _aligned(self.order_ws)
             L.check(L.lib().lgs_tile_order(_p(self.ranges), self.num_tiles, _p(self.order), ows, owsb, _stream()),
                     "lgs_tile_order")
@@ -212,10 +217,13 @@ class ViewBatch:
         means3d, log_scales, quats, logits, sh = params
         g = self.grad_rgb if grad_rgb is None else _req(grad_rgb, torch.float32, "grad_rgb")
         bv = L.RENDER_PLAIN if (self.variant & 0xF) == L.RENDER_PLAIN else L.RENDER_LOCAL | (self.variant & L.RENDER_Q8)
+        if self.bwd_lpt and not self._fwd_lpt():
+            self.tile_order(force=True)                  # the forward did not compute it
         L.check(lb.lgs_render_backward_batch(bv, self.cam_arr, self.V, self.V * self.n, _p(self.ranges),
                                              _p(self.vals), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
                                              _p(self.out_T), _p(self.out_nc), _p(g), _p(grad_T), _p(self.g_means2d),
-                                             _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb), s),
+                                             _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
+                                             _p(self.order) if self.bwd_lpt else None, s),
                 "lgs_render_backward_batch")
         L.check(lb.lgs_project_backward_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales),
                                               _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_means2d),

@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     __shared__ int s_max[kBlock / 64];
 
     const RenderArgs &a = ba.r;
-    const TileCtx<double> tc(a, xcd_tile(blockIdx.x, a.num_tiles), threadIdx.x >> 6, Q8);
+    const int tile = a.order ? (int)a.order[blockIdx.x] : xcd_tile(blockIdx.x, a.num_tiles);
+    const TileCtx<double> tc(a, tile, threadIdx.x >> 6, Q8);
     const int lane = __lane_id(), wid = tc.wid;
     const int px = tc.px, py = tc.py;
     const bool inside = tc.inside;
@@ -275,7 +276,8 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
                                                 const float *means2d, const float *conic_opacity, const float *rgb,
                                                 const float *out_T, const int32_t *out_ncontrib,
                                                 const float *grad_rgb, const float *grad_T, float *g_means2d,
-                                                float *g_conic, float *g_opacity, float *g_rgb, void *stream)
+                                                float *g_conic, float *g_opacity, float *g_rgb,
+                                                const uint32_t *tile_order, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_backward: num_views must be 1..%d", kMaxViews);
     LGS_REQUIRE(cameras != nullptr, "lgs_render_backward: invalid camera");
@@ -298,6 +300,7 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
     BwdArgs a;
     a.r = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
                     const_cast<int32_t *>(out_ncontrib), nullptr);
+    a.r.order = tile_order;
     a.grad_rgb = grad_rgb; a.grad_T = grad_T;
     a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
     if (a.r.num_tiles > 0) {
@@ -320,5 +323,6 @@ extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam
                                           float *g_opacity, float *g_rgb, void *stream)
 {
     return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, means2d, conic_opacity, rgb, out_T,
-                                     out_ncontrib, grad_rgb, grad_T, g_means2d, g_conic, g_opacity, g_rgb, stream);
+                                     out_ncontrib, grad_rgb, grad_T, g_means2d, g_conic, g_opacity, g_rgb, nullptr,
+                                     stream);
 }

@@ -40,7 +40,7 @@ struct RenderArgs {
     int32_t *out_nc;
     unsigned long long *stats;
     uint32_t *queue;            // persistent mode: kQueues counters (zeroed before launch), else null
-    const uint32_t *order;      // persistent mode: tile of each queue position, or null for index order
+    const uint32_t *order;      // tile of each queue position (persistent render) or workgroup (backward), or null
     int num_tiles;              // all views
     ViewTable vt;
 };

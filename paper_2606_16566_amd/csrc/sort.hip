@@ -102,22 +102,6 @@ __global__ __launch_bounds__(kBlock) void scan_reduce_kernel(L ld, int64_t n_max
     if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void scan_partials_kernel(T *partials, int64_t nb, T *total_out)
-{
-    __shared__ T s_warp[16];
-    T carry = 0;
-    for (int64_t c = 0; c < nb; c += 1024) {
-        const int64_t i = c + threadIdx.x;
-        T v = i < nb ? partials[i] : (T)0;
-        T tot;
-        T ex = block_exclusive_scan<T, 16>(v, tot, s_warp);
-        if (i < nb) partials[i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
 template <typename T, typename L, typename S>
 __global__ __launch_bounds__(kBlock) void scan_final_kernel(L ld, S st, int64_t n_max, const uint32_t *n_dev,
                                                             const T *partials)

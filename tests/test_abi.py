@@ -86,7 +86,7 @@ def test_batch_and_graph_arguments_rejected_on_host():
     for nv in (0, 17):
         assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 11)) == L.LGS_ERR_INVALID_ARG
         assert lb.lgs_render_batch(3, cams, nv, *([None] * 9), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 14)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 15)) == L.LGS_ERR_INVALID_ARG
         assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 16)) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
     assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, 10, None, None, None, 0, None) == \

@@ -129,13 +129,14 @@ def test_tile_order_is_longest_first_permutation():
         assert np.all(length[nz.max() + 1:] == 0)
 
 
-def test_batch_backward_equals_sum_of_views():
+@pytest.mark.parametrize("bwd_lpt", [True, False])
+def test_batch_backward_equals_sum_of_views(bwd_lpt):
     sc = scenes.make_config(5, n=6000)
     cams = ring_cameras([(128, 96), (100, 100), (64, 48)])
     params = scene_tensors(sc)
     rng = np.random.default_rng(7)
     gCs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
-    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local")
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local", bwd_lpt=bwd_lpt)
     vb.fit(params)
     vb.forward(params)
     vb.backward(params, grad_rgb=vb.pack([to_dev(g) for g in gCs]))
