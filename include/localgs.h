@@ -255,9 +255,10 @@ lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32
  *   blocks_per_cu workgroups per compute unit (<= 0: 8) whose wavefronts
  *   take wavefront sub-tiles from the counters until none is left.  Other
  *   variants ignore it.  Concurrent calls must not share a queue.
- * tile_order: NULL to hand out tiles in index order, else a device
- *   permutation [total tiles] (e.g. from lgs_tile_order) giving the tile of
- *   each queue position.  Outputs do not depend on the order. */
+ * tile_order: NULL to hand out tiles in index order (XCD-banded for one
+ *   workgroup per tile), else a device permutation [total tiles] (e.g. from
+ *   lgs_tile_order) giving the tile of each queue position, or of each
+ *   workgroup without a queue.  Outputs do not depend on the order. */
 lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num_views,
                             const uint32_t *ranges, const uint32_t *values,
                             const float *means2d, const float *conic_opacity, const float *rgb,

@@ -6,9 +6,10 @@ wavefront sub-tile and the exponent precision change):
   shape          16x4 row strips or 8x8 quadrants per wavefront
   vote           termination vote after every Gaussian, or once per four
   precision      exponent in double, or single precision throughout
-  schedule       one workgroup per tile, or a persistent queue of
-                 blocks_per_cu workgroups per compute unit (2, 4, 8) handing
-                 out sub-tiles in index or longest-first tile order
+  schedule       one workgroup per tile (XCD-banded index order or longest
+                 first), or a persistent queue of blocks_per_cu workgroups per
+                 compute unit (2, 4, 8) handing out sub-tiles in index or
+                 longest-first tile order
 
 Objective: median duration of the render launch over `reps` timed runs
 (HIP events on the launching stream).  A point is admissible only if its
@@ -44,6 +45,7 @@ def space(family: str = "local"):
     for shape, vote, prec in itertools.product(("16x4", "8x8"), votes, ("fp64", "fp32")):
         base = dict(family=family, shape=shape, vote=vote, precision=prec)
         pts.append(dict(base, persistent=False, blocks_per_cu=0, lpt=False))
+        pts.append(dict(base, persistent=False, blocks_per_cu=0, lpt=True))
         for bpc, lpt in itertools.product((2, 4, 8), (False, True)):
             pts.append(dict(base, persistent=True, blocks_per_cu=bpc, lpt=lpt))
     return pts

@@ -32,7 +32,7 @@ class ViewBatch:
     variant        render variant name or code (see rasterizer.variant_code)
     persistent     queue-driven render for the culling variants
     blocks_per_cu  workgroups per compute unit of the persistent render (0: 8)
-    lpt            hand out tiles longest first (persistent render only)
+    lpt            render tiles longest first (queue order, or workgroup order)
     capacity       initial pair capacity; `fit()` grows it from a measured count
     bwd_lpt        launch the backward's tiles longest first
     """
@@ -181,7 +181,7 @@ class ViewBatch:
         self.blend(stats)
 
     def _fwd_lpt(self):
-        return self.persistent and self.lpt
+        return self.lpt
 
     def tile_order(self, force: bool = False):
         """Enqueue the longest-first tile order (when the settings use it)."""
@@ -193,7 +193,7 @@ class ViewBatch:
     def blend(self, stats: torch.Tensor | None = None):
         """Enqueue the render launch itself."""
         lb, s = L.lib(), _stream()
-        order = _p(self.order) if (self.persistent and self.lpt) else None
+        order = _p(self.order) if self.lpt else None
         L.check(lb.lgs_render_batch(self.variant, self.cam_arr, self.V, _p(self.ranges), _p(self.vals),
                                     _p(self.means2d), _p(self.conic_opacity), _p(self.rgb), _p(self.out_rgb),
                                     _p(self.out_T), _p(self.out_nc), _p(stats),

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void render_block_kernel(RenderArgs args)
     __shared__ float4 s_c[kBlock];
     __shared__ int s_alive[kBlock / 64];
 
-    const TileCtx<R> tc(args, xcd_tile(blockIdx.x, args.num_tiles), threadIdx.x >> 6);
+    const TileCtx<R> tc(args, args.order ? (int)args.order[blockIdx.x] : xcd_tile(blockIdx.x, args.num_tiles),
+                        threadIdx.x >> 6);
     float T = 1.f;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f;
     int32_t last = 0;
@@ -278,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
     const int wid = threadIdx.x >> 6;
     WaveStats st;
     if (args.queue == nullptr) {
-        const TileCtx<R> tc(args, xcd_tile(blockIdx.x, args.num_tiles), wid, Q8);
+        const TileCtx<R> tc(args, args.order ? (int)args.order[blockIdx.x] : xcd_tile(blockIdx.x, args.num_tiles),
+                            wid, Q8);
         render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
     } else {
         const uint32_t units = 4u * (uint32_t)args.num_tiles;
@@ -379,13 +381,13 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     render::RenderArgs a = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb,
                                              out_T, out_ncontrib, stats);
     hipStream_t s = as_stream(stream);
+    a.order = tile_order;                     // queue position -> tile, or workgroup -> tile
     const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
     unsigned grid = (unsigned)a.num_tiles;
     if (persistent) {
         static_assert(kQueues * kQueueStride == LGS_QUEUE_WORDS, "queue block size");
         fill_async<uint32_t>(queue, 0u, kQueues * kQueueStride, s);
         a.queue = queue;
-        a.order = tile_order;
         const int per = blocks_per_cu > 0 ? blocks_per_cu : 8;
         // a multiple of kQueues, so that every counter has workgroups taking from it
         grid = (unsigned)((device_cus() * per + kQueues - 1) / kQueues * kQueues);

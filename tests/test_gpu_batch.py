@@ -56,8 +56,8 @@ def test_batch_forward_bitwise_small(variant):
     sc = scenes.make_config(5, n=20000)
     cams = ring_cameras([(160, 120), (203, 150), (96, 64), (33, 47)])
     params = scene_tensors(sc)
-    modes = [dict(persistent=False), dict(persistent=True, lpt=False), dict(persistent=True, lpt=True,
-                                                                           blocks_per_cu=2)]
+    modes = [dict(persistent=False), dict(persistent=False, lpt=True), dict(persistent=True, lpt=False),
+             dict(persistent=True, lpt=True, blocks_per_cu=2)]
     refs = [single_view(c, params, variant) for c in cams]
     for mode in modes:
         vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant=variant, **mode)
