@@ -7,10 +7,13 @@
 // Two-stage ordering.  Instead of radix-sorting 64-bit (tile << 32 | depth)
 // keys over all P pairs (ceil(log2 tiles) + 32 bits: six 8-bit passes over P),
 // the Gaussians are first sorted by depth (32-bit key over N; culled ones
-// carry depth +inf and sink to the end), duplicated in that order, and the
-// pairs are then stably sorted by tile id only (ceil(log2 tiles) bits: two
-// passes at 1080p).  Both sorts are stable and duplication follows
-// (depth, id) order, so the result is identical to the single 64-bit sort.
+// carry depth +inf and sink to the end) and the pairs, emitted in that order,
+// are then ordered stably by tile only.  For grids up to 256 tiles wide the
+// pairs are generated straight into tile-column order (the column pass) and
+// one stable radix pass on the tile row follows (one pass at 1080p); wider
+// grids store the duplicated pairs and sort them by tile id.  Every step is
+// stable and the emission follows (depth, id) order, so the result is
+// identical to the single 64-bit sort.
 #include "common.hpp"
 
 namespace lgs {
