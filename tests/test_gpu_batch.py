@@ -71,6 +71,25 @@ def test_batch_forward_bitwise_small(variant):
             assert np.array_equal(vb.n_contrib(v).cpu().numpy(), nc), (mode, v)
 
 
+def test_batch_forward_bitwise_wide_view():
+    """A view wider than 256 tiles sends the whole batch down the stored
+    duplication path; the narrow view must still match its single-view
+    (column-first) result bitwise, and the wide one its own."""
+    sc = scenes.make_config(5, n=20000)
+    cams = ring_cameras([(4200, 64), (160, 120)])
+    params = scene_tensors(sc)
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local")
+    vb.fit(params)
+    vb.forward(params)
+    torch.cuda.synchronize()
+    assert not vb.overflowed()
+    for v, c in enumerate(cams):
+        img, T, nc = single_view(c, params, "local")
+        assert np.array_equal(vb.image(v).cpu().numpy(), img), v
+        assert np.array_equal(vb.final_T(v).cpu().numpy(), T), v
+        assert np.array_equal(vb.n_contrib(v).cpu().numpy(), nc), v
+
+
 def test_batch_forward_bitwise_mixed_sizes():
     """Four views of the 16-view clustered recipe at its own resolutions."""
     sc = scenes.make_config(5, n=100000)
