@@ -298,6 +298,21 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbi
     return match;
 }
 
+// Four consecutive keys of type KT (uint32_t or uint16_t) in one vector load.
+template <typename KT> struct Key4;
+template <> struct Key4<uint32_t> {
+    using V = uint4;
+    __device__ static uint32_t at(const V &v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+};
+template <> struct Key4<uint16_t> {
+    using V = uint2;
+    __device__ static uint32_t at(const V &v, int e)
+    {
+        const uint32_t w = (e < 2) ? v.x : v.y;
+        return (e & 1) ? (w >> 16) : (w & 0xFFFFu);
+    }
+};
+
 // Per-block digit histograms (per-wavefront sub-histograms in LDS, so the
 // atomics of one wavefront never contend with another's).  One workgroup
 // counts kHistGroup consecutive blocks and writes their counts of each digit
@@ -308,26 +323,28 @@ constexpr int kHistGroup = 4;
 
 inline int64_t hist_stride(int64_t nblocks) { return (nblocks + kHistGroup - 1) / kHistGroup * kHistGroup; }
 
-template <int ITEMS>
-__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__restrict__ keys, int64_t n_max,
+template <int ITEMS, typename KT>
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict__ keys, int64_t n_max,
                                                             const uint32_t *n_dev, int shift, uint32_t mask,
                                                             uint32_t *__restrict__ hist, int64_t stride)
 {
+    using V = typename Key4<KT>::V;
     constexpr int kTileN = kBlock * ITEMS;
-    constexpr int kV = ITEMS / 4;                              // 16-byte loads per thread and block
+    constexpr int kV = ITEMS / 4;                              // 4-key loads per thread and block
     __shared__ uint32_t s_h[kWaves][kRadixBins];
     const int wid = threadIdx.x >> 6, lane = __lane_id();
     const int64_t n = live_count(n_max, n_dev);
     const int64_t g0 = (int64_t)blockIdx.x * kHistGroup * kTileN;
+    auto aligned = [&](int64_t start) { return (reinterpret_cast<uintptr_t>(keys + start) % sizeof(V)) == 0; };
     // the keys of block j + 1 are in flight while block j is counted
-    auto load = [&](int j, uint4 *v) {
+    auto load = [&](int j, V *v) {
         const int64_t start = g0 + (int64_t)j * kTileN;
-        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + start);
-        const bool full = start + kTileN <= n && ((reinterpret_cast<uintptr_t>(keys + start) & 15) == 0);
+        const V *k4 = reinterpret_cast<const V *>(keys + start);
+        const bool full = start + kTileN <= n && aligned(start);
 #pragma unroll
-        for (int r = 0; r < kV; ++r) v[r] = full ? k4[r * kBlock + threadIdx.x] : make_uint4(0u, 0u, 0u, 0u);
+        for (int r = 0; r < kV; ++r) v[r] = full ? k4[r * kBlock + threadIdx.x] : V{};
     };
-    uint4 cur[kV], nxt[kV];
+    V cur[kV], nxt[kV];
     load(0, cur);
     uint32_t c[kHistGroup];
 #pragma unroll
@@ -339,17 +356,15 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const uint32_t *__re
         const int64_t start = g0 + (int64_t)j * kTileN;
         if (start < n) {
             const int cnt = (int)min((int64_t)kTileN, n - start);
-            if (cnt == kTileN && ((reinterpret_cast<uintptr_t>(keys + start) & 15) == 0)) {
+            if (cnt == kTileN && aligned(start)) {
 #pragma unroll
                 for (int r = 0; r < kV; ++r) {
-                    atomicAdd(&s_h[wid][(cur[r].x >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(cur[r].y >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(cur[r].z >> shift) & mask], 1u);
-                    atomicAdd(&s_h[wid][(cur[r].w >> shift) & mask], 1u);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) atomicAdd(&s_h[wid][(Key4<KT>::at(cur[r], e) >> shift) & mask], 1u);
                 }
             } else {
-                const uint32_t *kp = keys + start;
-                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][(kp[e] >> shift) & mask], 1u);
+                const KT *kp = keys + start;
+                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][((uint32_t)kp[e] >> shift) & mask], 1u);
             }
         }
         __syncthreads();
@@ -448,8 +463,8 @@ struct RowMap {
     }
 };
 
-template <int ITEMS, int NT, bool MAP>
-__global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
+template <int ITEMS, int NT, bool MAP, typename KT>
+__global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict__ keys_in,
                                                            const uint32_t *__restrict__ vals_in,
                                                            uint32_t *__restrict__ keys_out,
                                                            uint32_t *__restrict__ vals_out, int64_t n_max,
@@ -490,13 +505,13 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const uint32_t *__res
         if (t < kRadixBins) s_gbase[t] = before + hist_scan[(int64_t)t * stride + blockIdx.x];
     }
 
-    const uint32_t *kin = keys_in + start;                  // uniform bases, 32-bit offsets
+    const KT *kin = keys_in + start;                        // uniform bases, 32-bit offsets
     const uint32_t *vin = vals_in ? vals_in + start : nullptr;
     uint32_t key[ITEMS], lp[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
-        key[r] = local < count ? kin[local] : 0u;
+        key[r] = local < count ? (uint32_t)kin[local] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -695,11 +710,11 @@ __global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restric
 // column's global start plus the column's pairs in earlier blocks and in
 // earlier chunks of this one.  Places at or past the capacity are not
 // written.
-template <int ITEMS>
+template <int ITEMS, typename KT>
 __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     const uint32_t *__restrict__ order, const int4 *__restrict__ rect, uint64_t cap, TileGrids tg, int64_t n,
     const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ col_total, int64_t stride, int ncols,
-    int nbits, uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
+    int nbits, KT *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
     constexpr int NT = kColBlock;
     constexpr int kW = NT / 64;
@@ -858,7 +873,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
                 const uint32_t d = k & dmask;
                 const uint32_t pos = gb[d] + (uint32_t)i - s_lbase[d];
                 if (pos < cap) {
-                    keys_out[pos] = k;
+                    keys_out[pos] = (KT)k;                  // 16-bit keys: rows and columns below 256
                     vals_out[pos] = s_id[s_osort[i]];
                 }
             }
@@ -996,8 +1011,8 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 
 // one stable radix pass over [0, min(n_max, *n_dev)) on key bits
 // [shift, shift + bits)
-template <int ITEMS, int SCATTER_THREADS>
-void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+template <int ITEMS, int SCATTER_THREADS, typename KT>
+void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
                   const int4 *gather_src, int4 *gather_dst, const RowMap &rows)
 {
@@ -1006,24 +1021,25 @@ void radix_pass_t(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint
     if (nb == 0) return;
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t stride = hist_stride(nb);
-    hipLaunchKernelGGL(radix_hist_kernel<ITEMS>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s, kin,
+    hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT>), dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s, kin,
                        n_max, n_dev, shift, mask, w.hist, stride);
     hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
                        kTileN, w.digit_total);
     constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
     if (rows.V)
-        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true>), dim3((unsigned)nb),
+        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true, KT>), dim3((unsigned)nb),
                            dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
                            n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
                            stride, gather_src, gather_dst, rows);
     else
-        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false>), dim3((unsigned)nb),
+        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false, KT>), dim3((unsigned)nb),
                            dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
                            n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
                            stride, gather_src, gather_dst, rows);
 }
 
-void radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
+template <typename KT>
+void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
                 const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{})
 {
@@ -1112,6 +1128,9 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     //    decides which buffer receives the pairs so that the sorted result
     //    ends in the caller's.
     const bool by_column = ncols <= kMaxCols;
+    // with fewer than 256 global rows the keys between the column and the row
+    // pass fit 16 bits (row << 8 | column), and the row pass is a single one
+    const bool key16 = by_column && total_rows <= 256;
     int bits = 1;
     while ((1ll << bits) < (by_column ? total_rows : total_tiles)) ++bits;
     const int passes = (bits + kRadixBits - 1) / kRadixBits;
@@ -1132,9 +1151,14 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         const PairTotal pt{w.col_pairs, nbc, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
         hipLaunchKernelGGL(col_rowscan_kernel, dim3(n > 0 ? ncols + 1 : 1), dim3(kBlock), 0, s, w.hist, stride, n,
                            n > 0 ? ncols : 0, w.digit_total, pt);
-        if (n > 0)
-            hipLaunchKernelGGL(col_scatter_kernel<kColItems>, dim3((unsigned)nbc), dim3(kColBlock), 0, s, order,
-                               (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
+        if (n > 0 && key16)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t>), dim3((unsigned)nbc), dim3(kColBlock), 0, s,
+                               order, (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
+                               (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
+                               reinterpret_cast<uint16_t *>(k0), v0);
+        else if (n > 0)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t>), dim3((unsigned)nbc), dim3(kColBlock), 0, s,
+                               order, (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
                                (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
                                k0, v0);
     } else {
@@ -1160,12 +1184,19 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     //    the last pass writing tile ids) or by tile id, the key bits split
     //    evenly over the passes (longer digit runs per block than 8 + remainder)
     const int base_shift = by_column ? kColBits : 0;
-    for (int pass = 0, shift = 0; pass < passes; ++pass) {
-        const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
-        const RowMap map = by_column && pass == passes - 1 ? rows : RowMap{};
-        if (pass & 1) radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
-        else radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
-        shift += b;
+    if (key16) {
+        radix_pass(reinterpret_cast<const uint16_t *>(k0), v0, k1, v1, capacity_pairs, w.n_eff, kColBits, bits, w, s,
+                   nullptr, nullptr, rows);
+    } else {
+        for (int pass = 0, shift = 0; pass < passes; ++pass) {
+            const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
+            const RowMap map = by_column && pass == passes - 1 ? rows : RowMap{};
+            if (pass & 1)
+                radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
+            else
+                radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
+            shift += b;
+        }
     }
     LGS_LAUNCHED("lgs_sort");
     return LGS_OK;

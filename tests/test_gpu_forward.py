@@ -86,6 +86,8 @@ def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True, wide=False):
     (3, 70000, 300, 260, True, False), (9, 3000, 257, 20, True, True),
     # the widest grid of the column-first path, splats over many columns
     (8, 3000, 256, 30, False, True), (10, 20000, 37, 200, True, True),
+    # more than 256 tile rows: 32-bit keys between the column and row passes
+    (11, 20000, 40, 300, False, True),
     # above 2^22 and 2^25 pairs: the larger radix tiers
     (4, 1000000, 120, 68, False, False), (5, 800000, 300, 260, True, False),
     pytest.param(6, 6000000, 300, 260, False, False, marks=pytest.mark.slow)])
