@@ -52,6 +52,29 @@ __device__ __forceinline__ T wave_inclusive_scan(T v)
     return v;
 }
 
+// v + (v of the lane the DPP control selects), 0 where it selects none or the
+// row is masked off (all 64 lanes must be active)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v)
+{
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// 32-bit inclusive scan over the wavefront in DPP steps: shifts by 1, 2, 4, 8
+// within each row of 16, then the last lane of rows 0 and 2 into rows 1 and 3
+// (row_bcast:15) and lane 31 into rows 2 and 3 (row_bcast:31)
+template <>
+__device__ __forceinline__ uint32_t wave_inclusive_scan<uint32_t>(uint32_t v)
+{
+    v = dpp_add<0x111, 0xF>(v);   // row_shr:1
+    v = dpp_add<0x112, 0xF>(v);   // row_shr:2
+    v = dpp_add<0x114, 0xF>(v);   // row_shr:4
+    v = dpp_add<0x118, 0xF>(v);   // row_shr:8
+    v = dpp_add<0x142, 0xA>(v);   // row_bcast:15
+    v = dpp_add<0x143, 0xC>(v);   // row_bcast:31
+    return v;
+}
+
 template <typename T, int NW>
 __device__ __forceinline__ T block_exclusive_scan(T v, T &total, T *s_warp /*[NW]*/)
 {
@@ -379,35 +402,57 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
         make_uint4(c[0], c[1], c[2], c[3]);
 }
 
-// Exclusive scan, in place, of one digit's row of per-block counts over the
-// blocks that hold elements: chunks of 2048 (8 consecutive per lane), block
-// scan of the lane sums, running carry between chunks.
+// Exclusive scan, in place, of one row of per-block counts over the blocks
+// that hold elements, in chunks of kBlock * KP: wavefront w takes the chunk's
+// w-th quarter, lane-contiguous (coalesced) in KP rounds of 64, scans each
+// round across its lanes with a running carry, and the wavefront totals are
+// combined through LDS.  The next chunk's counts are loaded while this one
+// is scanned.
+template <int KP>
 __device__ __forceinline__ void radix_rowscan_body(uint32_t *__restrict__ hist, int64_t stride, int64_t n_max,
                                                    const uint32_t *n_dev, int tile_n,
                                                    uint32_t *__restrict__ digit_total)
 {
-    constexpr int kPer = 8;
+    constexpr int64_t kChunk = (int64_t)kBlock * KP;
     __shared__ uint32_t s_warp[kWaves];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
     uint32_t *row = hist + (int64_t)blockIdx.x * stride;
     const int64_t n = live_count(n_max, n_dev);
     const int64_t live = (n + tile_n - 1) / tile_n;
+    auto at = [&](int64_t c, int k) { return c + (int64_t)wid * 64 * KP + (int64_t)k * 64 + lane; };
+    auto load = [&](int64_t c, uint32_t *d) {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) d[k] = at(c, k) < live ? row[at(c, k)] : 0u;
+    };
+    uint32_t v[KP], nx[KP];
+    load(0, v);
     uint32_t carry = 0;
-    for (int64_t c = 0; c < live; c += kBlock * kPer) {
-        const int64_t b0 = c + (int64_t)threadIdx.x * kPer;
-        uint32_t v[kPer], sum = 0;
+    for (int64_t c = 0; c < live; c += kChunk) {
+        if (c + kChunk < live) load(c + kChunk, nx);
+        uint32_t wrun = 0;                                   // this wavefront's running sum
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            v[k] = b0 + k < live ? row[b0 + k] : 0u;
-            sum += v[k];
+        for (int k = 0; k < KP; ++k) {
+            const uint32_t incl = wave_inclusive_scan(v[k]);
+            const uint32_t x = v[k];
+            v[k] = wrun + incl - x;                          // exclusive within the wavefront's quarter
+            wrun += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
-        uint32_t tot;
-        uint32_t run = carry + block_exclusive_scan<uint32_t, kWaves>(sum, tot, s_warp);
+        if (lane == 0) s_warp[wid] = wrun;
+        __syncthreads();
+        uint32_t before = carry, tot = 0;
 #pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            if (b0 + k < live) row[b0 + k] = run;
-            run += v[k];
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = s_warp[w];
+            if (w < wid) before += t;
+            tot += t;
         }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KP; ++k)
+            if (at(c, k) < live) row[at(c, k)] = before + v[k];
         carry += tot;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) v[k] = nx[k];
     }
     if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
@@ -416,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
                                                                int64_t n_max, const uint32_t *n_dev, int tile_n,
                                                                uint32_t *__restrict__ digit_total)
 {
-    radix_rowscan_body(hist, stride, n_max, n_dev, tile_n, digit_total);
+    radix_rowscan_body<8>(hist, stride, n_max, n_dev, tile_n, digit_total);
 }
 
 // Stable scatter of one block of 256 * ITEMS elements.  Wavefront w owns a
@@ -618,9 +663,9 @@ __device__ __forceinline__ int4 col_rect(int4 q)
 }
 
 // Per-block column counts: hist[c * stride + b] = pairs of column c among the
-// Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order, and the
-// block's pair total in block_pairs[b].  One workgroup counts kHistGroup
-// consecutive blocks (one 16-byte write per column).
+// Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order.  One
+// workgroup counts kHistGroup consecutive blocks (one 16-byte write per
+// column) and writes their pair total to block_pairs[workgroup].
 __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict__ rect, int64_t n, int ncols,
                                                           uint32_t *__restrict__ hist, int64_t stride,
                                                           uint64_t *__restrict__ block_pairs)
@@ -662,7 +707,12 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
     if (t < ncols)
         *reinterpret_cast<uint4 *>(hist + (int64_t)t * stride + (int64_t)blockIdx.x * kHistGroup) =
             make_uint4(c[0], c[1], c[2], c[3]);
-    if (t < kHistGroup) block_pairs[(int64_t)blockIdx.x * kHistGroup + t] = s_pairs[t];
+    if (t == 0) {
+        uint64_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kHistGroup; ++j) sum += s_pairs[j];
+        block_pairs[blockIdx.x] = sum;
+    }
 }
 
 // Scan of the per-block column counts (workgroup c < ncols: column c, as a
@@ -683,12 +733,22 @@ __global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restric
                                                              PairTotal pt)
 {
     if ((int)blockIdx.x < ncols) {
-        radix_rowscan_body(hist, stride, n, nullptr, kColBlock, col_total);
+        radix_rowscan_body<32>(hist, stride, n, nullptr, kColBlock, col_total);
         return;
     }
     __shared__ uint64_t s_warp[kWaves];
+    constexpr int kU = 16;                                 // independent loads in flight per thread
     uint64_t sum = 0;
-    for (int64_t i = threadIdx.x; i < pt.nb; i += kBlock) sum += pt.block_pairs[i];
+    for (int64_t i0 = threadIdx.x; i0 < pt.nb; i0 += (int64_t)kBlock * kU) {
+        uint64_t part[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            part[u] = i < pt.nb ? pt.block_pairs[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sum += part[u];
+    }
     uint64_t total;
     block_exclusive_scan<uint64_t, kWaves>(sum, total, s_warp);
     if (threadIdx.x == 0) {
@@ -1148,7 +1208,8 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
             hipLaunchKernelGGL(col_hist_kernel, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s,
                                (const int4 *)w.rect_sorted, n, ncols, w.hist, stride, w.col_pairs);
         }
-        const PairTotal pt{w.col_pairs, nbc, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
+        const int64_t nhg = n > 0 ? stride / kHistGroup : 0;      // column-histogram workgroups
+        const PairTotal pt{w.col_pairs, nhg, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
         hipLaunchKernelGGL(col_rowscan_kernel, dim3(n > 0 ? ncols + 1 : 1), dim3(kBlock), 0, s, w.hist, stride, n,
                            n > 0 ? ncols : 0, w.digit_total, pt);
         if (n > 0 && key16)
