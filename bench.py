@@ -41,7 +41,7 @@ OPS_PER_PAIR = 14
 # hbm_counters.md (24.7 MiB read, 41.3 MiB written, after the copy-kernel
 # calibration), valid for the variant, workload and kernel sources they were
 # taken with; anything else reports null.
-RENDER_TRAFFIC = {"variant": 0x63, "sources_sha": "1c0df08ca7f369ae", "bytes": (24.7 + 41.2) * 2 ** 20,
+RENDER_TRAFFIC = {"variant": 0x63, "sources_sha": "1c0df08ca7f369ae", "bytes": (24.7 + 41.3) * 2 ** 20,
                   "workload": 2}
 RENDER_SOURCES = ("paper_2606_16566_amd/csrc/render.hip", "paper_2606_16566_amd/csrc/render_common.hpp",
                   "paper_2606_16566_amd/csrc/common.hpp")
