@@ -163,6 +163,10 @@ def test_sort_overflow_flag_and_empty():
     e = R.Projected(None, None, None, to_dev(np.zeros(0, np.float32)), to_dev(np.zeros((0, 4), np.int32)))
     b = R.Binner(capacity=16).run(cam, e)
     assert int(b.num_pairs.item()) == 0 and np.all(_sync_np(b.ranges) == 0)
+    # every Gaussian culled (depth +inf, empty rectangle)
+    c = R.Projected(None, None, None, to_dev(np.full(3000, np.inf, np.float32)), to_dev(np.zeros((3000, 4), np.int32)))
+    b = R.Binner(capacity=16).run(cam, c)
+    assert int(b.num_pairs.item()) == 0 and int(b.overflow.item()) == 0 and np.all(_sync_np(b.ranges) == 0)
 
 
 # ---------------------------------------------------------------------------
