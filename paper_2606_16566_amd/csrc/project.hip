@@ -31,21 +31,14 @@ __device__ __forceinline__ ShConst sh_consts()
     return k;
 }
 
-// SH basis in index order l*l + l + m (m = -l..l) at unit direction (x, y, z);
-// optionally the gradient of each basis function w.r.t. (x, y, z).
-template <int DEG, bool GRAD>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y, double (*dY)[3])
+// SH basis in index order l*l + l + m (m = -l..l) at unit direction (x, y, z).
+template <int DEG>
+__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y)
 {
     const ShConst k = sh_consts();
     Y[0] = k.k0;
-    if (GRAD) { dY[0][0] = dY[0][1] = dY[0][2] = 0.0; }
     if (DEG >= 1) {
         Y[1] = -k.k1 * y; Y[2] = k.k1 * z; Y[3] = -k.k1 * x;
-        if (GRAD) {
-            dY[1][0] = 0; dY[1][1] = -k.k1; dY[1][2] = 0;
-            dY[2][0] = 0; dY[2][1] = 0; dY[2][2] = k.k1;
-            dY[3][0] = -k.k1; dY[3][1] = 0; dY[3][2] = 0;
-        }
     }
     if (DEG >= 2) {
         Y[4] = k.k2a * x * y;
@@ -53,13 +46,6 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y,
         Y[6] = k.k2b * (3.0 * z * z - 1.0);
         Y[7] = -k.k2a * x * z;
         Y[8] = k.k2c * (x * x - y * y);
-        if (GRAD) {
-            dY[4][0] = k.k2a * y; dY[4][1] = k.k2a * x; dY[4][2] = 0;
-            dY[5][0] = 0; dY[5][1] = -k.k2a * z; dY[5][2] = -k.k2a * y;
-            dY[6][0] = 0; dY[6][1] = 0; dY[6][2] = 6.0 * k.k2b * z;
-            dY[7][0] = -k.k2a * z; dY[7][1] = 0; dY[7][2] = -k.k2a * x;
-            dY[8][0] = 2.0 * k.k2c * x; dY[8][1] = -2.0 * k.k2c * y; dY[8][2] = 0;
-        }
     }
     if (DEG >= 3) {
         const double zz5 = 5.0 * z * z - 1.0;
@@ -70,16 +56,39 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y,
         Y[13] = -k.k3c * x * zz5;
         Y[14] = k.k3e * z * (x * x - y * y);
         Y[15] = -k.k3a * x * (x * x - 3.0 * y * y);
-        if (GRAD) {
-            dY[9][0] = -k.k3a * 6.0 * x * y; dY[9][1] = -k.k3a * (3.0 * x * x - 3.0 * y * y); dY[9][2] = 0;
-            dY[10][0] = k.k3b * y * z; dY[10][1] = k.k3b * x * z; dY[10][2] = k.k3b * x * y;
-            dY[11][0] = 0; dY[11][1] = -k.k3c * zz5; dY[11][2] = -k.k3c * 10.0 * y * z;
-            dY[12][0] = 0; dY[12][1] = 0; dY[12][2] = k.k3d * (15.0 * z * z - 3.0);
-            dY[13][0] = -k.k3c * zz5; dY[13][1] = 0; dY[13][2] = -k.k3c * 10.0 * x * z;
-            dY[14][0] = 2.0 * k.k3e * x * z; dY[14][1] = -2.0 * k.k3e * y * z; dY[14][2] = k.k3e * (x * x - y * y);
-            dY[15][0] = -k.k3a * (3.0 * x * x - 3.0 * y * y); dY[15][1] = k.k3a * 6.0 * x * y; dY[15][2] = 0;
-        }
     }
+}
+
+// g = sum_k w[k] grad Y_k at (x, y, z): the weighted gradient of the basis,
+// accumulated term by term so that no per-basis gradient table is held.
+template <int DEG>
+__device__ __forceinline__ void sh_grad_dir(double x, double y, double z, const double *w, double *g)
+{
+    const ShConst k = sh_consts();
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    if (DEG >= 1) {
+        gy -= k.k1 * w[1];
+        gz += k.k1 * w[2];
+        gx -= k.k1 * w[3];
+    }
+    if (DEG >= 2) {
+        gx += k.k2a * y * w[4]; gy += k.k2a * x * w[4];
+        gy -= k.k2a * z * w[5]; gz -= k.k2a * y * w[5];
+        gz += 6.0 * k.k2b * z * w[6];
+        gx -= k.k2a * z * w[7]; gz -= k.k2a * x * w[7];
+        gx += 2.0 * k.k2c * x * w[8]; gy -= 2.0 * k.k2c * y * w[8];
+    }
+    if (DEG >= 3) {
+        const double zz5 = 5.0 * z * z - 1.0, d33 = 3.0 * x * x - 3.0 * y * y, xy6 = 6.0 * x * y;
+        gx -= k.k3a * xy6 * w[9]; gy -= k.k3a * d33 * w[9];
+        gx += k.k3b * y * z * w[10]; gy += k.k3b * x * z * w[10]; gz += k.k3b * x * y * w[10];
+        gy -= k.k3c * zz5 * w[11]; gz -= k.k3c * 10.0 * y * z * w[11];
+        gz += k.k3d * (15.0 * z * z - 3.0) * w[12];
+        gx -= k.k3c * zz5 * w[13]; gz -= k.k3c * 10.0 * x * z * w[13];
+        gx += 2.0 * k.k3e * x * z * w[14]; gy -= 2.0 * k.k3e * y * z * w[14]; gz += k.k3e * (x * x - y * y) * w[14];
+        gx -= k.k3a * d33 * w[15]; gy += k.k3a * xy6 * w[15];
+    }
+    g[0] = gx; g[1] = gy; g[2] = gz;
 }
 
 // Forward intermediates of one Gaussian, kept for the backward recompute.
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
             continue;
         }
         double Y[K];
-        sh_eval<DEG, false>(P.dir[0], P.dir[1], P.dir[2], Y, nullptr);
+        sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
         double col[3] = {0.5, 0.5, 0.5};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -310,20 +319,19 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
     double gcol[3] = {g_col[0], g_col[1], g_col[2]};
 
     // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
-    double Y[K], dY[K][3];
-    sh_eval<DEG, true>(P.dir[0], P.dir[1], P.dir[2], Y, dY);
-    double gdir[3] = {0.0, 0.0, 0.0};
+    double Y[K];
+    sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
     for (int ch = 0; ch < 3; ++ch) {
         double val = 0.5;
         for (int k = 0; k < K; ++k) val += (double)shi[3 * k + ch] * Y[k];
         if (val < 0.0) gcol[ch] = 0.0;
     }
-    for (int k = 0; k < K; ++k) {
-        for (int ch = 0; ch < 3; ++ch) {
-            const double w = gcol[ch] * (double)shi[3 * k + ch];
-            gdir[0] += w * dY[k][0]; gdir[1] += w * dY[k][1]; gdir[2] += w * dY[k][2];
-        }
-    }
+    // dL/d dir = sum_k (sum_ch gcol_ch sh_k,ch) grad Y_k
+    double wk[K];
+    for (int k = 0; k < K; ++k)
+        wk[k] = gcol[0] * (double)shi[3 * k] + gcol[1] * (double)shi[3 * k + 1] + gcol[2] * (double)shi[3 * k + 2];
+    double gdir[3];
+    sh_grad_dir<DEG>(P.dir[0], P.dir[1], P.dir[2], wk, gdir);
     for (int k = 0; k < K; ++k)
         for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] += (float)(gcol[ch] * Y[k]);
     double gm[3] = {0.0, 0.0, 0.0};

@@ -13,7 +13,11 @@
 // one stable radix pass on the tile row follows (one pass at 1080p); wider
 // grids store the duplicated pairs and sort them by tile id.  Every step is
 // stable and the emission follows (depth, id) order, so the result is
-// identical to the single 64-bit sort.
+// identical to the single 64-bit sort.  The depth sort also brings the tile
+// rectangles into depth order, packed into 32 bits and carried as a third
+// payload of its passes when every view is at most 256 tiles wide and high
+// (coalesced, where a gather by the sorted ids would read a whole cache line
+// per 16-byte rectangle), otherwise gathered by its last pass.
 #include "common.hpp"
 
 namespace lgs {
@@ -464,6 +468,40 @@ __global__ __launch_bounds__(kBlock) void radix_rowscan_kernel(uint32_t *__restr
     radix_rowscan_body<8>(hist, stride, n_max, n_dev, tile_n, digit_total);
 }
 
+// Tile rectangles packed in 32 bits for views at most 256 tiles wide and
+// high: first column | (width - 1) << 8 | first row << 16 | (height - 1) << 24,
+// kEmptyRect when the rectangle is empty (no valid rectangle packs to it: a
+// first column of 255 implies a width of 1).  Columns are clamped to
+// [0, 256] and rows to [0, 256) with at most 256 of them, no-ops for
+// projected rectangles of such views.
+constexpr uint32_t kEmptyRect = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t pack_rect(int4 q)
+{
+    q.x = min(max(q.x, 0), 256);
+    q.z = min(max(q.z, q.x), 256);
+    if (!(q.z > q.x && q.w > q.y)) return kEmptyRect;
+    const int y0 = min(max(q.y, 0), 255);
+    const int y1 = min(max(q.w, y0 + 1), y0 + 256);
+    return (uint32_t)q.x | ((uint32_t)(q.z - q.x - 1) << 8) | ((uint32_t)y0 << 16) | ((uint32_t)(y1 - y0 - 1) << 24);
+}
+
+__device__ __forceinline__ int4 unpack_rect(uint32_t p)
+{
+    if (p == kEmptyRect) return make_int4(0, 0, 0, 0);
+    const int x0 = (int)(p & 255u), y0 = (int)((p >> 16) & 255u);
+    return make_int4(x0, y0, x0 + (int)((p >> 8) & 255u) + 1, y0 + (int)(p >> 24) + 1);
+}
+
+// Optional third payload of a scatter pass (32 bits per element): read from
+// in, or, in the first pass, packed from the rectangle of the element's index
+// (pack); written to out in sorted order.  out == nullptr: none.
+struct AuxPayload {
+    const uint32_t *in = nullptr;
+    uint32_t *out = nullptr;
+    const int4 *pack = nullptr;
+};
+
 // Stable scatter of one block of 256 * ITEMS elements.  Wavefront w owns a
 // contiguous quarter of the block and ranks its keys in rounds of 64 against
 // its own running digit counts, so no workgroup barrier is needed while
@@ -517,7 +555,8 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
                                                            const uint32_t *__restrict__ hist_scan,
                                                            const uint32_t *__restrict__ digit_total,
                                                            int64_t stride, const int4 *__restrict__ gather_src,
-                                                           int4 *__restrict__ gather_dst, RowMap rows)
+                                                           int4 *__restrict__ gather_dst, RowMap rows,
+                                                           AuxPayload aux)
 {
     constexpr int kW = NT / 64;                             // wavefronts per workgroup
     constexpr int kTileN = NT * ITEMS;
@@ -634,6 +673,30 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
             if (gather_dst) gather_dst[pos] = gather_src[v];
         }
     }
+    if (aux.out) {
+        // the third payload through the same LDS buffer
+        uint32_t x[ITEMS];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int local = wid * kPerWave + r * 64 + lane;
+            x[r] = local < count ? (aux.in ? aux.in[start + local] : pack_rect(aux.pack[start + local])) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int local = wid * kPerWave + r * 64 + lane;
+            if (local < count) s_buf[lp[r]] = x[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int i = threadIdx.x + r * NT;
+            if (i < count) {
+                const uint32_t d = s_dig[i];
+                aux.out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = s_buf[i];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -662,11 +725,23 @@ __device__ __forceinline__ int4 col_rect(int4 q)
     return q;
 }
 
+// Rectangle reader of the column pass: int4 records (columns clamped) or
+// packed ones.
+struct RectInt4 {
+    const int4 *p;
+    __device__ __forceinline__ int4 operator()(int64_t i) const { return col_rect(p[i]); }
+};
+struct RectPacked {
+    const uint32_t *p;
+    __device__ __forceinline__ int4 operator()(int64_t i) const { return unpack_rect(p[i]); }
+};
+
 // Per-block column counts: hist[c * stride + b] = pairs of column c among the
 // Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order.  One
 // workgroup counts kHistGroup consecutive blocks (one 16-byte write per
 // column) and writes their pair total to block_pairs[workgroup].
-__global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict__ rect, int64_t n, int ncols,
+template <typename RIN>
+__global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_t n, int ncols,
                                                           uint32_t *__restrict__ hist, int64_t stride,
                                                           uint64_t *__restrict__ block_pairs)
 {
@@ -687,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const int4 *__restrict
         for (int i = 0; i < kColBlock / kBlock; ++i) {
             const int64_t r = r0 + i * kBlock + t;
             if (r < n) {
-                const int4 q = col_rect(rect[r]);
+                const int4 q = rect(r);
                 if (q.z > q.x && q.w > q.y) {
                     const uint32_t h = (uint32_t)(q.w - q.y);
                     atomicAdd(&s_d[q.x], h);
@@ -770,9 +845,9 @@ __global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restric
 // column's global start plus the column's pairs in earlier blocks and in
 // earlier chunks of this one.  Places at or past the capacity are not
 // written.
-template <int ITEMS, typename KT>
+template <int ITEMS, typename KT, typename RIN>
 __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
-    const uint32_t *__restrict__ order, const int4 *__restrict__ rect, uint64_t cap, TileGrids tg, int64_t n,
+    const uint32_t *__restrict__ order, const RIN rect, uint64_t cap, TileGrids tg, int64_t n,
     const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ col_total, int64_t stride, int ncols,
     int nbits, KT *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
@@ -802,7 +877,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     if (t < cnt) {
         const uint32_t g = order[first + t];
         const int v = tg.V > 1 ? (int)(g / tg.per_view) : 0;
-        const int4 q = col_rect(rect[first + t]);
+        const int4 q = rect(first + t);
         const bool has = q.z > q.x && q.w > q.y;
         s_xw[t] = (uint32_t)q.x | ((uint32_t)(q.z - q.x) << 16);
         s_id[t] = g;
@@ -1074,7 +1149,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 template <int ITEMS, int SCATTER_THREADS, typename KT>
 void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows)
+                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows, const AuxPayload &aux)
 {
     constexpr int kTileN = kBlock * ITEMS;
     const int64_t nb = (n_max + kTileN - 1) / kTileN;
@@ -1090,26 +1165,29 @@ void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *
         hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true, KT>), dim3((unsigned)nb),
                            dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
                            n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
-                           stride, gather_src, gather_dst, rows);
+                           stride, gather_src, gather_dst, rows, aux);
     else
         hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false, KT>), dim3((unsigned)nb),
                            dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
                            n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
-                           stride, gather_src, gather_dst, rows);
+                           stride, gather_src, gather_dst, rows, aux);
 }
 
 template <typename KT>
 void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{})
+                const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{},
+                const AuxPayload &aux = AuxPayload{})
 {
     if (n_max >= kLargeRadixFrom)
-        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows);
+        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
+                              aux);
     else if (n_max >= kMidRadixFrom)
-        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows);
+        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
+                              aux);
     else
         radix_pass_t<kRadixItems, kBlock>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                          gather_dst, rows);
+                                          gather_dst, rows, aux);
 }
 
 
@@ -1139,7 +1217,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     tg.per_view = (uint32_t)(n_per_view > 0 ? n_per_view : 1);
     tg.V = num_views;
     int64_t total_tiles = 0, total_rows = 0;
-    int ncols = 0;
+    int ncols = 0, nrows = 0;
     RowMap rows{};
     rows.V = num_views;
     for (int v = 0; v < num_views; ++v) {
@@ -1153,6 +1231,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         total_tiles += (int64_t)tiles_x[v] * tiles_y[v];
         total_rows += tiles_y[v];
         ncols = tiles_x[v] > ncols ? tiles_x[v] : ncols;
+        nrows = tiles_y[v] > nrows ? tiles_y[v] : nrows;
         LGS_REQUIRE(total_tiles < (1ll << 31), "lgs_sort: too many tiles");
     }
     LGS_REQUIRE(capacity_pairs >= 0 && capacity_pairs < (int64_t)UINT32_MAX, "lgs_sort: capacity out of range");
@@ -1170,24 +1249,45 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     SortWorkspace w = plan_workspace(static_cast<char *>(workspace), n, capacity_pairs);
     const int4 *rc = reinterpret_cast<const int4 *>(rect);
 
+    // Column-first binning (views up to kMaxCols tiles wide) sorts by the
+    // global tile row after its column pass; otherwise the pairs are
+    // duplicated and sorted by tile id.  With views at most 256 tiles high as
+    // well, the rectangles travel packed in 32 bits.
+    const bool by_column = ncols <= kMaxCols;
+    const bool packed = by_column && nrows <= 256;
+    uint32_t *rp[2] = {reinterpret_cast<uint32_t *>(w.rect_sorted), reinterpret_cast<uint32_t *>(w.rect_sorted) + n};
+
     // 1. stable sort of all Gaussians by depth bits (positive floats order
     //    like their bit patterns; culled ones hold +inf and end up last):
-    //    four 8-bit passes, the first reading the depths and implicit ids
+    //    four 8-bit passes, the first reading the depths and implicit ids.
+    //    The rectangles follow into depth order: packed, as a payload of
+    //    every pass (the first packs them from the input, in index order),
+    //    or else gathered by the last pass.
     const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
-    radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s);
+    {
+        AuxPayload aux{};
+        if (packed) {
+            aux.out = rp[0];
+            aux.pack = rc;
+        }
+        radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s, nullptr, nullptr, RowMap{}, aux);
+    }
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
-        // the last pass also moves every rectangle into depth order
+        AuxPayload aux{};
+        if (packed) {
+            aux.in = rp[a];
+            aux.out = rp[a ^ 1];
+        }
+        const bool gather = !packed && pass == 3;
         radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
-                   pass == 3 ? rc : nullptr, pass == 3 ? w.rect_sorted : nullptr);
+                   gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux);
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
-    // 2. Column-first binning (views up to kMaxCols tiles wide) sorts by the
-    //    global tile row after its column pass; otherwise the pairs are
-    //    duplicated and sorted by tile id.  The number of tile-sort passes
-    //    decides which buffer receives the pairs so that the sorted result
-    //    ends in the caller's.
-    const bool by_column = ncols <= kMaxCols;
+    const RectPacked rect_packed{rp[1]};
+    const RectInt4 rect_int4{w.rect_sorted};
+    // 2. The number of tile-sort passes decides which buffer receives the
+    //    pairs so that the sorted result ends in the caller's.
     // with fewer than 256 global rows the keys between the column and the row
     // pass fit 16 bits (row << 8 | column), and the row pass is a single one
     const bool key16 = by_column && total_rows <= 256;
@@ -1204,23 +1304,29 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         const int64_t stride = hist_stride(nbc);
         int cbits = 1;
         while ((1 << cbits) < ncols) ++cbits;
-        if (n > 0) {
-            hipLaunchKernelGGL(col_hist_kernel, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s,
-                               (const int4 *)w.rect_sorted, n, ncols, w.hist, stride, w.col_pairs);
-        }
+        if (n > 0 && packed)
+            hipLaunchKernelGGL(col_hist_kernel<RectPacked>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0,
+                               s, rect_packed, n, ncols, w.hist, stride, w.col_pairs);
+        else if (n > 0)
+            hipLaunchKernelGGL(col_hist_kernel<RectInt4>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0,
+                               s, rect_int4, n, ncols, w.hist, stride, w.col_pairs);
         const int64_t nhg = n > 0 ? stride / kHistGroup : 0;      // column-histogram workgroups
         const PairTotal pt{w.col_pairs, nhg, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
         hipLaunchKernelGGL(col_rowscan_kernel, dim3(n > 0 ? ncols + 1 : 1), dim3(kBlock), 0, s, w.hist, stride, n,
                            n > 0 ? ncols : 0, w.digit_total, pt);
-        if (n > 0 && key16)
-            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t>), dim3((unsigned)nbc), dim3(kColBlock), 0, s,
-                               order, (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
-                               (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
+        const uint32_t *hs = w.hist, *ct = w.digit_total;
+        const uint64_t cp = (uint64_t)capacity_pairs;
+        if (n > 0 && key16)                                   // 16-bit keys imply packed rectangles
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked>), dim3((unsigned)nbc),
+                               dim3(kColBlock), 0, s, order, rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits,
                                reinterpret_cast<uint16_t *>(k0), v0);
+        else if (n > 0 && packed)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked>), dim3((unsigned)nbc),
+                               dim3(kColBlock), 0, s, order, rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits,
+                               k0, v0);
         else if (n > 0)
-            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t>), dim3((unsigned)nbc), dim3(kColBlock), 0, s,
-                               order, (const int4 *)w.rect_sorted, (uint64_t)capacity_pairs, tg, n,
-                               (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, ncols, cbits,
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4>), dim3((unsigned)nbc),
+                               dim3(kColBlock), 0, s, order, rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits,
                                k0, v0);
     } else {
         // 3. pair counts in depth order, their exclusive scan (total P,

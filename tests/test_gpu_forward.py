@@ -113,6 +113,32 @@ def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
     assert np.all(rg[~nonempty] == 0)
 
 
+@pytest.mark.parametrize("tx,ty", [(256, 256), (256, 257)])
+def test_sort_extreme_rectangles(tx, ty):
+    # rectangles at the limits of the 32-bit packed form (256 x 256 tiles):
+    # the whole grid, the last column and row, full-height and full-width
+    # strips; with 257 rows the rectangles stay 16-byte records
+    rng = np.random.default_rng(12)
+    fixed = [(0, 0, tx, ty), (tx - 1, ty - 1, tx, ty), (tx - 1, 0, tx, ty), (0, ty - 1, tx, ty),
+             (0, 0, 1, 1), (3, 0, 4, ty), (0, 7, tx, 8), (5, 5, 5, 9), (2, 2, 9, 2)]
+    n = 400
+    x0 = rng.integers(0, tx, n); y0 = rng.integers(0, ty, n)
+    x1 = np.minimum(x0 + rng.integers(1, 40, n), tx); y1 = np.minimum(y0 + rng.integers(1, 40, n), ty)
+    rect = np.stack([x0, y0, x1, y1], 1).astype(np.int32)
+    rect[:len(fixed)] = np.array(fixed, np.int32)
+    vis = ((rect[:, 2] > rect[:, 0]) & (rect[:, 3] > rect[:, 1])).astype(np.int32)
+    depth = np.where(vis > 0, rng.uniform(0.5, 20, n), np.inf).astype(np.float32)
+    print(f"sort extreme rectangles tiles={tx}x{ty}", flush=True)
+    W, H = 16 * tx, 16 * ty
+    cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), W, H)
+    off, ids = O.tile_lists(vis, depth, rect, W, H)
+    p = len(ids)
+    b = R.Binner(capacity=p + 5).run(cam, R.Projected(None, None, None, to_dev(depth), to_dev(rect)))
+    assert int(b.num_pairs.item()) == p and int(b.overflow.item()) == 0
+    assert np.array_equal(_sync_np(b.tile_keys)[:p].astype(np.int64), np.repeat(np.arange(tx * ty), np.diff(off)))
+    assert np.array_equal(_sync_np(b.values)[:p], ids)
+
+
 @pytest.mark.parametrize("case", ["gaps", "one", "none", "overflow", "first_last"])
 def test_tile_ranges_write_every_tile(case):
     """lgs_tile_ranges over a buffer holding garbage: runs get [start, end),
