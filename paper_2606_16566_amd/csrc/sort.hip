@@ -341,7 +341,8 @@ template <> struct Key4<uint16_t> {
 };
 
 // Per-block digit histograms (per-wavefront sub-histograms in LDS, so the
-// atomics of one wavefront never contend with another's).  One workgroup
+// atomics of one wavefront never contend with another's, optionally split
+// further into bank-staggered copies).  One workgroup
 // counts kHistGroup consecutive blocks and writes their counts of each digit
 // as one 16-byte row segment: hist[digit * stride + block], stride a
 // multiple of kHistGroup (single 4-byte writes at a stride of a whole row
@@ -350,7 +351,7 @@ constexpr int kHistGroup = 4;
 
 inline int64_t hist_stride(int64_t nblocks) { return (nblocks + kHistGroup - 1) / kHistGroup * kHistGroup; }
 
-template <int ITEMS, typename KT>
+template <int ITEMS, typename KT, int COPIES>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict__ keys, int64_t n_max,
                                                             const uint32_t *n_dev, int shift, uint32_t mask,
                                                             uint32_t *__restrict__ hist, int64_t stride)
@@ -358,8 +359,16 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
     using V = typename Key4<KT>::V;
     constexpr int kTileN = kBlock * ITEMS;
     constexpr int kV = ITEMS / 4;                              // 4-key loads per thread and block
-    __shared__ uint32_t s_h[kWaves][kRadixBins];
+    // COPIES counters per digit and wavefront, lane l counting into copy
+    // l % COPIES; the copies are kCopyStride words apart (odd), so the lanes
+    // of one digit hit different banks: keys with few distinct digits (the
+    // top digit of a key) would otherwise serialise the LDS atomics
+    constexpr int kHistCopies = COPIES;
+    constexpr int kCopyStride = kRadixBins + (COPIES > 1 ? 1 : 0);
+    constexpr int kSubHists = kWaves * kHistCopies;
+    __shared__ uint32_t s_h[kSubHists * kCopyStride];
     const int wid = threadIdx.x >> 6, lane = __lane_id();
+    uint32_t *my_h = s_h + (wid * kHistCopies + (lane & (kHistCopies - 1))) * kCopyStride;
     const int64_t n = live_count(n_max, n_dev);
     const int64_t g0 = (int64_t)blockIdx.x * kHistGroup * kTileN;
     auto aligned = [&](int64_t start) { return (reinterpret_cast<uintptr_t>(keys + start) % sizeof(V)) == 0; };
@@ -377,8 +386,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
 #pragma unroll
     for (int j = 0; j < kHistGroup; ++j) {
         if (j + 1 < kHistGroup) load(j + 1, nxt);
-#pragma unroll
-        for (int k = 0; k < kRadixBins / 64; ++k) s_h[wid][lane + 64 * k] = 0u;
+        for (int k = threadIdx.x; k < kSubHists * kCopyStride; k += kBlock) s_h[k] = 0u;
         __syncthreads();
         const int64_t start = g0 + (int64_t)j * kTileN;
         if (start < n) {
@@ -387,17 +395,17 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
 #pragma unroll
                 for (int r = 0; r < kV; ++r) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) atomicAdd(&s_h[wid][(Key4<KT>::at(cur[r], e) >> shift) & mask], 1u);
+                    for (int e = 0; e < 4; ++e) atomicAdd(&my_h[(Key4<KT>::at(cur[r], e) >> shift) & mask], 1u);
                 }
             } else {
                 const KT *kp = keys + start;
-                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&s_h[wid][((uint32_t)kp[e] >> shift) & mask], 1u);
+                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&my_h[((uint32_t)kp[e] >> shift) & mask], 1u);
             }
         }
         __syncthreads();
         c[j] = 0u;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) c[j] += s_h[w][threadIdx.x];
+        for (int h = 0; h < kSubHists; ++h) c[j] += s_h[h * kCopyStride + threadIdx.x];
         __syncthreads();                                       // before the next block re-zeroes
 #pragma unroll
         for (int r = 0; r < kV; ++r) cur[r] = nxt[r];
@@ -1149,15 +1157,22 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 template <int ITEMS, int SCATTER_THREADS, typename KT>
 void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows, const AuxPayload &aux)
+                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows, const AuxPayload &aux, bool top)
 {
     constexpr int kTileN = kBlock * ITEMS;
     const int64_t nb = (n_max + kTileN - 1) / kTileN;
     if (nb == 0) return;
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t stride = hist_stride(nb);
-    hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT>), dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0, s, kin,
-                       n_max, n_dev, shift, mask, w.hist, stride);
+    // bank-staggered counter copies where digits repeat within a wavefront:
+    // the top digit of a key, and long inputs (sorted pairs, stacked views)
+    const dim3 hg((unsigned)(stride / kHistGroup));
+    if (top || ITEMS >= 16)
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
+                           w.hist, stride);
+    else
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
+                           w.hist, stride);
     hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
                        kTileN, w.digit_total);
     constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
@@ -1177,17 +1192,17 @@ template <typename KT>
 void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
                 const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{},
-                const AuxPayload &aux = AuxPayload{})
+                const AuxPayload &aux = AuxPayload{}, bool top = false)
 {
     if (n_max >= kLargeRadixFrom)
         radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
-                              aux);
+                              aux, top);
     else if (n_max >= kMidRadixFrom)
         radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
-                              aux);
+                              aux, top);
     else
         radix_pass_t<kRadixItems, kBlock>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                          gather_dst, rows, aux);
+                                          gather_dst, rows, aux, top);
 }
 
 
@@ -1281,7 +1296,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         }
         const bool gather = !packed && pass == 3;
         radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
-                   gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux);
+                   gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux, pass == 3);
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     const RectPacked rect_packed{rp[1]};
@@ -1353,15 +1368,18 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     const int base_shift = by_column ? kColBits : 0;
     if (key16) {
         radix_pass(reinterpret_cast<const uint16_t *>(k0), v0, k1, v1, capacity_pairs, w.n_eff, kColBits, bits, w, s,
-                   nullptr, nullptr, rows);
+                   nullptr, nullptr, rows, AuxPayload{}, true);
     } else {
         for (int pass = 0, shift = 0; pass < passes; ++pass) {
             const int b = (bits - shift + (passes - pass) - 1) / (passes - pass);
             const RowMap map = by_column && pass == passes - 1 ? rows : RowMap{};
+            const bool top = pass == passes - 1;
             if (pass & 1)
-                radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
+                radix_pass(k1, v1, k0, v0, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map,
+                           AuxPayload{}, top);
             else
-                radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map);
+                radix_pass(k0, v0, k1, v1, capacity_pairs, w.n_eff, base_shift + shift, b, w, s, nullptr, nullptr, map,
+                           AuxPayload{}, top);
             shift += b;
         }
     }
