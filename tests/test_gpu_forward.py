@@ -90,6 +90,9 @@ def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True, wide=False):
     (11, 20000, 40, 300, False, True),
     # above 2^22 and 2^25 pairs: the larger radix tiers
     (4, 1000000, 120, 68, False, False), (5, 800000, 300, 260, True, False),
+    # above 2^22 Gaussians in the column path (the middle radix tier for the
+    # depth sort), with heavily tied depths
+    (13, 4300000, 120, 68, True, False),
     pytest.param(6, 6000000, 300, 260, False, False, marks=pytest.mark.slow)])
 def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
     vis, depth, rect = _synthetic_bins(seed, n, tx, ty, ties, wide)
