@@ -208,36 +208,36 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 const float s32 = (float)s;
                 const float raw = __builtin_amdgcn_exp2f(s32);
                 const bool act = pos1 <= last && s32 >= kLog2AlphaMin;
+                if (__ballot(act) == 0ull) continue;          // no lane of the wavefront takes this Gaussian
+                // Branch-free from here: a lane that does not take the Gaussian
+                // uses alpha = 0, so T (times 1/(1 - 0) = 1) and R are unchanged
+                // and every partial is zero.
+                const bool clamped = !(raw < kAlphaMax);
+                const float alf = act ? (clamped ? kAlphaMax : raw) : 0.f;
+                const double al = (double)alf;
+                const double inv = recip(1.0 - al);
+                T = T * inv;                                     // T before this Gaussian
+                const double w = al * T;
+                const float4 f = s_c[k];
+                const double dLda = (double)gc0 * ((double)f.x * T - R0 * inv)
+                                    + (double)gc1 * ((double)f.y * T - R1 * inv)
+                                    + (double)gc2 * ((double)f.z * T - R2 * inv) - gt * Tf * inv;
+                R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
+                // the per-pixel partials are single terms (no long sums):
+                // float is enough for them; no gradient through the clamp
                 float g[kNG];
-#pragma unroll
-                for (int f = 0; f < kNG; ++f) g[f] = 0.f;
-                if (act) {
-                    const bool clamped = !(raw < kAlphaMax);
-                    const double al = clamped ? (double)kAlphaMax : (double)raw;
-                    const double inv = recip(1.0 - al);
-                    T = T * inv;                                 // T before this Gaussian
-                    const double w = al * T;
-                    const float4 f = s_c[k];
-                    double dLda = (double)gc0 * ((double)f.x * T - R0 * inv) + (double)gc1 * ((double)f.y * T - R1 * inv)
-                                  + (double)gc2 * ((double)f.z * T - R2 * inv) - gt * Tf * inv;
-                    R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
-                    // the per-pixel partials are single terms (no long sums):
-                    // float is enough for them
-                    const float wf = (float)w;
-                    g[6] = gc0 * wf; g[7] = gc1 * wf; g[8] = gc2 * wf;
-                    if (!clamped) {
-                        const float alf = (float)al, dLdaf = (float)dLda;
-                        const float dLdq = -0.5f * alf * dLdaf;
-                        const float m2 = -2.0f * dLdq;
-                        g[0] = m2 * fmaf(co.x, dx, co.y * dy);
-                        g[1] = m2 * fmaf(co.y, dx, co.z * dy);
-                        g[2] = dLdq * dx * dx;
-                        g[3] = 2.0f * dLdq * dx * dy;
-                        g[4] = dLdq * dy * dy;
-                        g[5] = dLdaf * raw * __builtin_amdgcn_rcpf(co.w);
-                    }
-                }
-                if (__ballot(act) != 0ull) {
+                const float wf = (float)w;
+                g[6] = gc0 * wf; g[7] = gc1 * wf; g[8] = gc2 * wf;
+                const float dLdaf = (act && !clamped) ? (float)dLda : 0.f;
+                const float dLdq = -0.5f * alf * dLdaf;
+                const float m2 = -2.0f * dLdq;
+                g[0] = m2 * fmaf(co.x, dx, co.y * dy);
+                g[1] = m2 * fmaf(co.y, dx, co.z * dy);
+                g[2] = dLdq * dx * dx;
+                g[3] = 2.0f * dLdq * dx * dy;
+                g[4] = dLdq * dy * dy;
+                g[5] = dLdaf * raw * __builtin_amdgcn_rcpf(co.w);
+                {
                     // row sums of the nine components: even lane 2f of each
                     // row holds component f < 8, lane 1 component 8
                     static_assert(kNG == 9, "row_sums9 handles nine components");
