@@ -128,19 +128,46 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     const uint2 range = a.ranges[tc.tile];
     const uint32_t end = range.x + (uint32_t)bmax;
 
+    // Two-deep software pipeline over the batches (back to front, kBlock
+    // entries each): while batch i is replayed, thread t holds the attributes
+    // of entry t of batch i + 1 and the Gaussian id of entry t of batch i + 2
+    // in registers, so the dependent gathers overlap the replay.
+    auto batch_start = [&](int64_t be) { return (uint32_t)max((int64_t)range.x, be - kBlock); };
+    auto fetch_id = [&](int64_t be) -> uint32_t {
+        const uint32_t bs = batch_start(be);
+        return (be > (int64_t)range.x && (int64_t)threadIdx.x < be - (int64_t)bs) ? a.values[bs + threadIdx.x] : 0u;
+    };
+    struct Attr {
+        float2 m;
+        float4 co;
+        float r, gg, b;
+    };
+    auto fetch_attr = [&](int64_t be, uint32_t g) -> Attr {
+        Attr at{make_float2(0.f, 0.f), make_float4(0.f, 0.f, 0.f, 1.f), 0.f, 0.f, 0.f};
+        if (be > (int64_t)range.x && (int64_t)threadIdx.x < be - (int64_t)batch_start(be)) {
+            at.m = a.means2d[g];
+            at.co = a.conic_opacity[g];
+            at.r = a.rgb[3 * g]; at.gg = a.rgb[3 * g + 1]; at.b = a.rgb[3 * g + 2];
+        }
+        return at;
+    };
+    uint32_t id_cur = fetch_id(end);
+    Attr at_cur = fetch_attr(end, id_cur);
+    uint32_t id_next = fetch_id((int64_t)end - kBlock);
+
     for (int64_t bend = end; bend > (int64_t)range.x; bend -= kBlock) {
         const uint32_t bstart = (uint32_t)max((int64_t)range.x, bend - kBlock);
         const int nb = (int)(bend - bstart);
         __syncthreads();                                   // previous batch fully flushed
         if ((int)threadIdx.x < nb) {
             const int k = threadIdx.x;
-            const uint32_t g = a.values[bstart + k];
-            const float2 m = a.means2d[g];
-            const float4 co = a.conic_opacity[g];
+            const uint32_t g = id_cur;
+            const float2 m = at_cur.m;
+            const float4 co = at_cur.co;
             s_id[k] = g;
             s_mu[k] = m;
             s_co[k] = co;
-            s_c[k] = make_float4(a.rgb[3 * g], a.rgb[3 * g + 1], a.rgb[3 * g + 2], 0.f);
+            s_c[k] = make_float4(at_cur.r, at_cur.gg, at_cur.b, 0.f);
             const float lo = __builtin_amdgcn_logf(co.w);
             if (LOCAL) {
                 s_v[k] = hoist<double>(m, co, lo, tc.ox, tc.oy);
@@ -181,6 +208,10 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             for (int f = 0; f < kNG; ++f) s_g[f][k] = 0.f;
         }
         __syncthreads();
+        // the next batches' loads, in flight during this one's replay
+        id_cur = id_next;
+        at_cur = fetch_attr(bend - kBlock, id_cur);
+        id_next = fetch_id(bend - 2 * (int64_t)kBlock);
 
         // wavefront's own range: skip entries past its last contributor
         const int wlimit = (int)min((int64_t)nb, (int64_t)range.x + wmax - (int64_t)bstart);
