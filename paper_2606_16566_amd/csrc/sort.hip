@@ -29,11 +29,11 @@ constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
 // three tiers by input length: 2048 below 2^22 elements, so that enough
 // blocks exist to fill the chip; 4096 up to 2^25; 8192 beyond, which cuts
 // the per-block histogram traffic and lengthens the digit runs that the
-// scatter writes contiguously.  Every tier scatters with 512-thread
-// workgroups (4, 8 and 16 elements per thread), which keeps registers and LDS
-// low enough for 8 and 4 waves per SIMD in the larger tiers and gives the
-// small one twice the waves of a 256-thread launch.  Each tier was the
-// fastest measured at its size.
+// scatter writes contiguously.  The scatters use 512-thread workgroups (4
+// and 8 elements per thread) in the two smaller tiers and 1024 threads (8
+// elements each) in the top one: more waves per block than the histogram's
+// 256 threads, with registers and LDS low enough for several resident
+// blocks.  Each tier was the fastest measured at its size.
 constexpr int kRadixItems = 8;                         // smallest tier
 constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
 constexpr int64_t kMidRadixFrom = 1 << 22;             // elements
@@ -1196,7 +1196,7 @@ void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vo
                 const AuxPayload &aux = AuxPayload{}, bool top = false)
 {
     if (n_max >= kLargeRadixFrom)
-        radix_pass_t<32, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
+        radix_pass_t<32, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
                               aux, top);
     else if (n_max >= kMidRadixFrom)
         radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
