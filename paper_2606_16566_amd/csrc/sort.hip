@@ -343,16 +343,16 @@ template <> struct Key4<uint16_t> {
 
 // Per-block digit histograms (per-wavefront sub-histograms in LDS, so the
 // atomics of one wavefront never contend with another's, optionally split
-// further into bank-staggered copies).  One workgroup
-// counts kHistGroup consecutive blocks and writes their counts of each digit
-// as one 16-byte row segment: hist[digit * stride + block], stride a
-// multiple of kHistGroup (single 4-byte writes at a stride of a whole row
-// would each cost a partial cache-line write).
+// further into bank-staggered copies).  One workgroup counts HG consecutive
+// blocks: with HG = kHistGroup it writes their counts of each digit as one
+// 16-byte row segment, hist[digit * stride + block], stride a multiple of
+// kHistGroup (single 4-byte writes at a stride of a whole row would each cost
+// a partial cache-line write); short inputs use HG = 1 for more workgroups.
 constexpr int kHistGroup = 4;
 
 inline int64_t hist_stride(int64_t nblocks) { return (nblocks + kHistGroup - 1) / kHistGroup * kHistGroup; }
 
-template <int ITEMS, typename KT, int COPIES>
+template <int ITEMS, typename KT, int COPIES, int HG>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict__ keys, int64_t n_max,
                                                             const uint32_t *n_dev, int shift, uint32_t mask,
                                                             uint32_t *__restrict__ hist, int64_t stride)
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
     const int wid = threadIdx.x >> 6, lane = __lane_id();
     uint32_t *my_h = s_h + (wid * kHistCopies + (lane & (kHistCopies - 1))) * kCopyStride;
     const int64_t n = live_count(n_max, n_dev);
-    const int64_t g0 = (int64_t)blockIdx.x * kHistGroup * kTileN;
+    const int64_t g0 = (int64_t)blockIdx.x * HG * kTileN;
     auto aligned = [&](int64_t start) { return (reinterpret_cast<uintptr_t>(keys + start) % sizeof(V)) == 0; };
     // the keys of block j + 1 are in flight while block j is counted
     auto load = [&](int j, V *v) {
@@ -383,10 +383,10 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
     };
     V cur[kV], nxt[kV];
     load(0, cur);
-    uint32_t c[kHistGroup];
+    uint32_t c[HG];
 #pragma unroll
-    for (int j = 0; j < kHistGroup; ++j) {
-        if (j + 1 < kHistGroup) load(j + 1, nxt);
+    for (int j = 0; j < HG; ++j) {
+        if (j + 1 < HG) load(j + 1, nxt);
         for (int k = threadIdx.x; k < kSubHists * kCopyStride; k += kBlock) s_h[k] = 0u;
         __syncthreads();
         const int64_t start = g0 + (int64_t)j * kTileN;
@@ -411,8 +411,11 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
 #pragma unroll
         for (int r = 0; r < kV; ++r) cur[r] = nxt[r];
     }
-    *reinterpret_cast<uint4 *>(hist + (int64_t)threadIdx.x * stride + (int64_t)blockIdx.x * kHistGroup) =
-        make_uint4(c[0], c[1], c[2], c[3]);
+    if constexpr (HG == kHistGroup)
+        *reinterpret_cast<uint4 *>(hist + (int64_t)threadIdx.x * stride + (int64_t)blockIdx.x * kHistGroup) =
+            make_uint4(c[0], c[1], c[2], c[3]);
+    else
+        hist[(int64_t)threadIdx.x * stride + blockIdx.x] = c[0];
 }
 
 // Exclusive scan, in place, of one row of per-block counts over the blocks
@@ -1167,13 +1170,22 @@ void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *
     const int64_t stride = hist_stride(nb);
     // bank-staggered counter copies where digits repeat within a wavefront:
     // the top digit of a key, and long inputs (sorted pairs, stacked views)
-    const dim3 hg((unsigned)(stride / kHistGroup));
-    if (top || ITEMS >= 16)
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
-                           w.hist, stride);
+    // few blocks (short inputs): one block per workgroup, so that more of the
+    // chip counts; else kHistGroup blocks per workgroup and 16-byte writes
+    const bool copies = top || ITEMS >= 16, few = nb < 2048;
+    const dim3 hg((unsigned)(few ? nb : stride / kHistGroup));
+    if (copies && few)
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
+                           mask, w.hist, stride);
+    else if (copies)
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, kHistGroup>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
+                           shift, mask, w.hist, stride);
+    else if (few)
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
+                           mask, w.hist, stride);
     else
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift, mask,
-                           w.hist, stride);
+        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, kHistGroup>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
+                           shift, mask, w.hist, stride);
     hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
                        kTileN, w.digit_total);
     constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
