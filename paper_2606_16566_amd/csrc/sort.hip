@@ -29,11 +29,11 @@ constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
 // three tiers by input length: 2048 below 2^22 elements, so that enough
 // blocks exist to fill the chip; 4096 up to 2^25; 8192 beyond, which cuts
 // the per-block histogram traffic and lengthens the digit runs that the
-// scatter writes contiguously.  The scatters use 512-thread workgroups (4
-// and 8 elements per thread) in the two smaller tiers and 1024 threads (8
-// elements each) in the top one: more waves per block than the histogram's
-// 256 threads, with registers and LDS low enough for several resident
-// blocks.  Each tier was the fastest measured at its size.
+// scatter writes contiguously.  The scatters use 1024-thread workgroups (2
+// elements per thread) in the small tier, 512 threads (8 each) in the middle
+// one and 1024 threads (8 each) in the top one: more waves per block than the
+// histogram's 256 threads, with registers and LDS low enough for several
+// resident blocks.  Each tier was the fastest measured at its size.
 constexpr int kRadixItems = 8;                         // smallest tier
 constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
 constexpr int64_t kMidRadixFrom = 1 << 22;             // elements
@@ -1214,7 +1214,7 @@ void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vo
         radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
                               aux, top);
     else
-        radix_pass_t<kRadixItems, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
+        radix_pass_t<kRadixItems, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
                                           gather_dst, rows, aux, top);
 }
 
