@@ -26,18 +26,17 @@ namespace {
 constexpr int kScanItems = 8;                          // per thread
 constexpr int kScanTile = kBlock * kScanItems;         // 2048 per block
 // Radix blocks (one histogram partition each) hold 256 * ITEMS elements, in
-// three tiers by input length: 2048 below 2^22 elements, so that enough
-// blocks exist to fill the chip; 4096 up to 2^25; 8192 beyond, which cuts
-// the per-block histogram traffic and lengthens the digit runs that the
-// scatter writes contiguously.  The scatters use 1024-thread workgroups (2
-// elements per thread) in the small tier, 512 threads (8 each) in the middle
-// one and 1024 threads (8 each) in the top one: more waves per block than the
-// histogram's 256 threads, with registers and LDS low enough for several
-// resident blocks.  Each tier was the fastest measured at its size.
+// two tiers by input length: 2048 below 2^22 elements, so that enough blocks
+// exist to fill the chip; 8192 beyond, which cuts the per-block histogram
+// traffic and lengthens the digit runs that the scatter writes contiguously.
+// The scatters use 1024-thread workgroups (2 and 8 elements per thread): more
+// waves per block than the histogram's 256 threads, with registers and LDS
+// low enough for two resident blocks per CU.  Each tier was the fastest
+// measured at its size (a middle tier of 4096 on 512 threads was slower from
+// 2^22 up).
 constexpr int kRadixItems = 8;                         // smallest tier
 constexpr int kRadixTile = kBlock * kRadixItems;       // 2048 per block
-constexpr int64_t kMidRadixFrom = 1 << 22;             // elements
-constexpr int64_t kLargeRadixFrom = 1 << 25;           // elements
+constexpr int64_t kLargeRadixFrom = 1 << 22;           // elements
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kWaves = kBlock / 64;
@@ -1209,13 +1208,10 @@ void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vo
 {
     if (n_max >= kLargeRadixFrom)
         radix_pass_t<32, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
-                              aux, top);
-    else if (n_max >= kMidRadixFrom)
-        radix_pass_t<16, 512>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
-                              aux, top);
+                               aux, top);
     else
         radix_pass_t<kRadixItems, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                          gather_dst, rows, aux, top);
+                                        gather_dst, rows, aux, top);
 }
 
 

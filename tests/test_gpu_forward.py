@@ -88,9 +88,9 @@ def _synthetic_bins(seed, n, tiles_x, tiles_y, ties=True, wide=False):
     (8, 3000, 256, 30, False, True), (10, 20000, 37, 200, True, True),
     # more than 256 tile rows: 32-bit keys between the column and row passes
     (11, 20000, 40, 300, False, True),
-    # above 2^22 and 2^25 pairs: the larger radix tiers
+    # above 2^22 and 2^25 pairs: the larger radix tier
     (4, 1000000, 120, 68, False, False), (5, 800000, 300, 260, True, False),
-    # above 2^22 Gaussians in the column path (the middle radix tier for the
+    # above 2^22 Gaussians in the column path (the larger radix tier for the
     # depth sort), with heavily tied depths
     (13, 4300000, 120, 68, True, False),
     pytest.param(6, 6000000, 300, 260, False, False, marks=pytest.mark.slow)])
