@@ -434,14 +434,17 @@ static double conic_q(const double *K, double dx, double dy)
 /*
  * Blend one pixel over `list` (ids in front-to-back order).  Writes colour,
  * final T, the 1-based list position and the id of the last blended
- * Gaussian (0 / -1 if none), the number blended, and the smallest decision
- * margin in log space over all alpha-floor and termination tests.
+ * Gaussian (0 / -1 if none), the number blended, the smallest decision
+ * margin in log space over all alpha-floor and termination tests (the
+ * forward's only discrete decisions), and the smallest log-space distance of
+ * a blended Gaussian's unclamped alpha from the 0.99 clamp (where only the
+ * derivative switches).
  */
 static void blend_pixel(const splats_t *S, const int32_t *list, int64_t len, double px, double py,
                         double *C, double *Tout, int32_t *last_pos, int32_t *last_id, int32_t *count,
-                        double *margin)
+                        double *margin, double *cmargin)
 {
-    double T = 1.0, acc[3] = { 0, 0, 0 }, mmin = INFINITY;
+    double T = 1.0, acc[3] = { 0, 0, 0 }, mmin = INFINITY, cmin = INFINITY;
     int32_t lp = 0, lid = -1, cnt = 0;
     for (int64_t k = 0; k < len; ++k) {
         int32_t g = list[k];
@@ -454,10 +457,10 @@ static void blend_pixel(const splats_t *S, const int32_t *list, int64_t len, dou
         if (m1 < mmin) mmin = m1;
         double alpha = a_raw < ALPHA_MAX ? a_raw : ALPHA_MAX;
         if (alpha < ALPHA_MIN) continue;
-        /* the clamp at 0.99 does not change the colour continuously, but its
-           derivative switches there */
+        /* min(0.99, .) is continuous, so the clamp decides nothing in the
+           forward; only the derivative switches there (gradient tests) */
         double m3 = fabs(la - log(ALPHA_MAX));
-        if (m3 < mmin) mmin = m3;
+        if (m3 < cmin) cmin = m3;
         double test = T * (1.0 - alpha);
         double m2 = fabs(log(test) - log(T_MIN));
         if (m2 < mmin) mmin = m2;
@@ -468,17 +471,19 @@ static void blend_pixel(const splats_t *S, const int32_t *list, int64_t len, dou
     }
     for (int c = 0; c < 3; ++c) C[c] = acc[c] + T * S->bg[c];
     *Tout = T; *last_pos = lp; *last_id = lid; *count = cnt; *margin = mmin;
+    if (cmargin) *cmargin = cmin;
 }
 
 /*
  * oracle_render_untiled: the plain definition -- every pixel blends every
  * visible Gaussian in ascending (depth, id) order.  Outputs image [3,H,W],
- * T [H,W], last contributing id [H,W], contributor count [H,W], margin [H,W].
+ * T [H,W], last contributing id [H,W], contributor count [H,W], decision
+ * margin [H,W] and clamp margin [H,W] (NULL: not written).
  */
 void oracle_render_untiled(int W, int H, int64_t n, const int32_t *visible, const float *depth,
                            const double *means2d, const double *conic, const double *opacity,
                            const double *rgb, const double *bg, double *image, double *T_out,
-                           int32_t *last_id, int32_t *count, double *margin)
+                           int32_t *last_id, int32_t *count, double *margin, double *cmargin)
 {
     splats_t S = { means2d, conic, opacity, rgb, { bg[0], bg[1], bg[2] } };
     dkey *order = (dkey *)malloc(sizeof(dkey) * (n > 0 ? n : 1));
@@ -493,7 +498,8 @@ void oracle_render_untiled(int W, int H, int64_t n, const int32_t *visible, cons
         for (int x = 0; x < W; ++x) {
             int64_t p = (int64_t)y * W + x;
             double C[3]; int32_t lp;
-            blend_pixel(&S, list, m, x, y, C, &T_out[p], &lp, &last_id[p], &count[p], &margin[p]);
+            blend_pixel(&S, list, m, x, y, C, &T_out[p], &lp, &last_id[p], &count[p], &margin[p],
+                        cmargin ? &cmargin[p] : NULL);
             for (int c = 0; c < 3; ++c) image[c * HW + p] = C[c];
         }
     free(list);
@@ -510,7 +516,7 @@ void oracle_render_tiled(int W, int H, const int64_t *offsets, const int32_t *id
                          const double *means2d, const double *conic, const double *opacity,
                          const double *rgb, const double *bg, const int32_t *pix, int64_t npix,
                          double *image, double *T_out, int32_t *last_pos, int32_t *last_id,
-                         int32_t *count, double *margin)
+                         int32_t *count, double *margin, double *cmargin)
 {
     splats_t S = { means2d, conic, opacity, rgb, { bg[0], bg[1], bg[2] } };
     int tiles_x = (W + TILE - 1) / TILE;
@@ -521,7 +527,7 @@ void oracle_render_tiled(int W, int H, const int64_t *offsets, const int32_t *id
         int64_t t = (int64_t)(y / TILE) * tiles_x + x / TILE;
         double C[3];
         blend_pixel(&S, ids + offsets[t], offsets[t + 1] - offsets[t], x, y, C, &T_out[s], &last_pos[s],
-                    &last_id[s], &count[s], &margin[s]);
+                    &last_id[s], &count[s], &margin[s], cmargin ? &cmargin[s] : NULL);
         for (int c = 0; c < 3; ++c) image[c * total + s] = C[c];
     }
 }

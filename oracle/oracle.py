@@ -145,12 +145,12 @@ def render_untiled(width, height, visible, depth, means2d, conic, opacity, rgb, 
     hw = width * height
     out = dict(image=np.zeros((3, height, width)), T=np.zeros((height, width)),
                last_id=np.zeros((height, width), np.int32), count=np.zeros((height, width), np.int32),
-               margin=np.zeros((height, width)))
+               margin=np.zeros((height, width)), clamp_margin=np.zeros((height, width)))
     lib().oracle_render_untiled(C.c_int(width), C.c_int(height), C.c_int64(n),
                                 _p(np.ascontiguousarray(visible, np.int32)), _p(_f32(depth)),
                                 _p(_f64(means2d)), _p(_f64(conic)), _p(_f64(opacity)), _p(_f64(rgb)),
                                 _p(_bg(bg)), _p(out["image"]), _p(out["T"]), _p(out["last_id"]),
-                                _p(out["count"]), _p(out["margin"]))
+                                _p(out["count"]), _p(out["margin"]), _p(out["clamp_margin"]))
     assert hw == out["T"].size
     return out
 
@@ -168,13 +168,13 @@ def render_tiled(width, height, offsets, ids, means2d, conic, opacity, rgb, bg=(
         shape2 = (m,)
     out = dict(image=np.zeros((3,) + shape2), T=np.zeros(shape2), last_pos=np.zeros(shape2, np.int32),
                last_id=np.zeros(shape2, np.int32), count=np.zeros(shape2, np.int32),
-               margin=np.zeros(shape2))
+               margin=np.zeros(shape2), clamp_margin=np.zeros(shape2))
     ids = np.ascontiguousarray(ids, np.int32) if len(ids) else np.zeros(1, np.int32)
     lib().oracle_render_tiled(C.c_int(width), C.c_int(height), _p(np.ascontiguousarray(offsets, np.int64)),
                               _p(ids), _p(_f64(means2d)), _p(_f64(conic)), _p(_f64(opacity)),
                               _p(_f64(rgb)), _p(_bg(bg)), None if pix is None else _p(pix), C.c_int64(m),
                               _p(out["image"]), _p(out["T"]), _p(out["last_pos"]), _p(out["last_id"]),
-                              _p(out["count"]), _p(out["margin"]))
+                              _p(out["count"]), _p(out["margin"]), _p(out["clamp_margin"]))
     return out
 
 
@@ -194,10 +194,25 @@ def render_backward(width, height, offsets, ids, means2d, conic, opacity, rgb, g
 # ---------------------------------------------------------------------------
 # whole pipeline helpers
 # ---------------------------------------------------------------------------
-def render_scene(scene, view=0, proj=None, tiled=True) -> dict:
-    """Project and blend a whole scene in FP64 from its raw parameters."""
+def stored_projection(pr) -> dict:
+    """The projection as the rasterizer's interface stores it: the FP64
+    projected attributes (mean, conic, opacity, colour) rounded to float32 and
+    upcast exactly; visibility, depth keys and tile rectangles unchanged.  The
+    blend of these is the plain definition applied to float32 projected
+    splats, which is what the render stage receives."""
+    out = dict(pr)
+    for k in ("means2d", "conic", "opacity", "rgb"):
+        out[k] = np.asarray(pr[k], np.float64).astype(np.float32).astype(np.float64)
+    return out
+
+
+def render_scene(scene, view=0, proj=None, tiled=True, stored=False) -> dict:
+    """Project and blend a whole scene in FP64 from its raw parameters
+    (stored=True: blend the float32-stored projection, see stored_projection)."""
     cam = scene.cameras[view]
     pr = proj if proj is not None else project_scene(scene, view)
+    if stored:
+        pr = stored_projection(pr)
     if tiled:
         off, ids = tile_lists(pr["visible"], pr["depth"], pr["rect"], cam.width, cam.height)
         out = render_tiled(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"],
@@ -210,13 +225,17 @@ def render_scene(scene, view=0, proj=None, tiled=True) -> dict:
     return out
 
 
-def scene_gradients(scene, gC, gT=None, view=0) -> dict:
-    """dL/d(raw parameters) for L = sum(gC * image) + sum(gT * T_final)."""
+def scene_gradients(scene, gC, gT=None, view=0, stored=False) -> dict:
+    """dL/d(raw parameters) for L = sum(gC * image) + sum(gT * T_final)
+    (stored=True: the blend's gradient is taken at the float32-stored
+    projection, see stored_projection; the chain through the projection is
+    FP64 either way)."""
     cam = scene.cameras[view]
     pr = project_scene(scene, view)
     off, ids = tile_lists(pr["visible"], pr["depth"], pr["rect"], cam.width, cam.height)
-    g2 = render_backward(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"],
-                         pr["rgb"], gC, gT, cam.bg)
+    bl = stored_projection(pr) if stored else pr
+    g2 = render_backward(cam.width, cam.height, off, ids, bl["means2d"], bl["conic"], bl["opacity"],
+                         bl["rgb"], gC, gT, cam.bg)
     g3 = project_backward(cam, scene.means3d, scene.log_scales, scene.quats, scene.opacity_logits,
                           scene.sh, g2["means2d"], g2["conic"], g2["opacity"], g2["rgb"])
     g3["projected"] = g2
@@ -237,3 +256,10 @@ def flagged(margin, guard):
     """Pixels whose blend took a skip / stop decision within `guard` (log
     space) of its threshold: either outcome is a correct result there."""
     return np.asarray(margin) < guard
+
+
+def grad_flagged(out, guard):
+    """Pixels to leave out of gradient comparisons: a skip / stop decision or
+    the 0.99 clamp of a blended Gaussian (where the derivative switches)
+    within `guard` (log space) of its threshold."""
+    return (np.asarray(out["margin"]) < guard) | (np.asarray(out["clamp_margin"]) < guard)

@@ -1,9 +1,10 @@
 """GPU parity of the gradient path against the FP64 oracle.
 
-Tolerance: for each parameter tensor, ||g - g*|| / ||g*|| <= 1e-3 and
-elementwise |g - g*| <= 1e-3 * max(|g*|, 1e-3 * max|g*|).  Pixels whose
-skip / stop / clamp decisions lie within the guard of their thresholds get a
-zero incoming gradient on both sides (either decision is correct there).
+Tolerance: for each parameter tensor, ||g - g*|| / ||g*|| <= 1e-3 and, for
+every element, |g - g*| <= 1e-3 * max(|g*|, 1e-3 * max|g*|).  Pixels whose
+skip / stop decisions or 0.99 clamp lie within the guard of their thresholds
+get a zero incoming gradient on both sides (either decision is correct there,
+and such a pixel then contributes nothing to any gradient).
 """
 import numpy as np
 import pytest
@@ -33,8 +34,9 @@ def assert_grad_close(got, want, name, tol=GRAD_TOL):
         return
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert rel <= tol, (name, rel)
-    bad = np.abs(got - want) > tol * np.maximum(np.abs(want), 1e-3 * scale)
-    assert bad.mean() <= 1e-4, (name, bad.sum(), bad.size)
+    err = np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * scale)
+    print(f"  {name}: relative norm error {rel:.2e}, worst element {err.max():.2e}", flush=True)
+    assert err.max() <= tol, (name, int((err > tol).sum()), err.size, float(err.max()))
 
 
 @pytest.mark.parametrize("seed,W,H,n", [(0, 96, 64, 2000), (1, 160, 128, 12000), (2, 33, 47, 300)])
@@ -48,7 +50,9 @@ def test_render_backward_parity(seed, W, H, n, variant):
     rng = np.random.default_rng(seed)
     gC = rng.standard_normal((3, H, W)).astype(np.float32)
     gT = rng.standard_normal((H, W)).astype(np.float32)
-    flag = O.flagged(ref["margin"], 1e-5)
+    flag = O.grad_flagged(ref, 1e-5)
+    print(f"render backward {variant} seed={seed}: flagged {int(flag.sum())}/{flag.size}", flush=True)
+    assert flag.mean() <= 1e-3
     gC[:, flag] = 0.0
     gT[flag] = 0.0
     want = O.render_backward(W, H, off, ids, cen, con, op, col, gC, gT, cam.bg)
@@ -88,21 +92,23 @@ def test_l1_loss_kernel():
     assert np.array_equal(_np(grad), want.astype(np.float32).astype(np.float64))
 
 
-def _scene_grad_check(sc, guard=1e-3, variant="local", fd_params=0, seed=0):
+def _scene_grad_check(sc, guard=1e-5, variant="local", fd_params=0, seed=0):
     cam = sc.cameras[0]
-    ref = O.render_scene(sc)
+    ref = O.render_scene(sc, stored=True)
     target = scenes.make_target(cam.height, cam.width, 100 + seed)
     ps = [p.requires_grad_() for p in scene_tensors(sc)]
     img, T, nc = R.LocalGSFunction.apply(*ps, cam, variant, None)
     loss, gimg = R.l1_loss(img.detach().contiguous(), to_dev(target))
     # incoming gradient: the L1 gradient, zeroed where a decision is ambiguous
     # and where the L1 sign itself is within rounding
-    flag = O.flagged(ref["margin"], guard)
+    flag = O.grad_flagged(ref, guard)
+    print(f"scene gradients {variant} n={sc.n}: flagged {int(flag.sum())}/{flag.size}", flush=True)
+    assert flag.mean() <= 1e-3
     g = _np(gimg).astype(np.float32)
     g[:, flag] = 0.0
     g[np.abs(ref["image"] - target) < 1e-4] = 0.0
     img.backward(to_dev(g))
-    want = O.scene_gradients(sc, g.astype(np.float64))
+    want = O.scene_gradients(sc, g.astype(np.float64), stored=True)
     names = ("means3d", "log_scales", "quats", "opacity_logits", "sh")
     for p, k in zip(ps, names):
         assert_grad_close(_np(p.grad), want[k], k)

@@ -116,8 +116,9 @@ def test_batch_view_matches_oracle():
     vb.forward(params)
     torch.cuda.synchronize()
     for v in range(len(cams)):
-        ref = O.render_scene(sc, view=v)
+        ref = O.render_scene(sc, view=v, stored=True)
         flag = O.flagged(ref["margin"], 1e-5)
+        assert flag.mean() <= 1e-3
         got = vb.image(v).cpu().numpy().astype(np.float64)
         err = np.abs(got - ref["image"])[:, ~flag]
         assert err.size > 0 and err.max() <= 2e-4, (v, err.max())

@@ -23,8 +23,39 @@ pytestmark = pytest.mark.gpu
 
 TOL_ORACLE = 2e-4
 TOL_LADDER = 1e-6
-GUARD_RENDER = 1e-5       # decision margin (log space) for render-only inputs
-GUARD_E2E = 1e-3          # includes float32 rounding of projected means
+# Decision guards (log space).  Render-only inputs and the oracle's blend of
+# its own projection stored as float32 (what the render stage receives) differ
+# from the GPU's inputs by at most 2 ulp of the conic, opacity and colour:
+# ~1e-6 in ln alpha at the 1/255 floor (q <= 2 ln 255), plus the float32
+# rounding of the log2-domain exponent and v_exp/v_log (a few ulp): 1e-5.
+GUARD_RENDER = 1e-5
+# Against the unrounded FP64 projection the float32 rounding of the projected
+# mean (half an ulp, 6.1e-5 px at 1024..2048 px) moves q by 2 |K d| |delta|:
+# 1e-4 in ln alpha for the splats that reach the floor within the image's
+# pixel density (the survey's guard for the FP64 chain).
+GUARD_E2E = 1e-4
+MAX_FLAGGED = 1e-3        # fraction of pixels a parity gate may leave out
+
+
+def check_vs_oracle(img, T, lid, ref, guard, label, max_flagged=MAX_FLAGGED, tol=TOL_ORACLE, pix=None):
+    """Colour and T within `tol` and identical last contributor on pixels
+    whose decisions are outside `guard`; at most `max_flagged` flagged.
+    `pix` selects sampled pixels ([m,2] x, y) of full-image GPU outputs."""
+    if pix is not None:
+        img = img[:, pix[:, 1], pix[:, 0]]
+        T = T[pix[:, 1], pix[:, 0]]
+        lid = lid[pix[:, 1], pix[:, 0]]
+    flag = O.flagged(ref["margin"], guard)
+    ok = ~flag
+    e_img = float(np.abs(img - ref["image"])[:, ok].max()) if ok.any() else 0.0
+    e_T = float(np.abs(T - ref["T"])[ok].max()) if ok.any() else 0.0
+    print(f"  {label}: flagged {int(flag.sum())}/{flag.size} ({flag.mean():.2e}) at guard {guard:g}; "
+          f"max-abs colour {e_img:.2e}, T {e_T:.2e}", flush=True)
+    assert flag.mean() <= max_flagged, (label, flag.mean())
+    assert e_img <= tol and e_T <= tol, (label, e_img, e_T)
+    if lid is not None:
+        assert np.array_equal(lid[ok], ref["last_id"][ok]), label
+    return flag
 
 
 def _sync_np(t):
@@ -217,8 +248,10 @@ def _render_only(seed, W, H, n, sigma=(0.3, 12.0), margin=20.0):
 def test_render_only_ladder(seed, W, H, n):
     cam, proj, b, ref = _render_only(seed, W, H, n)
     print(f"render-only seed={seed} {W}x{H} n={n}", flush=True)
-    ok = ~O.flagged(ref["margin"], GUARD_RENDER)
-    assert ok.mean() > 0.99
+    flag = O.flagged(ref["margin"], GUARD_RENDER)
+    print(f"  flagged {int(flag.sum())}/{flag.size} at guard {GUARD_RENDER:g}", flush=True)
+    assert flag.mean() <= MAX_FLAGGED
+    ok = ~flag
     outs = {}
     for v in VARIANTS + [v + "_fp32" for v in VARIANTS]:
         img, T, nc = R.render(v, cam, b, proj)
@@ -278,7 +311,9 @@ def test_render_edge_cases():
             assert np.all(img == np.float32([0.5, 0.25, 1.0])[:, None, None])
     # one huge splat covering everything and opaque tiny ones
     cam, proj, b, ref = _render_only(11, 150, 90, 300, sigma=(0.05, 400.0), margin=300.0)
-    ok = ~O.flagged(ref["margin"], GUARD_RENDER)
+    flag = O.flagged(ref["margin"], GUARD_RENDER)
+    assert flag.mean() <= MAX_FLAGGED
+    ok = ~flag
     for v in VARIANTS:
         img, T, nc = (_sync_np(x) for x in R.render(v, cam, b, proj))
         assert np.abs(img - ref["image"])[:, ok].max() <= TOL_ORACLE
@@ -308,16 +343,18 @@ def test_end_to_end_parity(cfg, n, view):
     sc = scenes.make_config(cfg, n=n)
     cam = sc.cameras[view]
     print(f"end-to-end cfg={cfg} n={n} view={view}", flush=True)
-    ref = O.render_scene(sc, view)
-    ok = ~O.flagged(ref["margin"], GUARD_E2E)
-    assert ok.mean() > 0.98
+    pr = O.project_scene(sc, view)
+    ref = O.render_scene(sc, view, proj=pr, stored=True)      # the float32-stored projection
+    ref64 = O.render_scene(sc, view, proj=pr)                  # the unrounded FP64 projection
     imgs = {}
     for v in ("plain", "local", "local_q8", "local_q8_v4"):
         img, T, nc, (proj, b) = R.rasterize(cam, *scene_tensors(sc), variant=v)
         imgs[v] = _sync_np(img)
-        assert np.abs(imgs[v] - ref["image"])[:, ok].max() <= TOL_ORACLE, v
-        assert np.abs(_sync_np(T) - ref["T"])[ok].max() <= TOL_ORACLE, v
-        assert np.array_equal(last_ids(b, nc, cam)[ok], ref["last_id"][ok]), v
+        lid = last_ids(b, nc, cam)
+        check_vs_oracle(imgs[v], _sync_np(T), lid, ref, GUARD_RENDER, f"{v} vs stored projection")
+        # the float32 storage of the projected mean alone can flip a decision
+        # of the unrounded projection; reported, not gated at 1e-3
+        check_vs_oracle(imgs[v], _sync_np(T), lid, ref64, GUARD_E2E, f"{v} vs FP64 projection", max_flagged=1e-2)
     assert np.abs(imgs["local"] - imgs["plain"]).max() <= TOL_LADDER
     assert np.array_equal(imgs["local"], imgs["local_q8"])
     assert np.array_equal(imgs["local"], imgs["local_q8_v4"])
@@ -356,11 +393,11 @@ def test_full_size_sampled_parity():
     pix = np.stack([rng.integers(0, cam.width, 3000), rng.integers(0, cam.height, 3000)], 1)
     edges = np.array([[0, 0], [cam.width - 1, cam.height - 1], [15, 16], [16, 15], [cam.width - 1, 0]])
     pix = np.concatenate([pix, edges]).astype(np.int32)
-    ref = O.render_tiled(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"], pr["rgb"],
+    lid = last_ids(b, nc, cam)
+    st = O.stored_projection(pr)
+    ref = O.render_tiled(cam.width, cam.height, off, ids, st["means2d"], st["conic"], st["opacity"], st["rgb"],
                          cam.bg, pixels=pix)
-    ok = ~O.flagged(ref["margin"], GUARD_E2E)
-    got = img[:, pix[:, 1], pix[:, 0]]
-    assert np.abs(got - ref["image"])[:, ok].max() <= TOL_ORACLE
-    assert np.abs(T[pix[:, 1], pix[:, 0]] - ref["T"])[ok].max() <= TOL_ORACLE
-    lid = last_ids(b, nc, cam)[pix[:, 1], pix[:, 0]]
-    assert np.array_equal(lid[ok], ref["last_id"][ok])
+    check_vs_oracle(img, T, lid, ref, GUARD_RENDER, "c2 full size vs stored projection", pix=pix)
+    ref64 = O.render_tiled(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"], pr["rgb"],
+                           cam.bg, pixels=pix)
+    check_vs_oracle(img, T, lid, ref64, GUARD_E2E, "c2 full size vs FP64 projection", max_flagged=1e-2, pix=pix)

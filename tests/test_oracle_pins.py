@@ -210,6 +210,137 @@ def test_footprint_conservative_brute_force(oracle, seed):
     assert hits > 1000
 
 
+def _rotated_splats(rng, n, W, H, sig_lo=0.05, sig_hi=400.0, ratio_hi=20.0, pad=60.0):
+    """Screen-space splats drawn by covariance: rotated ellipses with major
+    standard deviation log-uniform in [sig_lo, sig_hi] px, axis ratio up to
+    ratio_hi, centres straddling the image edges; opacity log-uniform from
+    just below 1/255 to 1."""
+    cen = np.stack([rng.uniform(-pad, W - 1 + pad, n), rng.uniform(-pad, H - 1 + pad, n)], 1)
+    s1 = np.exp(rng.uniform(np.log(sig_lo), np.log(sig_hi), n))
+    s2 = s1 / np.exp(rng.uniform(0.0, np.log(ratio_hi), n))
+    th = rng.uniform(0.0, np.pi, n)
+    c, s = np.cos(th), np.sin(th)
+    sxx = c * c * s1 ** 2 + s * s * s2 ** 2
+    syy = s * s * s1 ** 2 + c * c * s2 ** 2
+    sxy = c * s * (s1 ** 2 - s2 ** 2)
+    det = sxx * syy - sxy * sxy
+    conic = np.stack([syy / det, -sxy / det, sxx / det], 1)
+    opac = np.exp(rng.uniform(np.log(0.9 / 255), 0.0, n))
+    return cen, conic, opac
+
+
+def _tile_box(xs, ys):
+    return (xs.min() // 16, ys.min() // 16, xs.max() // 16 + 1, ys.max() // 16 + 1)
+
+
+def _sampled_box(cen, conic, tau, W, H, k=4096, pad=0.0):
+    """Pixel-centre box [x0, x1] x [y0, y1] (clipped to the image) inside the
+    bounding box of the ellipse q <= tau widened by `pad` pixels, the box
+    found by sampling the ellipse boundary d = sqrt(tau) L (cos t, sin t),
+    Sigma = L L^T; None if it holds no pixel centre."""
+    a, b, c = conic
+    L = np.linalg.cholesky(np.linalg.inv(np.array([[a, b], [b, c]])))
+    t = np.linspace(0.0, 2 * np.pi, k, endpoint=False)
+    pts = math.sqrt(tau) * (L @ np.stack([np.cos(t), np.sin(t)]))
+    x0 = max(math.ceil(cen[0] + pts[0].min() - pad), 0)
+    x1 = min(math.floor(cen[0] + pts[0].max() + pad), W - 1)
+    y0 = max(math.ceil(cen[1] + pts[1].min() - pad), 0)
+    y1 = min(math.floor(cen[1] + pts[1].max() + pad), H - 1)
+    return None if x0 > x1 or y0 > y1 else (x0, y0, x1, y1)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_screen_footprint_brute_force(oracle, seed):
+    """The footprint of splats given in screen space (the rule the render-only
+    tests bin with).  Conservative: every pixel centre with alpha >= 1/255
+    (FP64, brute force over the image) lies in the returned tile rectangle.
+    Tight: the rectangle lies within the tiles of the pixel centres inside
+    the bounding box of a barely larger ellipse, that box found by sampling
+    the ellipse's boundary.  Culled exactly when that box holds no pixel
+    centre.  An under- or over-covering rule (swapped axes, a missing factor
+    of 2 in tau, the 3-sigma square) fails one of these."""
+    rng = np.random.default_rng(700 + seed)
+    W, H = 97, 61
+    cen, conic, opac = _rotated_splats(rng, 1500, W, H)
+    vis, rect = oracle.footprint(W, H, cen, conic, opac)
+    xs, ys = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    n_hit = 0
+    for g in range(len(opac)):
+        a, b, c = conic[g]
+        tau = 2.0 * math.log(255.0 * opac[g])
+        if tau <= 0:
+            assert vis[g] == 0, g                        # opacity below 1/255: never visible
+            continue
+        # the footprint's outward slack: 1e-5 relative and absolute in tau,
+        # 0.01 px in the half-widths; the loose box allows a little more
+        loose = _sampled_box(cen[g], conic[g], tau * 1.001 + 0.05, W, H, pad=0.02)
+        if loose is None:
+            assert vis[g] == 0, g
+            continue
+        dx, dy = xs - cen[g, 0], ys - cen[g, 1]
+        q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        iy, ix = np.nonzero(q <= tau)                    # alpha >= 1/255 exactly
+        x0, y0, x1, y1 = rect[g]
+        if len(ix):
+            n_hit += 1
+            assert vis[g] == 1, g
+            assert np.all((ix // 16 >= x0) & (ix // 16 < x1) & (iy // 16 >= y0) & (iy // 16 < y1)), (g, rect[g])
+        if vis[g]:
+            lx0, ly0, lx1, ly1 = loose
+            assert x0 >= lx0 // 16 and y0 >= ly0 // 16 and x1 <= lx1 // 16 + 1 and y1 <= ly1 // 16 + 1, \
+                (g, rect[g], loose)
+    assert n_hit > 300
+    # the draw reaches both ends: splats far larger than a tile and splats below a pixel
+    assert (rect[:, 2] - rect[:, 0]).max() == (W + 15) // 16 and ((rect[:, 2] - rect[:, 0]) == 1).sum() > 50
+
+
+def test_screen_footprint_equals_projection_rule(oracle):
+    """The screen-space footprint of the oracle's own projected splats equals
+    the rectangle the projection computed from the 2D covariance (the conic
+    is its inverse, so both describe the same ellipse)."""
+    sc = scenes.make_config(5, n=4000)
+    for v in (0, 1, 2):
+        cam = sc.cameras[v]
+        pr = oracle.project_scene(sc, v)
+        vis, rect = oracle.footprint(cam.width, cam.height, pr["means2d"], pr["conic"], pr["opacity"])
+        assert pr["visible"].sum() > 500
+        assert np.array_equal(vis, pr["visible"])
+        assert np.array_equal(rect, pr["rect"])
+
+
+@pytest.mark.parametrize("u,v,clamped", [(1.2, 0.0, "x"), (-1.5, 0.2, "x"), (0.3, 0.9, "y"), (1.1, -1.0, "xy"),
+                                         (0.6, 0.3, "")])
+def test_projection_guard_band_clamp(oracle, u, v, clamped):
+    """EWA guard band: the projection Jacobian is evaluated at the camera-space
+    point whose tangent coordinates are clamped to 1.3 tan(half fov), while
+    the mean uses the true point.  Closed form for an isotropic Gaussian
+    (Sigma3 = s^2 I, identity camera rotation):
+    Sigma2 = s^2 J J^T + 0.3 I with J = [[f/z, 0, -f uc/z], [0, f/z, -f vc/z]]."""
+    cam = _cam(64, 48)
+    f = float(np.float32(cam.fx))
+    tx, ty = float(np.float32(cam.tan_fovx)), float(np.float32(cam.tan_fovy))
+    z, s = 5.0, 0.04
+    x, y = u * z, v * z
+    pr = oracle.project(cam, *_one((x, y, z), (math.log(s),) * 3))
+
+    def conic_at(uc, vc):
+        J = np.array([[f / z, 0, -f * uc / z], [0, f / z, -f * vc / z]])
+        K = np.linalg.inv(s * s * J @ J.T + 0.3 * np.eye(2))
+        return np.array([K[0, 0], K[0, 1], K[1, 1]])
+
+    uc = float(np.clip(u, -1.3 * tx, 1.3 * tx))
+    vc = float(np.clip(v, -1.3 * ty, 1.3 * ty))
+    assert ("x" in clamped) == (uc != u) and ("y" in clamped) == (vc != v)
+    np.testing.assert_allclose(pr["means2d"][0], [f * u + cam.cx, f * v + cam.cy], rtol=1e-13)
+    # (the conic is reported also when the footprint then misses the image)
+    np.testing.assert_allclose(pr["conic"][0], conic_at(uc, vc), rtol=1e-9, atol=1e-15)
+    if not clamped:
+        assert pr["visible"][0] == 1
+    if clamped:
+        # the unclamped Jacobian gives a visibly different conic
+        assert np.abs(conic_at(u, v) - conic_at(uc, vc)).max() > 1e-3 * np.abs(conic_at(uc, vc)).max()
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_tiled_equals_untiled(oracle, seed):
     sc = scenes.make_config(1, seed=200 + seed, n=1500)
@@ -448,3 +579,28 @@ def test_scene_gradient_vs_finite_differences(oracle, deg):
             assert abs(an[key][idx] - fd) <= 1e-5 * scale + 1e-9, (key, idx, an[key][idx], fd)
             checked += 1
     assert checked > 10 * skipped
+
+
+def test_clamp_margin_is_not_a_forward_decision(oracle):
+    """min(0.99, .) is continuous: a Gaussian whose unclamped alpha sits next to
+    0.99 at a pixel gives a small clamp margin there (the derivative switches),
+    while the forward decision margin stays large."""
+    W = H = 16
+    args = _splats([[7.0, 7.0]], [[0.5, 0.0, 0.5]], [0.99 * math.exp(2e-6)], [[0.3, 0.6, 0.9]])
+    out = oracle.render_untiled(W, H, *args)
+    assert out["clamp_margin"][7, 7] == pytest.approx(2e-6, rel=1e-6)
+    assert out["margin"][7, 7] > 1.0
+    assert out["image"][0, 7, 7] == pytest.approx(0.3 * 0.99, rel=1e-15)
+
+
+def test_stored_projection_rounds_the_splats_only(oracle):
+    """The float32-stored projection rounds mean, conic, opacity and colour
+    and keeps visibility, depth keys and rectangles."""
+    sc = scenes.make_config(1, n=500)
+    pr = oracle.project_scene(sc)
+    st = oracle.stored_projection(pr)
+    for k in ("means2d", "conic", "opacity", "rgb"):
+        assert np.array_equal(st[k], pr[k].astype(np.float32).astype(np.float64))
+        assert np.abs(st[k] - pr[k]).max() <= np.abs(pr[k]).max() * 2.0 ** -24
+    for k in ("visible", "depth", "rect"):
+        assert np.array_equal(st[k], pr[k])
