@@ -84,8 +84,13 @@ typedef enum {
     LGS_RENDER_FP32 = 0x10,
     LGS_RENDER_Q8 = 0x20,       /* HOIST_CULL / LOCAL: each wavefront owns an 8x8 quadrant of
                                    the tile instead of a 16x4 row strip (same results) */
-    LGS_RENDER_VOTE4 = 0x40     /* LOCAL: the wave-wide termination vote runs once per 4
+    LGS_RENDER_VOTE4 = 0x40,    /* LOCAL: the wave-wide termination vote runs once per 4
                                    Gaussians instead of after each one (same results) */
+    LGS_RENDER_GLOBAL = 0x80    /* hoisted variants: the basis [x'^2, x'y', y'^2, x', y', 1]
+                                   in image coordinates instead of tile-centre ones (the
+                                   paper's global-coordinate precision baseline, Sec.
+                                   III-B-4; with LGS_RENDER_FP32 it loses the accuracy the
+                                   tile-local origin keeps) */
 } lgs_render_variant;
 
 /* Message for the last non-OK status on the calling host thread. */
@@ -188,9 +193,18 @@ lgs_status lgs_render(int32_t variant, const lgs_camera *cam, const uint32_t *ra
  * the clamp at 0.99 and all skip / stop decisions are held fixed.
  * `variant` is LGS_RENDER_PLAIN or LGS_RENDER_LOCAL (hoisted, culled), the
  * latter optionally with LGS_RENDER_Q8 (8x8 wavefront quadrants for the
- * culling); the other flag bits are ignored.  Gradients agree across these
- * choices up to the order of floating-point summation.
+ * culling), either with LGS_RENDER_FP32 when the forward ran a single-
+ * precision variant: the replay then evaluates alpha with that forward's
+ * expression (the float hoisted dot product, or the plain o * exp of the
+ * float quadratic), so it takes the forward's skip and clamp decisions.
+ * and with LGS_RENDER_GLOBAL after a global-coordinate forward.
+ * LGS_RENDER_VOTE4 is ignored.  Use PLAIN after a PLAIN forward and LOCAL
+ * after any hoisted one (HOIST, HOIST_CULL, LOCAL).  Gradients agree across
+ * these choices up to the order of floating-point summation.
+ * OR with LGS_BWD_ACCUMULATE to add into the gradient buffers instead of
+ * overwriting them (e.g. to sum the gradients of several batches of views).
  */
+#define LGS_BWD_ACCUMULATE 0x100
 lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam, int64_t n, const uint32_t *ranges,
                                const uint32_t *values, const float *means2d, const float *conic_opacity,
                                const float *rgb, const float *out_T, const int32_t *out_ncontrib,
@@ -277,16 +291,30 @@ lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *o
                           size_t workspace_bytes, void *stream);
 
 /* lgs_render_backward of a batch: n_elem = num_views * n elements of the
- * view-major gradient outputs.  tile_order: NULL, or a permutation of the
- * batch's global tile ids (as from lgs_tile_order) in which the tiles are
- * launched, e.g. longest list first so that the longest tiles do not run
- * last; the gradients do not depend on it beyond float summation order. */
+ * view-major gradient outputs.
+ * tile_order: NULL, or a permutation of the batch's global tile ids (as from
+ *   lgs_tile_order), e.g. longest list first so that the longest tiles do not
+ *   run last.
+ * queue: NULL for one workgroup per tile (in tile_order, if given); else
+ *   LGS_QUEUE_WORDS device uint32 words of work counters (cleared by the call
+ *   itself) that make the backward one persistent launch of blocks_per_cu
+ *   workgroups per compute unit (<= 0: 4), each taking whole tiles in
+ *   tile_order from the counters until none is left.  Concurrent calls must
+ *   not share a queue.
+ * stats: NULL, or device uint64[8] that receives (added) counters:
+ *   [0] (wavefront, Gaussian) steps met within the replay range (after
+ *   culling), [1] steps replayed (some lane takes the Gaussian), [2] (pixel,
+ *   Gaussian) pairs taken, [3] lane evaluations (64 per replayed step).
+ *   Counting runs a separate, slower instantiation.
+ * The gradients do not depend on the order or the schedule beyond float
+ * summation order. */
 lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, int32_t num_views, int64_t n_elem,
                                      const uint32_t *ranges, const uint32_t *values, const float *means2d,
                                      const float *conic_opacity, const float *rgb, const float *out_T,
                                      const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
                                      float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
-                                     const uint32_t *tile_order, void *stream);
+                                     const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
+                                     uint64_t *stats, void *stream);
 
 /* lgs_project_backward of a batch: the view-major gradients of the projected
  * attributes are summed over the views into the raw-parameter gradients
@@ -316,11 +344,16 @@ lgs_status lgs_graph_destroy(lgs_graph *graph);
 
 /*
  * lgs_l1_loss -- L = mean |image - target| over `count` floats and
- * grad = dL/d image = sign(image - target) / count (0 where equal).
+ * grad = dL/d image = sign(image - target) / count (0 where equal); the
+ * training objective of the differentiable path (not part of the paper).
  * loss: device float (overwritten); grad: device [count].
+ * workspace: 8-byte aligned device scratch of lgs_l1_workspace_size() bytes
+ * for the per-block partial sums (summed in a fixed order: the loss is
+ * deterministic).  Calls with distinct workspaces may run concurrently.
  */
+size_t lgs_l1_workspace_size(void);
 lgs_status lgs_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
-                       void *stream);
+                       void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

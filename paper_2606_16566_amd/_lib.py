@@ -25,12 +25,15 @@ RENDER_LOCAL = 3
 RENDER_FP32 = 0x10
 RENDER_Q8 = 0x20
 RENDER_VOTE4 = 0x40
+RENDER_GLOBAL = 0x80
+BWD_ACCUMULATE = 0x100
 
 MAX_VIEWS = 16
 QUEUE_WORDS = 256
 
 EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort",
-           "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_loss",
+           "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_workspace_size",
+           "lgs_l1_loss",
            "lgs_project_batch", "lgs_sort_batch", "lgs_render_batch", "lgs_render_backward_batch",
            "lgs_project_backward_batch", "lgs_graph_begin", "lgs_graph_end", "lgs_graph_launch",
            "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order"]
@@ -59,14 +62,15 @@ _SIG = {
     "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 10),
     "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 14),
     "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 16),
-    "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P]),
+    "lgs_l1_workspace_size": (C.c_size_t, []),
+    "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
     "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 11),
     "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _I64, _P, _P, _P,
                                  C.c_size_t, _P]),
     "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9 + [_P, _P, _I32, _P]),
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
-    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 15),
+    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 15 + [_I32, _P, _P]),
     "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 16),
     "lgs_graph_begin": (C.c_int, [_P]),
     "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),

@@ -1,7 +1,8 @@
 """Autotuner of the render launch settings.
 
-Search space (every point computes the same blend; only the schedule, the
-wavefront sub-tile and the exponent precision change):
+Search space of the culling families ('local', 'hoist_cull'; every point
+computes the same blend; only the schedule, the wavefront sub-tile and the
+exponent precision change):
 
   shape          16x4 row strips or 8x8 quadrants per wavefront
   vote           termination vote after every Gaussian, or once per four
@@ -10,6 +11,15 @@ wavefront sub-tile and the exponent precision change):
                  first), or a persistent queue of blocks_per_cu workgroups per
                  compute unit (2, 4, 8) handing out sub-tiles in index or
                  longest-first tile order
+
+The plain per-pixel renderer (family 'plain', the comparison baseline) is
+tuned over what it has: exponent precision (double, or the 3DGS float
+expression) and tile order (XCD-banded or longest first); its workgroups
+share LDS batches, so it has no sub-tile shape, vote or queue.
+
+`tune_backward` chooses the backward's schedule the same way: one workgroup
+per tile or persistent (2, 4, 8 workgroups per CU), index or longest-first
+order (the gradients agree up to float summation order).
 
 Objective: median duration of the render launch over `reps` timed runs
 (HIP events on the launching stream).  A point is admissible only if its
@@ -39,7 +49,11 @@ KEYS = ("family", "shape", "vote", "precision", "persistent", "blocks_per_cu", "
 
 
 def space(family: str = "local"):
-    """All candidate settings of one variant family ('local' or 'hoist_cull')."""
+    """All candidate settings of one variant family ('local', 'hoist_cull'
+    or 'plain')."""
+    if family == "plain":
+        return [dict(family="plain", shape="16x4", vote=1, precision=prec, persistent=False, blocks_per_cu=0, lpt=lpt)
+                for prec in ("fp64", "fp32") for lpt in (False, True)]
     votes = (1, 4) if family == "local" else (1,)
     pts = []
     for shape, vote, prec in itertools.product(("16x4", "8x8"), votes, ("fp64", "fp32")):
@@ -144,5 +158,53 @@ def tune(vb, params, family: str = "local", reps: int = 9, warmup: int = 2, tol:
         cache = load_cache(cache_path)
         cache[key] = {"best": best_cfg, "median_ms": best["median_ms"], "results": results,
                       "tuned_s": time.perf_counter() - t0}
+        save_cache(cache, cache_path)
+    return {"key": key, "best": best_cfg, "results": results, "cached": False}
+
+
+BWD_KEYS = ("bwd_persistent", "bwd_blocks_per_cu", "bwd_lpt")
+
+
+def backward_space():
+    pts = [dict(bwd_persistent=False, bwd_blocks_per_cu=0, bwd_lpt=lpt) for lpt in (False, True)]
+    pts += [dict(bwd_persistent=True, bwd_blocks_per_cu=b, bwd_lpt=lpt) for b in (2, 4, 8) for lpt in (False, True)]
+    return pts
+
+
+def tune_backward(vb, params, grad_rgb=None, reps: int = 5, warmup: int = 1, cache_path: str | None = None,
+                  use_cache: bool = True) -> dict:
+    """Tune the backward render's schedule on `vb` (forward settings as
+    configured; the forward is run once, then only the backward render is
+    re-launched with `grad_rgb`, default the batch's own buffer).  Leaves `vb`
+    configured with the fastest point."""
+    vb.forward(params)
+    torch.cuda.synchronize()
+    num_pairs = int(vb.num_pairs.item())
+    key = workload_key(vb, num_pairs, "backward") + f"|variant={vb.variant}"
+    cache = load_cache(cache_path) if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]["best"]
+        vb.configure(**best)
+        return {"key": key, "best": best, "results": cache[key].get("results", []), "cached": True}
+    stream = torch.cuda.current_stream()
+    results = []
+    for cfg in backward_space():
+        vb.configure(**cfg)
+        for _ in range(warmup):
+            vb.backward_render(grad_rgb)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            vb.backward_render(grad_rgb)
+            b.record(stream)
+        torch.cuda.synchronize()
+        t = [a.elapsed_time(b) for a, b in ev]
+        results.append(dict(cfg, median_ms=float(np.median(t)), min_ms=float(np.min(t))))
+    best = min(results, key=lambda r: r["median_ms"])
+    best_cfg = {k: best[k] for k in BWD_KEYS}
+    vb.configure(**best_cfg)
+    if use_cache:
+        cache = load_cache(cache_path)
+        cache[key] = {"best": best_cfg, "median_ms": best["median_ms"], "results": results}
         save_cache(cache, cache_path)
     return {"key": key, "best": best_cfg, "results": results, "cached": False}

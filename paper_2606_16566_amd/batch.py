@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .rasterizer import _p, _req, _stream, variant_code
+from .rasterizer import _p, _req, _stream, backward_variant, variant_code
 
 
 def _aligned(buf: torch.Tensor):
@@ -34,11 +34,14 @@ class ViewBatch:
     blocks_per_cu  workgroups per compute unit of the persistent render (0: 8)
     lpt            render tiles longest first (queue order, or workgroup order)
     capacity       initial pair capacity; `fit()` grows it from a measured count
-    bwd_lpt        launch the backward's tiles longest first
+    bwd_lpt        the backward takes its tiles longest first
+    bwd_persistent the backward is one persistent launch of bwd_blocks_per_cu
+                   workgroups per compute unit taking tiles from a queue
     """
 
     def __init__(self, cams, n: int, sh_degree: int, variant="local_q8", persistent: bool = False,
-                 blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda", bwd_lpt: bool = True):
+                 blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda", bwd_lpt: bool = True,
+                 bwd_persistent: bool = False, bwd_blocks_per_cu: int = 0):
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_VIEWS:
             raise ValueError(f"a batch holds 1..{L.MAX_VIEWS} cameras, got {len(cams)}")
@@ -74,13 +77,17 @@ class ViewBatch:
         self.out_nc = z(self.num_pixels, dtype=i32)
         self.grad_rgb = z(3 * self.num_pixels)
         self.loss = z(1)
+        self.l1_ws = torch.empty(L.lib().lgs_l1_workspace_size() // 8, dtype=torch.float64, device=dev)
         # binning
         self.num_pairs = z(1, dtype=torch.int64)
         self.overflow = z(1, dtype=i32)
         self.ranges = z(self.num_tiles, 2, dtype=i32)
         self.queue = z(L.QUEUE_WORDS, dtype=i32)
+        self.bwd_queue = z(L.QUEUE_WORDS, dtype=i32)
         self.order = z(self.num_tiles, dtype=i32)
         self.bwd_lpt = bool(bwd_lpt)
+        self.bwd_persistent = bool(bwd_persistent)
+        self.bwd_blocks_per_cu = int(bwd_blocks_per_cu)
         self.order_ws = torch.empty(L.lib().lgs_tile_order_workspace_size(self.num_tiles) + 256, dtype=torch.uint8,
                                     device=dev)
         self.capacity = 0
@@ -140,7 +147,8 @@ class ViewBatch:
         self.bin(params)
         self.render(stats)
 
-    def configure(self, variant=None, persistent=None, blocks_per_cu=None, lpt=None):
+    def configure(self, variant=None, persistent=None, blocks_per_cu=None, lpt=None, bwd_lpt=None,
+                  bwd_persistent=None, bwd_blocks_per_cu=None):
         """Change launch settings (e.g. from the autotuner); buffers are kept."""
         if variant is not None:
             self.variant = variant_code(variant)
@@ -150,6 +158,12 @@ class ViewBatch:
             self.blocks_per_cu = int(blocks_per_cu)
         if lpt is not None:
             self.lpt = bool(lpt)
+        if bwd_lpt is not None:
+            self.bwd_lpt = bool(bwd_lpt)
+        if bwd_persistent is not None:
+            self.bwd_persistent = bool(bwd_persistent)
+        if bwd_blocks_per_cu is not None:
+            self.bwd_blocks_per_cu = int(bwd_blocks_per_cu)
 
     def bin(self, params):
         """Enqueue project -> sort -> ranges for all views."""
@@ -207,24 +221,39 @@ class ViewBatch:
         if target_packed.numel() != self.out_rgb.numel():
             raise ValueError("target does not match the packed image size")
         L.check(L.lib().lgs_l1_loss(_p(self.out_rgb), _p(target_packed), self.out_rgb.numel(), _p(self.loss),
-                                    _p(self.grad_rgb), _stream()), "lgs_l1_loss")
+                                    _p(self.grad_rgb), _p(self.l1_ws), self.l1_ws.numel() * 8, _stream()),
+                "lgs_l1_loss")
 
     def backward(self, params, grad_rgb: torch.Tensor | None = None, grad_T: torch.Tensor | None = None):
         """Enqueue the gradient of the step into d_* (raw parameters, summed
         over views).  grad_rgb defaults to self.grad_rgb (set by l1)."""
         self._check(params)
+        self.backward_render(grad_rgb, grad_T)
+        self.backward_project(params)
+
+    def backward_render(self, grad_rgb: torch.Tensor | None = None, grad_T: torch.Tensor | None = None,
+                        stats: torch.Tensor | None = None, accumulate: bool = False):
+        """Enqueue the blend's backward into the projected gradients g_*
+        (overwritten, or added to with accumulate=True)."""
         lb, s = L.lib(), _stream()
-        means3d, log_scales, quats, logits, sh = params
         g = self.grad_rgb if grad_rgb is None else _req(grad_rgb, torch.float32, "grad_rgb")
-        bv = L.RENDER_PLAIN if (self.variant & 0xF) == L.RENDER_PLAIN else L.RENDER_LOCAL | (self.variant & L.RENDER_Q8)
+        bv = backward_variant(self.variant) | (L.BWD_ACCUMULATE if accumulate else 0)
         if self.bwd_lpt and not self._fwd_lpt():
             self.tile_order(force=True)                  # the forward did not compute it
         L.check(lb.lgs_render_backward_batch(bv, self.cam_arr, self.V, self.V * self.n, _p(self.ranges),
                                              _p(self.vals), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
                                              _p(self.out_T), _p(self.out_nc), _p(g), _p(grad_T), _p(self.g_means2d),
                                              _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
-                                             _p(self.order) if self.bwd_lpt else None, s),
+                                             _p(self.order) if self.bwd_lpt else None,
+                                             _p(self.bwd_queue) if self.bwd_persistent else None,
+                                             self.bwd_blocks_per_cu, _p(stats), s),
                 "lgs_render_backward_batch")
+
+    def backward_project(self, params):
+        """Enqueue the projection's backward into the raw-parameter gradients."""
+        self._check(params)
+        lb, s = L.lib(), _stream()
+        means3d, log_scales, quats, logits, sh = params
         L.check(lb.lgs_project_backward_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales),
                                               _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_means2d),
                                               _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
@@ -288,3 +317,44 @@ class StepGraph:
             self.close()
         except Exception:
             pass
+
+
+class CapturedStep:
+    """A ViewBatch step (`fn`, which enqueues library calls on `vb`'s
+    buffers) captured once as a graph and replayed, grown and re-captured
+    when the pair count outgrows the capacity it was captured with.
+
+    A replay never synchronises the host.  `check()` does (it reads the
+    overflow flag the sort left on the device): if the last replay
+    overflowed, its outputs are invalid (every tile list came out empty); the
+    pair buffers are then regrown to the pair count the sort reported, with
+    `headroom`, the step is captured again on the new buffers and replayed.
+    """
+
+    def __init__(self, vb: ViewBatch, fn, headroom: float = 1.15, warmup: int = 1):
+        self.vb, self.fn, self.headroom, self.warmup = vb, fn, float(headroom), int(warmup)
+        self.recaptures = 0
+        self.graph = StepGraph(fn, warmup=self.warmup)
+
+    def replay(self):
+        self.graph.replay()
+
+    def check(self, max_grow: int = 4) -> bool:
+        """True if the last replay had overflowed (and has now been redone on
+        grown buffers)."""
+        grown = False
+        for _ in range(max_grow):
+            torch.cuda.current_stream().synchronize()
+            if not self.vb.overflowed():
+                return grown
+            p = int(self.vb.num_pairs.item())
+            self.graph.close()
+            self.vb._alloc_pairs(int(p * self.headroom) + 1024)
+            self.graph = StepGraph(self.fn, warmup=self.warmup)
+            self.recaptures += 1
+            self.graph.replay()
+            grown = True
+        raise RuntimeError("pair count did not settle")
+
+    def close(self):
+        self.graph.close()

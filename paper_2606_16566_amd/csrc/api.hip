@@ -25,10 +25,12 @@ lgs_status launch_status(const char *what)
 
 namespace {
 
-// L = mean |x - y|, dL/dx = sign(x - y) / count.  Block partial sums are
-// reduced in double and added with one atomic per block.
+// L = mean |x - y|, dL/dx = sign(x - y) / count.  Each block writes its
+// partial sum of |x - y| (double) to its own slot; one workgroup then adds the
+// slots in a fixed order, so the loss is deterministic and a call touches no
+// memory but its own arguments.
 __global__ __launch_bounds__(256) void l1_kernel(const float *__restrict__ x, const float *__restrict__ y, int64_t n,
-                                                 float inv_n, float *__restrict__ grad, double *__restrict__ acc)
+                                                 float inv_n, float *__restrict__ grad, double *__restrict__ partial)
 {
     __shared__ double s_w[4];
     double sum = 0.0;
@@ -41,20 +43,35 @@ __global__ __launch_bounds__(256) void l1_kernel(const float *__restrict__ x, co
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
     if (__lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(acc, s_w[0] + s_w[1] + s_w[2] + s_w[3]);
+    if (threadIdx.x == 0) partial[blockIdx.x] = (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]);
 }
 
-__global__ void l1_finish_kernel(double *acc, float *loss, double inv_n)
+__global__ __launch_bounds__(256) void l1_finish_kernel(const double *__restrict__ partial, int nparts,
+                                                        float *__restrict__ loss, double inv_n)
 {
-    *loss = (float)(*acc * inv_n);
-    *acc = 0.0;
+    __shared__ double s_w[4];
+    double sum = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) sum += partial[i];
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+    if (__lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) *loss = (float)(((s_w[0] + s_w[1]) + (s_w[2] + s_w[3])) * inv_n);
 }
-
-// one double accumulator per device for the loss reduction (cleared by
-// l1_finish_kernel after every use, so it is zero between calls)
-__device__ double g_l1_acc = 0.0;
 
 }  // namespace
+
+lgs_status l1_launch(const float *image, const float *target, int64_t count, float *loss, float *grad,
+                     double *partial, hipStream_t s)
+{
+    unsigned g = grid_for(count, 256);
+    if (g > (unsigned)kL1Parts) g = kL1Parts;
+    hipLaunchKernelGGL(l1_kernel, dim3(g), dim3(256), 0, s, image, target, count, (float)(1.0 / (double)count), grad,
+                       partial);
+    hipLaunchKernelGGL(l1_finish_kernel, dim3(1), dim3(256), 0, s, (const double *)partial, (int)g, loss,
+                       1.0 / (double)count);
+    return launch_status("lgs_l1_loss");
+}
+
 }  // namespace lgs
 
 using namespace lgs;
@@ -63,24 +80,13 @@ extern "C" const char *lgs_last_error(void) { return g_error; }
 
 extern "C" const char *lgs_version(void) { return "localgs-gfx950 0.1"; }
 
+extern "C" size_t lgs_l1_workspace_size(void) { return kL1Parts * sizeof(double); }
+
 extern "C" lgs_status lgs_l1_loss(const float *image, const float *target, int64_t count, float *loss, float *grad,
-                                  void *stream)
+                                  void *workspace, size_t workspace_bytes, void *stream)
 {
     LGS_REQUIRE(count > 0 && image && target && loss && grad, "lgs_l1_loss: bad arguments");
-    hipStream_t s = as_stream(stream);
-    // the accumulator's device address, looked up once per device (so the
-    // call stays capturable into a graph)
-    static double *acc_of[64] = {nullptr};
-    int dev = 0;
-    LGS_HIP(hipGetDevice(&dev));
-    LGS_REQUIRE(dev >= 0 && dev < 64, "lgs_l1_loss: device index %d out of range", dev);
-    if (!acc_of[dev]) LGS_HIP(hipGetSymbolAddress((void **)&acc_of[dev], HIP_SYMBOL(g_l1_acc)));
-    double *acc = acc_of[dev];
-    unsigned g = grid_for(count, 256);
-    if (g > 2048) g = 2048;
-    hipLaunchKernelGGL(l1_kernel, dim3(g), dim3(256), 0, s, image, target, count, (float)(1.0 / (double)count), grad,
-                       acc);
-    hipLaunchKernelGGL(l1_finish_kernel, dim3(1), dim3(1), 0, s, acc, loss, 1.0 / (double)count);
-    LGS_LAUNCHED("lgs_l1_loss");
-    return LGS_OK;
+    LGS_REQUIRE(workspace && workspace_bytes >= lgs_l1_workspace_size() && (uintptr_t)workspace % 8 == 0,
+                "lgs_l1_loss: workspace must be 8-byte aligned and hold lgs_l1_workspace_size() bytes");
+    return l1_launch(image, target, count, loss, grad, static_cast<double *>(workspace), as_stream(stream));
 }

@@ -15,6 +15,7 @@ namespace lgs {
 constexpr int kTile = LGS_TILE;          // 16x16 pixel tiles
 constexpr int kBlock = 256;              // one workgroup per tile: 4 wave64
 constexpr int kMaxViews = LGS_MAX_VIEWS; // cameras per view batch
+constexpr int kL1Parts = 2048;            // partial sums of the L1 loss reduction
 constexpr float kAlphaMax = 0.99f;       // opacity clamp (Sec. III-D-1)
 constexpr double kTMin = 1e-4;           // termination threshold (Alg. 1)
 constexpr double kLowpass = 0.3;         // 2D covariance dilation, px^2
@@ -86,6 +87,21 @@ inline bool cam_from(const lgs_camera *c, Cam &d)
 }
 
 inline unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
+
+// compute units of the current device (cached per device; 256 if unknown)
+inline int device_cus()
+{
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 

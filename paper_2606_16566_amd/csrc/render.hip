@@ -337,20 +337,6 @@ void launch_render(const RenderArgs &a, bool stats, bool q8, bool vote4, unsigne
     }
 }
 
-int device_cus()
-{
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-        cached[dev] = cus;
-    }
-    return cached[dev];
-}
-
 }  // namespace
 }  // namespace lgs
 
@@ -372,7 +358,8 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     const bool fp32 = (variant & LGS_RENDER_FP32) != 0;
     const bool q8 = (variant & LGS_RENDER_Q8) != 0;
     const bool vote4 = (variant & LGS_RENDER_VOTE4) != 0;
-    LGS_REQUIRE(v >= 0 && v <= 3 && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8 | LGS_RENDER_VOTE4)) == 0,
+    LGS_REQUIRE(v >= 0 && v <= 3
+                    && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8 | LGS_RENDER_VOTE4 | LGS_RENDER_GLOBAL)) == 0,
                 "lgs_render: unknown variant %d", variant);
     LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
     LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && (means2d == nullptr || (uintptr_t)means2d % 8 == 0)
@@ -382,6 +369,7 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
                                              out_T, out_ncontrib, stats);
     hipStream_t s = as_stream(stream);
     a.order = tile_order;                     // queue position -> tile, or workgroup -> tile
+    a.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
     const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
     unsigned grid = (unsigned)a.num_tiles;
     if (persistent) {

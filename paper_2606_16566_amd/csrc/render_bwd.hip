@@ -88,10 +88,29 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, e, r);
 }
 
-template <bool LOCAL, bool Q8>
+// R is the precision of the forward's exponent (double, or float for the
+// single-precision variants): the replay evaluates alpha with the same
+// expression as the forward kernel it follows, so that it takes the same skip
+// and clamp decisions.
+//
+// Grid mode: one workgroup per tile (in the order of `order`, else XCD-banded).
+// Persistent mode (queue != null): blocks_per_cu workgroups per CU pop tiles
+// from eight per-XCD counters (workgroup b draws from counter b % 8, which
+// hands out queue positions b % 8, b % 8 + 8, ...; position -> tile through
+// `order`) until the positions run out; every workgroup reaches that exit.
+//
+// STATS counts, per wavefront: [0] (wavefront, Gaussian) steps whose strip
+// bit is set within the wavefront's replay range, [1] steps some lane takes
+// (replayed), [2] (lane, Gaussian) pairs taken, [3] lane evaluations (64 per
+// replayed step).
+struct BwdStats {
+    unsigned long long cand = 0, proc = 0, taken = 0;
+};
+
+template <bool LOCAL, bool Q8, typename R, bool STATS>
 __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
 {
-    __shared__ Hoisted<double> s_v[kBlock];  // hoisted exponent coefficients
+    __shared__ Hoisted<R> s_v[kBlock];       // hoisted exponent coefficients
     __shared__ float4 s_co[kBlock];          // a, b, c, o
     __shared__ float2 s_mu[kBlock];          // mean
     __shared__ float4 s_c[kBlock];           // colour
@@ -99,10 +118,13 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     __shared__ uint8_t s_m[kBlock];
     __shared__ float s_g[kNG][kBlock];
     __shared__ int s_max[kBlock / 64];
+    __shared__ uint32_t s_pos;
 
     const RenderArgs &a = ba.r;
-    const int tile = a.order ? (int)a.order[blockIdx.x] : xcd_tile(blockIdx.x, a.num_tiles);
-    const TileCtx<double> tc(a, tile, threadIdx.x >> 6, Q8);
+    BwdStats st;
+
+    auto replay_tile = [&](const int tile) {
+    const TileCtx<R> tc(a, tile, threadIdx.x >> 6, Q8);
     const int lane = __lane_id(), wid = tc.wid;
     const int px = tc.px, py = tc.py;
     const bool inside = tc.inside;
@@ -170,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             s_c[k] = make_float4(at_cur.r, at_cur.gg, at_cur.b, 0.f);
             const float lo = __builtin_amdgcn_logf(co.w);
             if (LOCAL) {
-                s_v[k] = hoist<double>(m, co, lo, tc.ox, tc.oy);
+                s_v[k] = hoist<R>(m, co, lo, tc.ox, tc.oy);
                 // strip bits of the four wavefronts (the forward's test; the
                 // strips share their columns, so the ellipse's vertical span
                 // over them is computed once)
@@ -201,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 }
                 s_m[k] = (uint8_t)mk;
             } else {
-                s_v[k].v[5] = (double)lo;
+                s_v[k].v[5] = (R)lo;
                 s_m[k] = 0xF;
             }
 #pragma unroll
@@ -219,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             const int j = c0 + lane;
             const bool bit = j < wlimit && ((s_m[j] >> wid) & 1u);
             uint64_t bits = __ballot(bit);
+            if (STATS) st.cand += (unsigned long long)__popcll(bits);
             while (bits) {
                 const int kk = 63 - __builtin_clzll(bits);
                 bits &= ~(1ull << kk);
@@ -226,20 +249,31 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 const int pos1 = (int)(bstart + k - range.x) + 1;
                 const float4 co = s_co[k];
                 const float2 m = s_mu[k];
-                double s;
+                // raw: the unclamped alpha o exp(-q/2), as the forward computed it
+                float raw;
+                bool keep;
                 if (LOCAL) {
-                    s = dot_exponent(s_v[k], tc);
-                } else {
+                    const float s32 = (float)dot_exponent(s_v[k], tc);
+                    raw = __builtin_amdgcn_exp2f(s32);
+                    keep = s32 >= kLog2AlphaMin;
+                } else if constexpr (sizeof(R) == 8) {
                     const double dxd = (double)px - (double)m.x, dyd = (double)py - (double)m.y;
                     const double q = (double)co.x * dxd * dxd + 2.0 * (double)co.y * dxd * dyd
                                      + (double)co.z * dyd * dyd;
-                    s = s_v[k].v[5] - 0.5 * kLog2e * q;
+                    const float s32 = (float)((double)s_v[k].v[5] - 0.5 * kLog2e * q);
+                    raw = __builtin_amdgcn_exp2f(s32);
+                    keep = s32 >= kLog2AlphaMin;
+                } else {
+                    // the plain single-precision forward: o * exp(power) in float
+                    const float ex = m.x - (float)px, ey = m.y - (float)py;
+                    const float power = -0.5f * (co.x * ex * ex + co.z * ey * ey) - co.y * ex * ey;
+                    raw = co.w * __builtin_amdgcn_exp2f(power * (float)kLog2e);
+                    keep = fminf(raw, kAlphaMax) >= kAlphaMinF;
                 }
                 const float dx = (float)px - m.x, dy = (float)py - m.y;
-                const float s32 = (float)s;
-                const float raw = __builtin_amdgcn_exp2f(s32);
-                const bool act = pos1 <= last && s32 >= kLog2AlphaMin;
+                const bool act = pos1 <= last && keep;
                 if (__ballot(act) == 0ull) continue;          // no lane of the wavefront takes this Gaussian
+                if (STATS) { st.proc++; st.taken += act ? 1ull : 0ull; }
                 // Branch-free from here: a lane that does not take the Gaussian
                 // uses alpha = 0, so T (times 1/(1 - 0) = 1) and R are unchanged
                 // and every partial is zero.
@@ -295,6 +329,39 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             if ((v = s_g[8][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid + 2], v);
         }
     }
+    };  // replay_tile
+
+    if (a.queue == nullptr) {
+        replay_tile(a.order ? (int)a.order[blockIdx.x] : xcd_tile(blockIdx.x, a.num_tiles));
+    } else {
+        const uint32_t x = blockIdx.x & (kQueues - 1);
+        uint32_t *counter = a.queue + x * kQueueStride;
+        for (;;) {
+            __syncthreads();                                // s_pos of the last round read by all
+            if (threadIdx.x == 0) s_pos = atomicAdd(counter, 1u);
+            __syncthreads();
+            const uint64_t pos = (uint64_t)s_pos * kQueues + x;
+            if (pos >= (uint64_t)a.num_tiles) break;
+            replay_tile(a.order ? (int)a.order[pos] : (int)pos);
+        }
+    }
+    if (STATS) {
+        unsigned long long cand = st.cand, proc = st.proc, taken = st.taken;
+        for (int off = 32; off > 0; off >>= 1) taken += (unsigned long long)__shfl_xor(taken, off, 64);
+        if (__lane_id() == 0) {
+            atomicAdd(&a.stats[0], cand);
+            atomicAdd(&a.stats[1], proc);
+            atomicAdd(&a.stats[2], taken);
+            atomicAdd(&a.stats[3], 64ull * proc);
+        }
+    }
+}
+
+template <bool LOCAL, bool Q8, typename R>
+void launch_bwd(bool stats, dim3 g, hipStream_t s, const BwdArgs &a)
+{
+    if (stats) hipLaunchKernelGGL((render_bwd_kernel<LOCAL, Q8, R, true>), g, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((render_bwd_kernel<LOCAL, Q8, R, false>), g, dim3(kBlock), 0, s, a);
 }
 
 }  // namespace
@@ -308,7 +375,8 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
                                                 const float *out_T, const int32_t *out_ncontrib,
                                                 const float *grad_rgb, const float *grad_T, float *g_means2d,
                                                 float *g_conic, float *g_opacity, float *g_rgb,
-                                                const uint32_t *tile_order, void *stream)
+                                                const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
+                                                uint64_t *stats, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_backward: num_views must be 1..%d", kMaxViews);
     LGS_REQUIRE(cameras != nullptr, "lgs_render_backward: invalid camera");
@@ -317,6 +385,8 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
         LGS_REQUIRE(cam_from(&cameras[v], cams[v]), "lgs_render_backward: invalid camera %d", v);
     const int v = variant & 0xF;
     LGS_REQUIRE(v == LGS_RENDER_PLAIN || v == LGS_RENDER_LOCAL, "lgs_render_backward: variant must be PLAIN or LOCAL");
+    const bool fp32 = (variant & LGS_RENDER_FP32) != 0;
+    const bool q8 = (variant & LGS_RENDER_Q8) != 0;
     LGS_REQUIRE(n_elem >= 0, "lgs_render_backward: n < 0");
     LGS_REQUIRE(ranges && out_T && out_ncontrib && grad_rgb, "lgs_render_backward: null input");
     LGS_REQUIRE(n_elem == 0 || (values && means2d && conic_opacity && rgb && g_means2d && g_conic && g_opacity && g_rgb),
@@ -324,24 +394,38 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
     LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0),
                 "lgs_render_backward: misaligned ranges/means2d/conic_opacity");
     hipStream_t s = as_stream(stream);
-    fill_async<float>(g_means2d, 0.f, 2 * n_elem, s);
-    fill_async<float>(g_conic, 0.f, 3 * n_elem, s);
-    fill_async<float>(g_opacity, 0.f, n_elem, s);
-    fill_async<float>(g_rgb, 0.f, 3 * n_elem, s);
+    if (!(variant & LGS_BWD_ACCUMULATE)) {
+        fill_async<float>(g_means2d, 0.f, 2 * n_elem, s);
+        fill_async<float>(g_conic, 0.f, 3 * n_elem, s);
+        fill_async<float>(g_opacity, 0.f, n_elem, s);
+        fill_async<float>(g_rgb, 0.f, 3 * n_elem, s);
+    }
     BwdArgs a;
     a.r = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
-                    const_cast<int32_t *>(out_ncontrib), nullptr);
+                    const_cast<int32_t *>(out_ncontrib), stats);
     a.r.order = tile_order;
+    a.r.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
     a.grad_rgb = grad_rgb; a.grad_T = grad_T;
     a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
     if (a.r.num_tiles > 0) {
-        if (v == LGS_RENDER_LOCAL)
-            if (variant & LGS_RENDER_Q8)
-                hipLaunchKernelGGL((render_bwd_kernel<true, true>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
-            else
-                hipLaunchKernelGGL((render_bwd_kernel<true, false>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((render_bwd_kernel<false, false>), dim3(a.r.num_tiles), dim3(kBlock), 0, s, a);
+        dim3 g(a.r.num_tiles);
+        if (queue != nullptr) {
+            static_assert(kQueues * kQueueStride == LGS_QUEUE_WORDS, "queue block size");
+            fill_async<uint32_t>(queue, 0u, kQueues * kQueueStride, s);
+            a.r.queue = queue;
+            const int per = blocks_per_cu > 0 ? blocks_per_cu : 4;
+            g = dim3((unsigned)((device_cus() * per + kQueues - 1) / kQueues * kQueues));
+        }
+        const bool st = stats != nullptr;
+        if (fp32) {
+            if (v == LGS_RENDER_PLAIN) launch_bwd<false, false, float>(st, g, s, a);
+            else if (q8) launch_bwd<true, true, float>(st, g, s, a);
+            else launch_bwd<true, false, float>(st, g, s, a);
+        } else {
+            if (v == LGS_RENDER_PLAIN) launch_bwd<false, false, double>(st, g, s, a);
+            else if (q8) launch_bwd<true, true, double>(st, g, s, a);
+            else launch_bwd<true, false, double>(st, g, s, a);
+        }
     }
     LGS_LAUNCHED("lgs_render_backward");
     return LGS_OK;
@@ -355,5 +439,5 @@ extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam
 {
     return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, means2d, conic_opacity, rgb, out_T,
                                      out_ncontrib, grad_rgb, grad_T, g_means2d, g_conic, g_opacity, g_rgb, nullptr,
-                                     stream);
+                                     nullptr, 0, nullptr, stream);
 }

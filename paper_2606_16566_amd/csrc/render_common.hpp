@@ -42,6 +42,7 @@ struct RenderArgs {
     uint32_t *queue;            // persistent mode: kQueues counters (zeroed before launch), else null
     const uint32_t *order;      // tile of each queue position (persistent render) or workgroup (backward), or null
     int num_tiles;              // all views
+    int global_origin;          // hoisted basis at the image origin instead of the tile centre
     ViewTable vt;
 };
 
@@ -81,6 +82,7 @@ inline RenderArgs make_args(const Cam *cams, int V, const uint32_t *ranges, cons
     a.stats = reinterpret_cast<unsigned long long *>(stats);
     a.queue = nullptr;
     a.order = nullptr;
+    a.global_origin = 0;
     fill_views(a.vt, cams, V);
     a.num_tiles = a.vt.tile_off[V];
     return a;
@@ -98,8 +100,10 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
 // `strip` (0..3): view, pixel, output offset and the tile-local basis.  The
 // sub-tiles are 16x4 row strips, or with q8 the four 8x8 quadrants.  The
 // tile-local origin is the tile centre, so the basis coordinates are the
-// exact values -7.5 .. 7.5.  [sx0, sx1] x [sy0, sy1] is the sub-tile clipped
-// to the image (empty when no pixel of it is inside).
+// exact values -7.5 .. 7.5 (with global_origin: the image origin, basis
+// coordinates the pixel's own, as in the paper's global-coordinate
+// precision baseline).  [sx0, sx1] x [sy0, sy1] is the sub-tile clipped to
+// the image (empty when no pixel of it is inside).
 template <typename R>
 struct TileCtx {
     int tile, view, tx, ty, wid, px, py, W, H;
@@ -141,10 +145,17 @@ struct TileCtx {
         px = tx * kTile + lx;
         py = ty * kTile + ly;
         inside = px < W && py < H;
-        ox = tx * kTile + 7.5;
-        oy = ty * kTile + 7.5;
-        xl = (R)(lx - 7.5);
-        yl = (R)(ly - 7.5);
+        if (a.global_origin) {
+            ox = 0.0;
+            oy = 0.0;
+            xl = (R)px;
+            yl = (R)py;
+        } else {
+            ox = tx * kTile + 7.5;
+            oy = ty * kTile + 7.5;
+            xl = (R)(lx - 7.5);
+            yl = (R)(ly - 7.5);
+        }
         bxx = xl * xl; bxy = xl * yl; byy = yl * yl;
     }
 };

@@ -18,19 +18,30 @@ VARIANTS = {"plain": L.RENDER_PLAIN, "hoist": L.RENDER_HOIST, "hoist_cull": L.RE
 
 
 def variant_code(variant) -> int:
-    """'local' / 'plain' / ... with optional '_q8', '_v4' and '_fp32'
-    suffixes (in that order, e.g. 'local_q8_v4_fp32'), or an int."""
+    """'local' / 'plain' / ... with optional '_q8', '_v4', '_global' and
+    '_fp32' suffixes (in that order, e.g. 'local_q8_v4_fp32'), or an int."""
     if isinstance(variant, int):
         return variant
     v = variant.lower()
     code = 0
     if v.endswith("_fp32"):
         v, code = v[:-5], code | L.RENDER_FP32
+    if v.endswith("_global"):
+        v, code = v[:-7], code | L.RENDER_GLOBAL
     if v.endswith("_v4"):
         v, code = v[:-3], code | L.RENDER_VOTE4
     if v.endswith("_q8"):
         v, code = v[:-3], code | L.RENDER_Q8
     return VARIANTS[v] | code
+
+
+def backward_variant(variant) -> int:
+    """The backward replay matching a forward variant: PLAIN after the plain
+    renderer, LOCAL after any hoisted one, with the forward's sub-tile shape
+    and precision."""
+    code = variant_code(variant)
+    base = L.RENDER_PLAIN if code & 0xF == L.RENDER_PLAIN else L.RENDER_LOCAL
+    return base | (code & (L.RENDER_Q8 | L.RENDER_FP32 | L.RENDER_GLOBAL))
 
 
 def _p(t):
@@ -170,12 +181,18 @@ def project_backward(cam, means3d, log_scales, quats, opacity_logits, sh, rect, 
     return d
 
 
-def l1_loss(image, target):
+def l1_workspace(device) -> torch.Tensor:
+    """Scratch for lgs_l1_loss's partial sums (one per concurrent call)."""
+    return torch.empty(L.lib().lgs_l1_workspace_size() // 8, dtype=torch.float64, device=device)
+
+
+def l1_loss(image, target, workspace: torch.Tensor | None = None):
     """(loss [1], grad) of mean |image - target|."""
     loss = torch.empty(1, device=image.device)
     grad = torch.empty_like(image)
-    L.check(L.lib().lgs_l1_loss(_p(image), _p(target), image.numel(), _p(loss), _p(grad), _stream()),
-            "lgs_l1_loss")
+    ws = l1_workspace(image.device) if workspace is None else workspace
+    L.check(L.lib().lgs_l1_loss(_p(image), _p(target), image.numel(), _p(loss), _p(grad), _p(ws),
+                                ws.numel() * ws.element_size(), _stream()), "lgs_l1_loss")
     return loss, grad
 
 
@@ -209,8 +226,6 @@ class LocalGSFunction(torch.autograd.Function):
         means3d, log_scales, quats, opacity_logits, sh, T, nc = ctx.saved_tensors
         grad_img = grad_img.contiguous() if grad_img is not None else torch.zeros((3,) + T.shape, device=T.device)
         grad_T = grad_T.contiguous() if grad_T is not None else None
-        code = variant_code(ctx.variant)
-        var = L.RENDER_PLAIN if code & 0xF == L.RENDER_PLAIN else L.RENDER_LOCAL | (code & L.RENDER_Q8)
-        g = render_backward(var, ctx.cam, ctx.binned, ctx.proj, T, nc, grad_img, grad_T)
+        g = render_backward(backward_variant(ctx.variant), ctx.cam, ctx.binned, ctx.proj, T, nc, grad_img, grad_T)
         d = project_backward(ctx.cam, means3d, log_scales, quats, opacity_logits, sh, ctx.proj.rect, g)
         return d["means3d"], d["log_scales"], d["quats"], d["opacity_logits"], d["sh"], None, None, None

@@ -65,8 +65,13 @@ def test_invalid_arguments_rejected_on_host():
     assert st == L.LGS_ERR_INVALID_ARG
     st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, 100, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
-    st = L.lib().lgs_l1_loss(None, None, 0, None, None, None)
+    st = L.lib().lgs_l1_loss(None, None, 0, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
+    # a workspace below lgs_l1_workspace_size() is rejected before any launch
+    one = C.c_void_p(256)
+    st = L.lib().lgs_l1_loss(one, one, 10, one, one, one, L.lib().lgs_l1_workspace_size() - 8, None)
+    assert st == L.LGS_ERR_INVALID_ARG and b"workspace" in L.lib().lgs_last_error()
+    assert L.lib().lgs_l1_workspace_size() >= 8
 
 
 def test_variant_codes():
@@ -86,7 +91,8 @@ def test_batch_and_graph_arguments_rejected_on_host():
     for nv in (0, 17):
         assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 11)) == L.LGS_ERR_INVALID_ARG
         assert lb.lgs_render_batch(3, cams, nv, *([None] * 9), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 15)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 15), 0, None, None) == \
+            L.LGS_ERR_INVALID_ARG
         assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 16)) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
     assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, 10, None, None, None, 0, None) == \

@@ -40,8 +40,13 @@ def assert_grad_close(got, want, name, tol=GRAD_TOL):
 
 
 @pytest.mark.parametrize("seed,W,H,n", [(0, 96, 64, 2000), (1, 160, 128, 12000), (2, 33, 47, 300)])
-@pytest.mark.parametrize("variant", ["plain", "local", "local_q8"])
+@pytest.mark.parametrize("variant", ["plain", "local", "local_q8", "plain_fp32", "local_fp32", "local_q8_fp32"])
 def test_render_backward_parity(seed, W, H, n, variant):
+    """The backward after each forward variant, replayed with that forward's
+    own exponent precision.  Single-precision forwards decide the 1/255 floor
+    and the 0.99 clamp from a float exponent, which is up to ~4e-5 off in
+    ln alpha for the hoisted form (tile-centre coordinates, small splats) and
+    ~1e-5 for the direct one, so their guard is 1e-4."""
     cam, cen, con, op, col, dep = render_only_case(100 + seed, W, H, n, sigma=(0.4, 10.0))
     vis, rect = O.footprint(W, H, cen, con, op)
     dep = np.where(vis == 1, dep, np.float32(np.inf)).astype(np.float32)
@@ -50,9 +55,10 @@ def test_render_backward_parity(seed, W, H, n, variant):
     rng = np.random.default_rng(seed)
     gC = rng.standard_normal((3, H, W)).astype(np.float32)
     gT = rng.standard_normal((H, W)).astype(np.float32)
-    flag = O.grad_flagged(ref, 1e-5)
+    fp32 = variant.endswith("_fp32")
+    flag = O.grad_flagged(ref, 1e-4 if fp32 else 1e-5)
     print(f"render backward {variant} seed={seed}: flagged {int(flag.sum())}/{flag.size}", flush=True)
-    assert flag.mean() <= 1e-3
+    assert flag.mean() <= (1e-2 if fp32 else 1e-3)
     gC[:, flag] = 0.0
     gT[flag] = 0.0
     want = O.render_backward(W, H, off, ids, cen, con, op, col, gC, gT, cam.bg)
@@ -90,6 +96,29 @@ def test_l1_loss_kernel():
     assert float(loss.item()) == pytest.approx(np.abs(x.astype(np.float64) - y).mean(), rel=1e-6)
     want = np.sign(x - y) / x.size
     assert np.array_equal(_np(grad), want.astype(np.float32).astype(np.float64))
+    # deterministic: the partial sums are added in a fixed order
+    loss2, _ = R.l1_loss(to_dev(x), to_dev(y))
+    assert float(loss2.item()) == float(loss.item())
+
+
+def test_l1_loss_concurrent_streams():
+    """Two losses in flight on two streams at once, each with its own
+    workspace, each get their own value (no shared accumulator)."""
+    rng = np.random.default_rng(4)
+    n = 3 * 1080 * 1920
+    xs = [to_dev(rng.uniform(size=n).astype(np.float32)) for _ in range(2)]
+    ys = [to_dev(rng.uniform(size=n).astype(np.float32) * (k + 1)) for k in range(2)]
+    want = [float(np.abs(_np(x) - _np(y)).mean()) for x, y in zip(xs, ys)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(20):
+        outs = []
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                outs.append(R.l1_loss(xs[k], ys[k]))
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert float(outs[k][0].item()) == pytest.approx(want[k], rel=1e-6), (rep, k)
 
 
 def _scene_grad_check(sc, guard=1e-5, variant="local", fd_params=0, seed=0):

@@ -149,22 +149,30 @@ def test_tile_order_is_longest_first_permutation():
         assert np.all(length[nz.max() + 1:] == 0)
 
 
-@pytest.mark.parametrize("bwd_lpt", [True, False])
-def test_batch_backward_equals_sum_of_views(bwd_lpt):
+@pytest.mark.parametrize("variant,bwd_lpt,bwd_persistent,bpc", [
+    ("local", True, False, 0), ("local", False, False, 0), ("local", True, True, 4), ("local", False, True, 2),
+    ("local_q8", True, True, 4), ("local_q8_v4", True, True, 8), ("plain", True, True, 4), ("plain", False, False, 0),
+    ("local_q8_fp32", True, True, 4)])
+def test_batch_backward_equals_sum_of_views(variant, bwd_lpt, bwd_persistent, bpc):
+    """The batch backward (one launch over the tiles of all views, grid or
+    persistent queue, index or longest-first order) equals the sum of the
+    single-view backwards; mixed view sizes with ragged edge tiles."""
     sc = scenes.make_config(5, n=6000)
-    cams = ring_cameras([(128, 96), (100, 100), (64, 48)])
+    cams = ring_cameras([(128, 96), (100, 100), (64, 48), (37, 53)])
     params = scene_tensors(sc)
     rng = np.random.default_rng(7)
     gCs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
-    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local", bwd_lpt=bwd_lpt)
+    print(f"batch backward {variant} lpt={bwd_lpt} persistent={bwd_persistent} bpc={bpc}", flush=True)
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant=variant, bwd_lpt=bwd_lpt, bwd_persistent=bwd_persistent,
+                     bwd_blocks_per_cu=bpc)
     vb.fit(params)
     vb.forward(params)
     vb.backward(params, grad_rgb=vb.pack([to_dev(g) for g in gCs]))
     torch.cuda.synchronize()
     want = {k: 0.0 for k in ("means3d", "log_scales", "quats", "opacity_logits", "sh")}
     for v, c in enumerate(cams):
-        img, T, nc, (proj, binned) = R.rasterize(c, *params, variant="local", binner=R.Binner(capacity=0))
-        g = R.render_backward("local", c, binned, proj, T, nc, to_dev(gCs[v]))
+        img, T, nc, (proj, binned) = R.rasterize(c, *params, variant=variant, binner=R.Binner(capacity=0))
+        g = R.render_backward(R.backward_variant(variant), c, binned, proj, T, nc, to_dev(gCs[v]))
         d = R.project_backward(c, *params, proj.rect, g)
         torch.cuda.synchronize()
         sl = slice(v * sc.n, (v + 1) * sc.n)
@@ -209,6 +217,64 @@ def test_step_graph_replays_match_eager():
                 _close_scaled(g_d[k].cpu().numpy(), t.cpu().numpy(), f"{k}@{rep}")
     finally:
         graph.close()
+
+
+def test_backward_stats_count_replayed_steps():
+    """The backward's counters: replayed steps <= candidate steps, taken
+    pairs <= 64 x replayed steps, identical in grid and persistent mode."""
+    sc = scenes.make_config(5, n=8000)
+    cams = ring_cameras([(160, 120), (96, 64)])
+    params = scene_tensors(sc)
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local_q8")
+    vb.fit(params)
+    vb.forward(params)
+    rng = np.random.default_rng(3)
+    vb.grad_rgb.copy_(to_dev(rng.standard_normal(vb.grad_rgb.numel()).astype(np.float32)))
+    res = []
+    for pers in (False, True):
+        vb.configure(bwd_persistent=pers, bwd_blocks_per_cu=2)
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        vb.backward_render(stats=st)
+        res.append(st.cpu().numpy())
+    for st in res:
+        assert 0 < st[1] <= st[0] and 0 < st[2] <= 64 * st[1] and st[3] == 64 * st[1]
+    assert np.array_equal(res[0][:4], res[1][:4])
+
+
+def test_captured_step_grows_and_recaptures():
+    """A captured step whose pair count outgrows its capacity (the splats
+    grow between replays) overflows, and check() regrows the buffers,
+    captures again and redoes the step: then it equals the eager step."""
+    sc = scenes.make_config(5, n=8000)
+    cams = ring_cameras([(128, 96), (96, 96)])
+    params = scene_tensors(sc)
+    rng = np.random.default_rng(12)
+    target = to_dev(rng.uniform(0, 1, size=3 * sum(c.num_pixels for c in cams)).astype(np.float32))
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local_q8", persistent=True, lpt=True,
+                     bwd_persistent=True)
+    vb.fit(params, headroom=1.05)
+    cap0 = vb.capacity
+    step = B.CapturedStep(vb, lambda: vb.train_step(params, target), headroom=1.1)
+    try:
+        step.replay()
+        assert step.check() is False and step.recaptures == 0
+        with torch.no_grad():
+            params[1].add_(3.0)                           # 20x larger splats: 2.4x the pairs
+        step.replay()
+        assert step.check() is True and step.recaptures >= 1 and vb.capacity > cap0
+        assert not vb.overflowed()
+        g_img = vb.out_rgb.clone()
+        g_d = {k: t.clone() for k, t in vb.grads().items()}
+        step.replay()
+        assert step.check() is False
+        assert torch.equal(g_img, vb.out_rgb)
+        vb.train_step(params, target)
+        torch.cuda.synchronize()
+        assert torch.equal(g_img, vb.out_rgb)
+        for k, t in vb.grads().items():
+            _close_scaled(g_d[k].cpu().numpy(), t.cpu().numpy(), k)
+    finally:
+        step.close()
 
 
 def test_single_view_batch_equals_plain_entry_points():
