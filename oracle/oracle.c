@@ -417,6 +417,96 @@ int64_t oracle_tile_lists(int64_t n, const int32_t *visible, const float *depth,
     return offsets[nt];
 }
 
+/*
+ * Minimum of the quadratic q(d) = a dx^2 + 2 b dx dy + c dy^2 (positive
+ * definite) over the rectangle [x0, x1] x [y0, y1]: 0 if the rectangle holds
+ * the origin, else the minimum lies on its boundary, and along each edge q is
+ * a convex parabola, smallest at its stationary point clamped to the edge.
+ */
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+double oracle_rect_min_q(double a, double b, double c, double x0, double x1, double y0, double y1)
+{
+    if (x0 <= 0.0 && 0.0 <= x1 && y0 <= 0.0 && 0.0 <= y1) return 0.0;
+    double best = INFINITY;
+    const double xs[2] = { x0, x1 }, ys[2] = { y0, y1 };
+    for (int k = 0; k < 2; ++k) {
+        double X = xs[k], Y = clampd(-b * X / c, y0, y1);        /* edge x = X */
+        double v = a * X * X + 2.0 * b * X * Y + c * Y * Y;
+        if (v < best) best = v;
+        Y = ys[k];
+        X = clampd(-b * Y / a, x0, x1);                          /* edge y = Y */
+        v = a * X * X + 2.0 * b * X * Y + c * Y * Y;
+        if (v < best) best = v;
+    }
+    return best;
+}
+
+/*
+ * oracle_tile_lists_exact: per-tile lists as oracle_tile_lists, but a
+ * Gaussian is listed in a tile of its rectangle only where its alpha >= 1/255
+ * ellipse, q <= tau (1 + tau_rel) + tau_abs with tau = 2 ln(255 o), meets the
+ * rectangle spanned by the tile's pixel centres (clip != 0: the in-image ones;
+ * else all 16 x 16) widened by `pad` pixels on every side: the exact
+ * tile-ellipse intersection of the footprint (Sec. II-A's tile assignment
+ * made exact, as in the block-level culling the paper builds on).  Returns
+ * the pair count; with ids == NULL only counts (offsets still filled).
+ */
+int64_t oracle_tile_lists_exact(int64_t n, const int32_t *visible, const float *depth, const int32_t *rect,
+                                const double *means2d, const double *conic, const double *opacity, int W, int H,
+                                double tau_rel, double tau_abs, double pad, int clip, int64_t *offsets,
+                                int32_t *ids)
+{
+    int tiles_x = (W + TILE - 1) / TILE, tiles_y = (H + TILE - 1) / TILE;
+    int64_t nt = (int64_t)tiles_x * tiles_y;
+    for (int64_t t = 0; t <= nt; ++t) offsets[t] = 0;
+    int64_t *fill = ids ? (int64_t *)malloc(sizeof(int64_t) * (nt > 0 ? nt : 1)) : NULL;
+    for (int pass = 0; pass < (ids ? 2 : 1); ++pass) {
+        if (pass == 1) {
+            for (int64_t t = 0; t < nt; ++t) offsets[t + 1] += offsets[t];
+            for (int64_t t = 0; t < nt; ++t) fill[t] = offsets[t];
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (!visible[i]) continue;
+            double a = conic[3 * i], b = conic[3 * i + 1], c = conic[3 * i + 2];
+            double tau = 2.0 * log(255.0 * opacity[i]);
+            double tm = tau * (1.0 + tau_rel) + tau_abs;
+            for (int ty = rect[4 * i + 1]; ty < rect[4 * i + 3]; ++ty)
+                for (int tx = rect[4 * i]; tx < rect[4 * i + 2]; ++tx) {
+                    double px0 = TILE * tx, px1 = TILE * tx + TILE - 1;
+                    double py0 = TILE * ty, py1 = TILE * ty + TILE - 1;
+                    if (clip) {
+                        if (px1 > W - 1) px1 = W - 1;
+                        if (py1 > H - 1) py1 = H - 1;
+                    }
+                    double qm = oracle_rect_min_q(a, b, c, px0 - pad - means2d[2 * i], px1 + pad - means2d[2 * i],
+                                                  py0 - pad - means2d[2 * i + 1], py1 + pad - means2d[2 * i + 1]);
+                    if (!(qm <= tm)) continue;
+                    int64_t t = (int64_t)ty * tiles_x + tx;
+                    if (pass == 0) offsets[t + 1]++;
+                    else ids[fill[t]++] = (int32_t)i;
+                }
+        }
+    }
+    if (!ids) {
+        int64_t p = 0;
+        for (int64_t t = 0; t < nt; ++t) p += offsets[t + 1];
+        return p;
+    }
+    free(fill);
+    int64_t maxlen = 0;
+    for (int64_t t = 0; t < nt; ++t) if (offsets[t + 1] - offsets[t] > maxlen) maxlen = offsets[t + 1] - offsets[t];
+    dkey *buf = (dkey *)malloc(sizeof(dkey) * (maxlen > 0 ? maxlen : 1));
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t a0 = offsets[t], b0 = offsets[t + 1];
+        for (int64_t k = a0; k < b0; ++k) { buf[k - a0].d = depth[ids[k]]; buf[k - a0].id = ids[k]; }
+        qsort(buf, (size_t)(b0 - a0), sizeof(dkey), cmp_dkey);
+        for (int64_t k = a0; k < b0; ++k) ids[k] = buf[k - a0].id;
+    }
+    free(buf);
+    return offsets[nt];
+}
+
 /* ------------------------------------------------------------------------ */
 /* per-pixel blending (Alg. 1, baseline column)                              */
 /* ------------------------------------------------------------------------ */

@@ -89,6 +89,20 @@ def project(cam, means3d, log_scales, quats, logits, sh) -> dict:
     return out
 
 
+def project_chunked(cam, means3d, log_scales, quats, logits, sh, threads=8) -> dict:
+    """project() of large inputs split into chunks of Gaussians on host
+    threads (the C code is reentrant and ctypes releases the GIL), results
+    concatenated in order: identical to one call."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = int(means3d.shape[0])
+    chunk = max(1, -(-n // (4 * threads)))
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda a: project(cam, means3d[a:a + chunk], log_scales[a:a + chunk],
+                                              quats[a:a + chunk], logits[a:a + chunk], sh[a:a + chunk]),
+                            range(0, max(n, 1), chunk)))
+    return {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+
+
 def project_scene(scene, view=0) -> dict:
     return project(scene.cameras[view], scene.means3d, scene.log_scales, scene.quats,
                    scene.opacity_logits, scene.sh)
@@ -130,6 +144,39 @@ def tile_lists(visible, depth, rect, width, height):
     ids = np.zeros(max(p, 1), np.int32)
     lib().oracle_tile_lists(C.c_int64(n), _p(visible), _p(depth), _p(rect), C.c_int(tx), C.c_int(ty),
                             _p(offsets), _p(ids))
+    return offsets, ids[:p]
+
+
+# exact tile assignment: the footprint's slack (as in the rectangle rule), and
+# a looser ellipse that bounds any conservative float implementation of it
+EXACT_TIGHT = dict(tau_rel=1e-5, tau_abs=1e-5, pad=1e-2, clip=True)
+EXACT_LOOSE = dict(tau_rel=2e-3, tau_abs=2e-2, pad=2e-2, clip=False)
+
+
+def rect_min_q(a, b, c, x0, x1, y0, y1) -> float:
+    lib().oracle_rect_min_q.restype = C.c_double
+    return lib().oracle_rect_min_q(*(C.c_double(float(v)) for v in (a, b, c, x0, x1, y0, y1)))
+
+
+def tile_lists_exact(visible, depth, rect, means2d, conic, opacity, width, height, tau_rel=1e-5, tau_abs=1e-5,
+                     pad=1e-2, clip=True):
+    """Per-tile (depth, id)-ordered lists keeping a Gaussian only in the tiles
+    of its rectangle that its alpha >= 1/255 ellipse (with the given slack)
+    meets: (offsets, ids)."""
+    tx, ty = (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+    visible = np.ascontiguousarray(visible, np.int32)
+    rect = np.ascontiguousarray(rect, np.int32)
+    depth = _f32(depth)
+    n = visible.shape[0]
+    lb = lib()
+    lb.oracle_tile_lists_exact.restype = C.c_int64
+    args = [C.c_int64(n), _p(visible), _p(depth), _p(rect), _p(_f64(means2d)), _p(_f64(conic)), _p(_f64(opacity)),
+            C.c_int(width), C.c_int(height), C.c_double(tau_rel), C.c_double(tau_abs), C.c_double(pad),
+            C.c_int(int(clip))]
+    offsets = np.zeros(tx * ty + 1, np.int64)
+    p = lb.oracle_tile_lists_exact(*args, _p(offsets), None)
+    ids = np.zeros(max(p, 1), np.int32)
+    lb.oracle_tile_lists_exact(*args, _p(offsets), _p(ids))
     return offsets, ids[:p]
 
 

@@ -604,3 +604,92 @@ def test_stored_projection_rounds_the_splats_only(oracle):
         assert np.abs(st[k] - pr[k]).max() <= np.abs(pr[k]).max() * 2.0 ** -24
     for k in ("visible", "depth", "rect"):
         assert np.array_equal(st[k], pr[k])
+
+
+def test_chunked_projection_equals_one_call(oracle):
+    sc = scenes.make_config(5, n=3001)
+    cam = sc.cameras[2]
+    a = oracle.project_scene(sc, 2)
+    b = oracle.project_chunked(cam, sc.means3d, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh, threads=3)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+# ---------------------------------------------------------------------------
+# exact tile-ellipse intersection (the tile assignment made exact)
+# ---------------------------------------------------------------------------
+def test_rect_min_quadratic_brute_force(oracle):
+    """The closed-form minimum of a positive-definite quadratic over a
+    rectangle equals a dense sampling of the rectangle (the sampled minimum is
+    never below it and approaches it)."""
+    rng = np.random.default_rng(31)
+    for _ in range(300):
+        s1, s2 = np.exp(rng.uniform(-2, 4, 2))
+        th = rng.uniform(0, np.pi)
+        c_, s_ = math.cos(th), math.sin(th)
+        S = np.array([[c_ * c_ * s1 * s1 + s_ * s_ * s2 * s2, c_ * s_ * (s1 * s1 - s2 * s2)],
+                      [c_ * s_ * (s1 * s1 - s2 * s2), s_ * s_ * s1 * s1 + c_ * c_ * s2 * s2]])
+        K = np.linalg.inv(S)
+        a, b, c = K[0, 0], K[0, 1], K[1, 1]
+        x0, y0 = rng.uniform(-60, 40, 2)
+        x1, y1 = x0 + rng.uniform(0.5, 30), y0 + rng.uniform(0.5, 30)
+        got = oracle.rect_min_q(a, b, c, x0, x1, y0, y1)
+        xs, ys = np.meshgrid(np.linspace(x0, x1, 401), np.linspace(y0, y1, 401))
+        q = a * xs * xs + 2 * b * xs * ys + c * ys * ys
+        assert got <= q.min() * (1 + 1e-12) + 1e-300
+        # the grid's spacing bounds how far above the true minimum it can be
+        h = max(x1 - x0, y1 - y0) / 400
+        grad = 2 * np.sqrt(max(a, c) * max(q.min(), 1e-300)) + 2 * max(a, c) * h
+        assert q.min() - got <= grad * h * 2 + 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_exact_tile_lists_conservative_and_within_rectangles(oracle, seed):
+    """Exact lists: a subset of the rectangle lists in the same order, a
+    superset of the tiles holding a pixel centre with alpha >= 1/255 (brute
+    force), and contained in the lists of the looser ellipse."""
+    rng = np.random.default_rng(800 + seed)
+    W, H = 109, 77
+    cen, conic, opac = _rotated_splats(rng, 800, W, H, sig_hi=60.0)
+    vis, rect = oracle.footprint(W, H, cen, conic, opac)
+    depth = rng.uniform(1, 5, len(opac)).astype(np.float32)
+    off_r, ids_r = oracle.tile_lists(vis, depth, rect, W, H)
+    off_e, ids_e = oracle.tile_lists_exact(vis, depth, rect, cen, conic, opac, W, H, **oracle.EXACT_TIGHT)
+    off_l, ids_l = oracle.tile_lists_exact(vis, depth, rect, cen, conic, opac, W, H, **oracle.EXACT_LOOSE)
+    ntx = (W + 15) // 16
+    xs, ys = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    need = [set() for _ in range(len(off_r) - 1)]
+    for g in np.nonzero(vis)[0]:
+        a, b, c = conic[g]
+        dx, dy = xs - cen[g, 0], ys - cen[g, 1]
+        hit = a * dx * dx + 2 * b * dx * dy + c * dy * dy <= 2 * math.log(255 * opac[g])
+        for t in np.unique((ys[hit] // 16) * ntx + xs[hit] // 16).astype(int):
+            need[t].add(int(g))
+    dropped = 0
+    for t in range(len(off_r) - 1):
+        r = list(ids_r[off_r[t]:off_r[t + 1]])
+        e = list(ids_e[off_e[t]:off_e[t + 1]])
+        lo = set(ids_l[off_l[t]:off_l[t + 1]])
+        assert e == [g for g in r if g in set(e)], t          # same order, a subsequence
+        assert need[t] <= set(e) <= lo, t
+        dropped += len(r) - len(e)
+    assert dropped > 0.1 * len(ids_r)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_exact_tiled_equals_untiled(oracle, seed):
+    """Blending over the exact lists gives the untiled definition bitwise."""
+    sc = scenes.make_config(1, seed=300 + seed, n=1500)
+    sc.cameras = [_cam(88, 56, bg=(0.3, 0.2, 0.1))]
+    sc.means3d[:, 2] -= 1.0
+    cam = sc.cameras[0]
+    pr = oracle.project_scene(sc)
+    off, ids = oracle.tile_lists_exact(pr["visible"], pr["depth"], pr["rect"], pr["means2d"], pr["conic"],
+                                       pr["opacity"], cam.width, cam.height, **oracle.EXACT_TIGHT)
+    t = oracle.render_tiled(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"], pr["rgb"],
+                            cam.bg)
+    u = oracle.render_scene(sc, tiled=False)
+    assert np.array_equal(t["image"], u["image"]) and np.array_equal(t["T"], u["T"])
+    assert np.array_equal(t["last_id"], u["last_id"])
+    off_r, ids_r = oracle.tile_lists(pr["visible"], pr["depth"], pr["rect"], cam.width, cam.height)
+    assert len(ids) < len(ids_r)
