@@ -565,6 +565,100 @@ static void blend_pixel(const splats_t *S, const int32_t *list, int64_t len, dou
 }
 
 /*
+ * Alternatives of one pixel's blend (reading of the several-correct-results
+ * remark, Sec. IV-B): every decision of the blend (the 1/255 floor of a
+ * Gaussian, the 1e-4 stop) whose log-space margin is below `guard` may go
+ * either way under rounding, so the blend is explored along both outcomes of
+ * each such decision, depth first, front to back.  Writes up to max_alts
+ * outcomes (colour + T bg, final T, id of the last blended Gaussian or -1) and
+ * returns their number, or -1 if there were more (then the first max_alts).
+ */
+typedef struct {
+    const splats_t *S;
+    const int32_t *list;
+    int64_t len;
+    double px, py, guard;
+    int max_alts, n;
+    double *img, *T;
+    int32_t *lid;
+    int overflow;
+} alt_ctx;
+
+static void alt_explore(alt_ctx *c, int64_t k0, double T, double a0, double a1, double a2, int32_t lid)
+{
+    if (c->overflow) return;
+    const splats_t *S = c->S;
+    for (int64_t k = k0; k < c->len; ++k) {
+        int32_t g = c->list[k];
+        const double *K = S->conic + 3 * g;
+        double dx = c->px - S->mean[2 * g], dy = c->py - S->mean[2 * g + 1];
+        double q = conic_q(K, dx, dy);
+        double a_raw = S->opac[g] * exp(-0.5 * q);
+        double la = log(S->opac[g]) - 0.5 * q;
+        double alpha = a_raw < ALPHA_MAX ? a_raw : ALPHA_MAX;
+        int keep = !(alpha < ALPHA_MIN);
+        if (fabs(la - log(ALPHA_MIN)) < c->guard) {
+            /* the other outcome of the floor, explored first */
+            if (keep) {
+                alt_explore(c, k + 1, T, a0, a1, a2, lid);
+            } else {
+                double test = T * (1.0 - alpha);
+                if (!(test < T_MIN))
+                    alt_explore(c, k + 1, test, a0 + S->rgb[3 * g] * alpha * T, a1 + S->rgb[3 * g + 1] * alpha * T,
+                                a2 + S->rgb[3 * g + 2] * alpha * T, g);
+            }
+            if (c->overflow) return;
+        }
+        if (!keep) continue;
+        double test = T * (1.0 - alpha);
+        int stop = test < T_MIN;
+        if (T > 0.0 && fabs(log(test) - log(T_MIN)) < c->guard) {
+            if (stop) {
+                alt_explore(c, k + 1, test, a0 + S->rgb[3 * g] * alpha * T, a1 + S->rgb[3 * g + 1] * alpha * T,
+                            a2 + S->rgb[3 * g + 2] * alpha * T, g);
+            } else {
+                /* stopping here instead */
+                if (c->n >= c->max_alts) { c->overflow = 1; return; }
+                c->img[3 * c->n] = a0 + T * S->bg[0];
+                c->img[3 * c->n + 1] = a1 + T * S->bg[1];
+                c->img[3 * c->n + 2] = a2 + T * S->bg[2];
+                c->T[c->n] = T;
+                c->lid[c->n] = lid;
+                c->n++;
+            }
+            if (c->overflow) return;
+        }
+        if (stop) break;
+        a0 += S->rgb[3 * g] * alpha * T;
+        a1 += S->rgb[3 * g + 1] * alpha * T;
+        a2 += S->rgb[3 * g + 2] * alpha * T;
+        T = test;
+        lid = g;
+    }
+    if (c->n >= c->max_alts) { c->overflow = 1; return; }
+    c->img[3 * c->n] = a0 + T * S->bg[0];
+    c->img[3 * c->n + 1] = a1 + T * S->bg[1];
+    c->img[3 * c->n + 2] = a2 + T * S->bg[2];
+    c->T[c->n] = T;
+    c->lid[c->n] = lid;
+    c->n++;
+}
+
+int oracle_blend_alternatives(int W, int H, const int64_t *offsets, const int32_t *ids, const double *means2d,
+                              const double *conic, const double *opacity, const double *rgb, const double *bg,
+                              int x, int y, double guard, int max_alts, double *img, double *T, int32_t *last_id)
+{
+    splats_t S = { means2d, conic, opacity, rgb, { bg[0], bg[1], bg[2] } };
+    int tiles_x = (W + TILE - 1) / TILE;
+    int64_t t = (int64_t)(y / TILE) * tiles_x + x / TILE;
+    (void)H;
+    alt_ctx c = { &S, ids + offsets[t], offsets[t + 1] - offsets[t], (double)x, (double)y, guard, max_alts, 0,
+                  img, T, last_id, 0 };
+    alt_explore(&c, 0, 1.0, 0.0, 0.0, 0.0, -1);
+    return c.overflow ? -1 : c.n;
+}
+
+/*
  * oracle_render_untiled: the plain definition -- every pixel blends every
  * visible Gaussian in ascending (depth, id) order.  Outputs image [3,H,W],
  * T [H,W], last contributing id [H,W], contributor count [H,W], decision

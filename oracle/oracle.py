@@ -299,6 +299,35 @@ def footprint(width, height, means2d, conic, opacity):
     return vis, rect
 
 
+def blend_alternatives(width, height, offsets, ids, means2d, conic, opacity, rgb, bg, x, y, guard, max_alts=64):
+    """All outcomes of pixel (x, y)'s blend when each decision within `guard`
+    of its threshold may go either way: (image [m,3], T [m], last id [m]);
+    raises if there are more than max_alts."""
+    img = np.zeros((max_alts, 3))
+    T = np.zeros(max_alts)
+    lid = np.zeros(max_alts, np.int32)
+    ids = np.ascontiguousarray(ids, np.int32) if len(ids) else np.zeros(1, np.int32)
+    lib().oracle_blend_alternatives.restype = C.c_int
+    m = lib().oracle_blend_alternatives(C.c_int(width), C.c_int(height), _p(np.ascontiguousarray(offsets, np.int64)),
+                                        _p(ids), _p(_f64(means2d)), _p(_f64(conic)), _p(_f64(opacity)), _p(_f64(rgb)),
+                                        _p(_bg(bg)), C.c_int(int(x)), C.c_int(int(y)), C.c_double(guard),
+                                        C.c_int(max_alts), _p(img), _p(T), _p(lid))
+    if m < 0:
+        raise ValueError(f"more than {max_alts} alternative blends at pixel ({x}, {y})")
+    return img[:m], T[:m], lid[:m]
+
+
+def matches_an_alternative(width, height, offsets, ids, splats, bg, x, y, guard, colour, T, last_id, tol):
+    """Does a blend result (colour [3], T, last contributor id) match one of
+    the alternatives of pixel (x, y) within tol (and the id exactly)?"""
+    img, Ts, lids = blend_alternatives(width, height, offsets, ids, splats["means2d"], splats["conic"],
+                                       splats["opacity"], splats["rgb"], bg, x, y, guard)
+    ok = (np.abs(img - np.asarray(colour)[None, :]).max(1) <= tol) & (np.abs(Ts - T) <= tol)
+    if last_id is not None:
+        ok &= lids == last_id
+    return bool(ok.any())
+
+
 def flagged(margin, guard):
     """Pixels whose blend took a skip / stop decision within `guard` (log
     space) of its threshold: either outcome is a correct result there."""

@@ -693,3 +693,62 @@ def test_exact_tiled_equals_untiled(oracle, seed):
     assert np.array_equal(t["last_id"], u["last_id"])
     off_r, ids_r = oracle.tile_lists(pr["visible"], pr["depth"], pr["rect"], cam.width, cam.height)
     assert len(ids) < len(ids_r)
+
+
+# ---------------------------------------------------------------------------
+# alternatives of near-threshold decisions
+# ---------------------------------------------------------------------------
+def _alts(oracle, means, conics, opac, rgb, W, H, x, y, guard, bg=(0, 0, 0)):
+    vis, dep, m, k, o, c = _splats(means, conics, opac, rgb)
+    rect = np.tile(np.int32([[0, 0, (W + 15) // 16, (H + 15) // 16]]), (len(o), 1))
+    off, ids = oracle.tile_lists(vis, dep, rect, W, H)
+    return oracle.blend_alternatives(W, H, off, ids, m, k, o, c, bg, x, y, guard), (off, ids, m, k, o, c)
+
+
+def test_alternatives_single_outcome_off_threshold(oracle):
+    """Far from every threshold a pixel has exactly one outcome, the blend."""
+    rng = np.random.default_rng(5)
+    n = 30
+    means = rng.uniform(0, 31, (n, 2))
+    conics = np.tile([[0.05, 0.01, 0.06]], (n, 1))
+    opac = rng.uniform(0.2, 0.9, n)
+    rgb = rng.uniform(0, 1, (n, 3))
+    (img, T, lid), lists = _alts(oracle, means, conics, opac, rgb, 32, 32, 11, 17, 1e-9, bg=(0.2, 0.3, 0.4))
+    ref = oracle.render_untiled(32, 32, *_splats(means, conics, opac, rgb), bg=(0.2, 0.3, 0.4))
+    assert len(T) == 1 and ref["margin"][17, 11] > 1e-9
+    np.testing.assert_allclose(img[0], ref["image"][:, 17, 11], rtol=0, atol=1e-15)
+    assert T[0] == pytest.approx(ref["T"][17, 11], abs=1e-15) and lid[0] == ref["last_id"][17, 11]
+
+
+def test_alternatives_floor_and_stop_knife_edges(oracle):
+    """A Gaussian at alpha = 1/255 (1 + 1e-9) gives both outcomes of the
+    floor; a stop test at T (1 - alpha) = 1e-4 (1 + 1e-9) both outcomes of
+    the stop.  With the floor Gaussian in front of the stop test: three, as
+    blending it lowers T by 1/255, which moves the later stop test off its
+    threshold (it stops), while skipping it leaves the knife edge (two)."""
+    W = H = 16
+    # floor: o exp(-q/2) = 1/255 (1 + 1e-9) at pixel (5, 5) with the centre at (5, 5 + d)
+    o = 0.5
+    d = math.sqrt(2 * math.log(o * 255 / (1 + 1e-9)) / 0.2)
+    (img, T, lid), _ = _alts(oracle, [[5.0, 5.0 + d]], [[0.2, 0.0, 0.2]], [o], [[0.9, 0.5, 0.1]], W, H, 5, 5, 1e-6)
+    assert len(T) == 2
+    al = 1 / 255 * (1 + 1e-9)
+    got = sorted(zip(T, lid))
+    assert got[0][0] == pytest.approx(1 - al, rel=1e-12) and got[0][1] == 0
+    assert got[1] == (1.0, -1)
+    # stop: alpha_1 = 0.99, then T (1 - alpha_2) = 1e-4 (1 + 1e-9)
+    a2 = 1 - 0.01 * (1 + 1e-9)
+    o2 = a2                                               # centred: alpha = o
+    means = [[8.0, 8.0], [8.0, 8.0]]
+    (img, T, lid), _ = _alts(oracle, means, [[0.3, 0, 0.3]] * 2, [0.995, o2], [[1, 0, 0], [0, 1, 0]], W, H, 8, 8, 1e-6)
+    assert len(T) == 2
+    got = {int(l): (t, tuple(c)) for l, t, c in zip(lid, T, img)}
+    assert got[0][0] == pytest.approx(0.01, rel=1e-12) and got[0][1][1] == 0.0       # stopped before the second
+    assert got[1][0] == pytest.approx(1e-4 * (1 + 1e-9), rel=1e-9)                  # blended the second
+    # both knife edges on one pixel
+    means = [[8.0, 8.0 + d], [8.0, 8.0], [8.0, 8.0]]
+    (img, T, lid), _ = _alts(oracle, means, [[0.2, 0, 0.2], [0.3, 0, 0.3], [0.3, 0, 0.3]], [o, 0.995, o2],
+                             [[0, 0, 1], [1, 0, 0], [0, 1, 0]], W, H, 8, 8, 1e-6)
+    assert len(T) == 3
+    want = sorted([(1 - al) * 0.01, 0.01, 1e-4 * (1 + 1e-9)])
+    np.testing.assert_allclose(sorted(T), want, rtol=1e-9)
