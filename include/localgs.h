@@ -139,6 +139,14 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * (tile << 32 | depth bits) keys emitted in id order.
  *
  * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
+ * means2d [n,2], conic_opacity [n,4] (from lgs_project): NULL (both) to give
+ *   each Gaussian every tile of its rectangle, else the exact tile
+ *   assignment: only the tiles whose pixel-centre square its alpha >= 1/255
+ *   ellipse meets (the test is conservative: a float evaluation on a
+ *   slightly enlarged ellipse), which removes the rectangle's corner tiles
+ *   (about 20% of the pairs of round splats).  Applied on grids at most 256
+ *   tiles wide; wider grids keep the rectangles.  Either way every pixel's
+ *   contributors are listed, so the rendered image is the same.
  * Outputs (device):
  *   tile_keys [capacity_pairs]  tile id of each pair, ascending
  *   values    [capacity_pairs]  Gaussian id of each pair
@@ -151,6 +159,7 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  */
 size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int32_t num_tiles);
 lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
+                    const float *means2d, const float *conic_opacity,
                     uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
                     int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                     void *stream);
@@ -257,6 +266,7 @@ lgs_status lgs_project_batch(const lgs_camera *cams, int32_t num_views, int64_t 
  * lgs_sort_workspace_size(num_views * n_per_view, capacity_pairs, total tiles). */
 lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
                           int64_t n_per_view, const float *depth, const int32_t *rect,
+                          const float *means2d, const float *conic_opacity,
                           uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
                           int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                           void *stream);
@@ -279,6 +289,22 @@ lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num
                             float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
                             uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
                             void *stream);
+
+/* lgs_render_debug -- lgs_render_batch's statistics instantiation (one
+ * workgroup per tile, tiles in index order) that also records the culling
+ * decisions of the culling variants (Sec. III-C-3, the warp mask): for every
+ * list entry j (position in the sorted pairs) that wavefront sub-tile w of
+ * the entry's tile tested, masks[j] gets bit w, and bit 4 + w if the test
+ * kept it (tight-box test passed).  Sub-tiles: 16x4 row strips (w = row
+ * quarter of the tile), or with LGS_RENDER_Q8 8x8 quadrants (w = 2 * row half
+ * + column half).  masks: device uint32 [num_pairs], zeroed by the caller;
+ * stats: device uint64[8] as for lgs_render.  A verification aid (one atomic
+ * per tested entry); the other variants leave masks untouched. */
+lgs_status lgs_render_debug(int32_t variant, const lgs_camera *cams, int32_t num_views,
+                            const uint32_t *ranges, const uint32_t *values,
+                            const float *means2d, const float *conic_opacity, const float *rgb,
+                            float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
+                            uint32_t *masks, void *stream);
 
 /* lgs_tile_order -- longest-first work order for the persistent render: a
  * permutation of the tile ids (device uint32 [num_tiles]) by non-increasing

@@ -36,7 +36,7 @@ EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_s
            "lgs_l1_loss",
            "lgs_project_batch", "lgs_sort_batch", "lgs_render_batch", "lgs_render_backward_batch",
            "lgs_project_backward_batch", "lgs_graph_begin", "lgs_graph_end", "lgs_graph_launch",
-           "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order"]
+           "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order", "lgs_render_debug"]
 
 
 class LgsCamera(C.Structure):
@@ -57,7 +57,7 @@ _SIG = {
     "lgs_version": (C.c_char_p, []),
     "lgs_project": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 11),
     "lgs_sort_workspace_size": (C.c_size_t, [_I64, _I64, _I32]),
-    "lgs_sort": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
+    "lgs_sort": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
     "lgs_tile_ranges": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P]),
     "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 10),
     "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 14),
@@ -65,9 +65,10 @@ _SIG = {
     "lgs_l1_workspace_size": (C.c_size_t, []),
     "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
     "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 11),
-    "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _I64, _P, _P, _P,
-                                 C.c_size_t, _P]),
+    "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
+                                 _P, C.c_size_t, _P]),
     "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9 + [_P, _P, _I32, _P]),
+    "lgs_render_debug": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 11),
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
     "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 15 + [_I32, _P, _P]),

@@ -37,11 +37,13 @@ class ViewBatch:
     bwd_lpt        the backward takes its tiles longest first
     bwd_persistent the backward is one persistent launch of bwd_blocks_per_cu
                    workgroups per compute unit taking tiles from a queue
+    exact_tiles    exact tile assignment in the sort (only the tiles a splat's
+                   alpha >= 1/255 ellipse meets), else whole rectangles
     """
 
     def __init__(self, cams, n: int, sh_degree: int, variant="local_q8", persistent: bool = False,
                  blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda", bwd_lpt: bool = True,
-                 bwd_persistent: bool = False, bwd_blocks_per_cu: int = 0):
+                 bwd_persistent: bool = False, bwd_blocks_per_cu: int = 0, exact_tiles: bool = False):
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_VIEWS:
             raise ValueError(f"a batch holds 1..{L.MAX_VIEWS} cameras, got {len(cams)}")
@@ -88,6 +90,7 @@ class ViewBatch:
         self.bwd_lpt = bool(bwd_lpt)
         self.bwd_persistent = bool(bwd_persistent)
         self.bwd_blocks_per_cu = int(bwd_blocks_per_cu)
+        self.exact_tiles = bool(exact_tiles)
         self.order_ws = torch.empty(L.lib().lgs_tile_order_workspace_size(self.num_tiles) + 256, dtype=torch.uint8,
                                     device=dev)
         self.capacity = 0
@@ -148,8 +151,11 @@ class ViewBatch:
         self.render(stats)
 
     def configure(self, variant=None, persistent=None, blocks_per_cu=None, lpt=None, bwd_lpt=None,
-                  bwd_persistent=None, bwd_blocks_per_cu=None):
-        """Change launch settings (e.g. from the autotuner); buffers are kept."""
+                  bwd_persistent=None, bwd_blocks_per_cu=None, exact_tiles=None):
+        """Change launch settings (e.g. from the autotuner); buffers are kept
+        (a change of exact_tiles changes the pair count: re-fit)."""
+        if exact_tiles is not None:
+            self.exact_tiles = bool(exact_tiles)
         if variant is not None:
             self.variant = variant_code(variant)
         if persistent is not None:
@@ -183,7 +189,9 @@ class ViewBatch:
         """Enqueue the pair sort and the tile ranges of all views."""
         lb, s = L.lib(), _stream()
         ws, wsb = _aligned(self.ws)
+        ex = self.exact_tiles
         L.check(lb.lgs_sort_batch(self.V, self.tiles_x, self.tiles_y, self.n, _p(self.depth), _p(self.rect),
+                                  _p(self.means2d) if ex else None, _p(self.conic_opacity) if ex else None,
                                   _p(self.keys), _p(self.vals), self.capacity, _p(self.num_pairs), _p(self.overflow),
                                   ws, wsb, s), "lgs_sort_batch")
         L.check(lb.lgs_tile_ranges(_p(self.keys), _p(self.num_pairs), _p(self.overflow), self.capacity,

@@ -12,6 +12,9 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "liblocalgs.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "project.hip", "sort.hip", "render.hip", "render_bwd.hip", "graph.hip"]
+# the binning's column histogram and scatter evaluate the same floating-point
+# tile test and must agree bit for bit: no contraction into FMAs there
+EXTRA = {"sort.hip": ["-ffp-contract=off"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
@@ -26,7 +29,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -310,6 +310,13 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
                                                   float *dshi)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
+    // every term below is linear in the incoming gradients: a view that sends
+    // none (the Gaussian culled, or covered by nearer ones in every pixel it
+    // reaches) adds nothing, and whole wavefronts of neighbouring Gaussians
+    // skip it together
+    if (g2.x == 0.f && g2.y == 0.f && g_con[0] == 0.f && g_con[1] == 0.f && g_con[2] == 0.f && g_op == 0.f
+        && g_col[0] == 0.f && g_col[1] == 0.f && g_col[2] == 0.f)
+        return;
     Proj P;
     const bool vis = (r.z > r.x) && (r.w > r.y) && project_geometry(cam, m3, ls, qt, logit, P);
     if (!vis) return;

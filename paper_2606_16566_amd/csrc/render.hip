@@ -181,6 +181,9 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
         const uint64_t bits = __ballot(hit);
         const int cnt = __popcll(bits);
         if (STATS) st.staged += cnt;
+        // culling record: this wavefront tested entry j (bit w) and kept it (bit 4 + w)
+        if (STATS && args.masks != nullptr && j < range.y)
+            atomicOr(&args.masks[j], (1u << tc.wid) | (hit ? (16u << tc.wid) : 0u));
         if (hit) {
             const int slot = __popcll(bits & lt);
             s_e[slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
@@ -342,11 +345,11 @@ void launch_render(const RenderArgs &a, bool stats, bool q8, bool vote4, unsigne
 
 using namespace lgs;
 
-extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
-                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
-                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
-                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
-                                       const uint32_t *tile_order, int32_t blocks_per_cu, void *stream)
+namespace {
+lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views, const uint32_t *ranges,
+                        const uint32_t *values, const float *means2d, const float *conic_opacity, const float *rgb,
+                        float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
+                        const uint32_t *tile_order, int32_t blocks_per_cu, uint32_t *masks, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_batch: num_views must be 1..%d",
                 kMaxViews);
@@ -370,6 +373,7 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     hipStream_t s = as_stream(stream);
     a.order = tile_order;                     // queue position -> tile, or workgroup -> tile
     a.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
+    a.masks = masks;
     const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
     unsigned grid = (unsigned)a.num_tiles;
     if (persistent) {
@@ -398,6 +402,27 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
     }
     LGS_LAUNCHED("lgs_render");
     return LGS_OK;
+}
+}  // namespace
+
+extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
+                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
+                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
+                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
+                                       const uint32_t *tile_order, int32_t blocks_per_cu, void *stream)
+{
+    return render_batch(variant, cameras, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
+                        out_ncontrib, stats, queue, tile_order, blocks_per_cu, nullptr, stream);
+}
+
+extern "C" lgs_status lgs_render_debug(int32_t variant, const lgs_camera *cameras, int32_t num_views,
+                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
+                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
+                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *masks, void *stream)
+{
+    LGS_REQUIRE(stats != nullptr && masks != nullptr, "lgs_render_debug: stats and masks are required");
+    return render_batch(variant, cameras, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
+                        out_ncontrib, stats, nullptr, nullptr, 0, masks, stream);
 }
 
 extern "C" lgs_status lgs_render(int32_t variant, const lgs_camera *camera, const uint32_t *ranges,

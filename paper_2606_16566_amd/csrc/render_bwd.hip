@@ -331,19 +331,23 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     }
     };  // replay_tile
 
-    if (a.queue == nullptr) {
-        replay_tile(a.order ? (int)a.order[blockIdx.x] : xcd_tile(blockIdx.x, a.num_tiles));
-    } else {
-        const uint32_t x = blockIdx.x & (kQueues - 1);
-        uint32_t *counter = a.queue + x * kQueueStride;
-        for (;;) {
+    // one call site of the tile body for both modes (two would be inlined
+    // twice and the register allocation would take the larger of both)
+    const uint32_t x = blockIdx.x & (kQueues - 1);
+    for (int round = 0;; ++round) {
+        int tile;
+        if (a.queue == nullptr) {
+            if (round > 0) break;
+            tile = a.order ? (int)a.order[blockIdx.x] : xcd_tile(blockIdx.x, a.num_tiles);
+        } else {
             __syncthreads();                                // s_pos of the last round read by all
-            if (threadIdx.x == 0) s_pos = atomicAdd(counter, 1u);
+            if (threadIdx.x == 0) s_pos = atomicAdd(a.queue + x * kQueueStride, 1u);
             __syncthreads();
             const uint64_t pos = (uint64_t)s_pos * kQueues + x;
             if (pos >= (uint64_t)a.num_tiles) break;
-            replay_tile(a.order ? (int)a.order[pos] : (int)pos);
+            tile = a.order ? (int)a.order[pos] : (int)pos;
         }
+        replay_tile(tile);
     }
     if (STATS) {
         unsigned long long cand = st.cand, proc = st.proc, taken = st.taken;

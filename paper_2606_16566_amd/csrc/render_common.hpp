@@ -43,6 +43,7 @@ struct RenderArgs {
     const uint32_t *order;      // tile of each queue position (persistent render) or workgroup (backward), or null
     int num_tiles;              // all views
     int global_origin;          // hoisted basis at the image origin instead of the tile centre
+    uint32_t *masks;            // statistics instantiation only: per-entry culling record, or null
     ViewTable vt;
 };
 
@@ -83,6 +84,7 @@ inline RenderArgs make_args(const Cam *cams, int V, const uint32_t *ranges, cons
     a.queue = nullptr;
     a.order = nullptr;
     a.global_origin = 0;
+    a.masks = nullptr;
     fill_views(a.vt, cams, V);
     a.num_tiles = a.vt.tile_off[V];
     return a;

@@ -19,6 +19,7 @@
 // (coalesced, where a gather by the sorted ids would read a whole cache line
 // per 16-byte rectangle), otherwise gathered by its last pass.
 #include "common.hpp"
+#include "render_common.hpp"
 
 namespace lgs {
 namespace {
@@ -747,14 +748,56 @@ struct RectPacked {
     __device__ __forceinline__ int4 operator()(int64_t i) const { return unpack_rect(p[i]); }
 };
 
+// Exact tile assignment.  A splat's tiles are those of its rectangle whose
+// pixel-centre square [16 col, 16 col + 15] x [16 row, 16 row + 15] its
+// alpha >= 1/255 ellipse meets (the tile assignment of Sec. II-A made exact,
+// as in the block-level culling the paper composes with).  Per tile column,
+// the ellipse's vertical span over the column's pixel-centre range (the
+// render's tight-box test of Sec. III-C-2 on the same enlarged ellipse, so the
+// set is a superset of the exact one) gives the rows it meets.  The column
+// histogram counts with this function and the scatter tests its candidates
+// with it; the file is built without floating-point contraction so that both
+// take every decision alike.
+struct Splat {
+    float mx, my, a, b, c, lo;
+};
+
+__device__ __forceinline__ Splat load_splat(const float2 *__restrict__ means2d, const float4 *__restrict__ co,
+                                            uint32_t g)
+{
+    const float2 m = means2d[g];
+    const float4 k = co[g];
+    return Splat{m.x, m.y, k.x, k.y, k.z, __builtin_amdgcn_logf(k.w)};
+}
+
+// tile rows [x, y] (view-local, unclipped; empty when x > y) of tile column
+// `col` that the splat's ellipse meets
+__device__ __forceinline__ int2 exact_rows(const Splat &g, int col)
+{
+    float ymin, ymax;
+    const float x0 = (float)(col * kTile) - g.mx, x1 = x0 + (float)(kTile - 1);
+    if (!render::column_span(g.a, g.b, g.c, g.lo, x0, x1, ymin, ymax)) return make_int2(1, 0);
+    // row r meets when 16 r <= my + ymax and 16 r + 15 >= my + ymin (1e-3 px slack)
+    const float top = fminf(fmaxf(g.my + ymin - 1e-3f, -1e8f), 1e8f);
+    const float bot = fminf(fmaxf(g.my + ymax + 1e-3f, -1e8f), 1e8f);
+    return make_int2((int)ceilf((top - (float)(kTile - 1)) * (1.0f / kTile)), (int)floorf(bot * (1.0f / kTile)));
+}
+
+// geometry of the splats (view-major element ids), or none: rectangles only
+struct SplatGeom {
+    const float2 *means2d;
+    const float4 *conic_opacity;
+};
+
 // Per-block column counts: hist[c * stride + b] = pairs of column c among the
 // Gaussians [b * kColBlock, (b + 1) * kColBlock) of the depth order.  One
 // workgroup counts kHistGroup consecutive blocks (one 16-byte write per
 // column) and writes their pair total to block_pairs[workgroup].
-template <typename RIN>
+template <typename RIN, bool EXACT>
 __global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_t n, int ncols,
                                                           uint32_t *__restrict__ hist, int64_t stride,
-                                                          uint64_t *__restrict__ block_pairs)
+                                                          uint64_t *__restrict__ block_pairs,
+                                                          const uint32_t *__restrict__ order, SplatGeom geom)
 {
     __shared__ uint32_t s_d[kMaxCols + 1];
     __shared__ uint32_t s_warp[kWaves];
@@ -775,10 +818,24 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_
             if (r < n) {
                 const int4 q = rect(r);
                 if (q.z > q.x && q.w > q.y) {
-                    const uint32_t h = (uint32_t)(q.w - q.y);
-                    atomicAdd(&s_d[q.x], h);
-                    atomicAdd(&s_d[q.z], 0u - h);
-                    pairs += (uint64_t)h * (uint64_t)(q.z - q.x);
+                    if constexpr (EXACT) {
+                        // each column its own row count: a difference pair per column
+                        const Splat sp = load_splat(geom.means2d, geom.conic_opacity, order[r]);
+                        for (int col = q.x; col < q.z; ++col) {
+                            const int2 rr = exact_rows(sp, col);
+                            const int h = min(rr.y, q.w - 1) - max(rr.x, q.y) + 1;
+                            if (h > 0) {
+                                atomicAdd(&s_d[col], (uint32_t)h);
+                                atomicAdd(&s_d[col + 1], 0u - (uint32_t)h);
+                                pairs += (uint64_t)h;
+                            }
+                        }
+                    } else {
+                        const uint32_t h = (uint32_t)(q.w - q.y);
+                        atomicAdd(&s_d[q.x], h);
+                        atomicAdd(&s_d[q.z], 0u - h);
+                        pairs += (uint64_t)h * (uint64_t)(q.z - q.x);
+                    }
                 }
             }
         }
@@ -856,11 +913,11 @@ __global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restric
 // column's global start plus the column's pairs in earlier blocks and in
 // earlier chunks of this one.  Places at or past the capacity are not
 // written.
-template <int ITEMS, typename KT, typename RIN>
+template <int ITEMS, typename KT, typename RIN, bool EXACT>
 __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     const uint32_t *__restrict__ order, const RIN rect, uint64_t cap, TileGrids tg, int64_t n,
     const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ col_total, int64_t stride, int ncols,
-    int nbits, KT *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
+    int nbits, KT *__restrict__ keys_out, uint32_t *__restrict__ vals_out, SplatGeom geom)
 {
     constexpr int NT = kColBlock;
     constexpr int kW = NT / 64;
@@ -878,6 +935,12 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     __shared__ __align__(16) uint16_t s_own[kTileN];       // block-local Gaussian of each generated pair
     __shared__ uint16_t s_osort[kTileN];                   // the same, by column
     __shared__ uint32_t s_tot[kW];
+    // exact assignment: the block's splats and the first (view-local) row of
+    // each rectangle; a candidate tile of the rectangle is generated only if
+    // its row is among those the splat meets in its column
+    __shared__ Splat s_sp[EXACT ? NT : 1];
+    __shared__ int s_y0[EXACT ? NT : 1];
+    constexpr uint32_t kNone = 0xFFFFFFFFu;                // key of a candidate the ellipse misses
     const int64_t first = (int64_t)blockIdx.x * NT;
     if (first >= n) return;
     const int cnt = (int)min((int64_t)NT, n - first);
@@ -894,6 +957,10 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
         s_id[t] = g;
         s_row[t] = (uint32_t)(tg.row_off[v] + q.y);
         npairs = has ? (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y) : 0u;
+        if constexpr (EXACT) {
+            if (has) s_sp[t] = load_splat(geom.means2d, geom.conic_opacity, g);
+            s_y0[t] = q.y;
+        }
     }
     {
         // block-local r-major offsets of the Gaussians' pairs
@@ -946,7 +1013,13 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
                             tx = 0;
                             ty = 0;
                         }
-                        kk[e] = ((row + ty) << kColBits) | ((xw & 0xFFFFu) + tx);
+                        const uint32_t col = (xw & 0xFFFFu) + tx;
+                        kk[e] = ((row + ty) << kColBits) | col;
+                        if constexpr (EXACT) {
+                            const int2 rr = exact_rows(s_sp[k], (int)col);
+                            const int r = s_y0[k] + (int)ty;
+                            if (r < rr.x || r > rr.y) kk[e] = kNone;
+                        }
                         ow[e] = (uint32_t)k;
                         if (++tx == w) { tx = 0; ++ty; }
                     }
@@ -970,7 +1043,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const int local = wid * kPerWave + r * 64 + lane;
-            const bool active = local < count;
+            const bool active = local < count && (!EXACT || key[r] != kNone);
             const uint32_t d = key[r] & dmask;
             const uint64_t match = digit_match(active, d, nbits);
             const uint32_t before = active ? s_wc[wid][d] : 0u;
@@ -981,6 +1054,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
         }
         __syncthreads();
         // 3. per column: prefix over wavefronts, chunk offsets, next chunk's bases
+        uint32_t placed;                                      // pairs of this chunk (candidates kept)
         {
             uint32_t ccount = 0;
             if (t < kMaxCols) {
@@ -992,8 +1066,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
                 }
                 s_gb[par ^ 1][t] = s_gb[par][t] + ccount;
             }
-            uint32_t tot;
-            const uint32_t ex = block_exclusive_scan<uint32_t, kW>(ccount, tot, s_tot);
+            const uint32_t ex = block_exclusive_scan<uint32_t, kW>(ccount, placed, s_tot);
             if (t < kMaxCols) s_lbase[t] = ex;
         }
         __syncthreads();
@@ -1001,7 +1074,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const int local = wid * kPerWave + r * 64 + lane;
-            if (local < count) {
+            if (local < count && (!EXACT || key[r] != kNone)) {
                 const uint32_t d = key[r] & dmask;
                 const uint32_t at = lp[r] + s_lbase[d] + s_wc[wid][d];
                 s_buf[at] = key[r];
@@ -1014,7 +1087,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const int i = t + r * NT;
-            if (i < count) {
+            if (i < (int)placed) {
                 const uint32_t k = s_buf[i];
                 const uint32_t d = k & dmask;
                 const uint32_t pos = gb[d] + (uint32_t)i - s_lbase[d];
@@ -1229,6 +1302,7 @@ extern "C" size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int
 
 extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
                                      int64_t n_per_view, const float *depth, const int32_t *rect,
+                                     const float *means2d, const float *conic_opacity,
                                      uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
                                      int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                                      void *stream)
@@ -1265,6 +1339,11 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     LGS_REQUIRE(((uintptr_t)tile_keys % 16 == 0) && ((uintptr_t)values % 16 == 0),
                 "lgs_sort: tile_keys and values must be 16-byte aligned");
     LGS_REQUIRE(rect == nullptr || (uintptr_t)rect % 16 == 0, "lgs_sort: rect must be 16-byte aligned");
+    LGS_REQUIRE((means2d == nullptr) == (conic_opacity == nullptr),
+                "lgs_sort: means2d and conic_opacity go together (both or neither)");
+    LGS_REQUIRE((means2d == nullptr || (uintptr_t)means2d % 8 == 0)
+                    && (conic_opacity == nullptr || (uintptr_t)conic_opacity % 16 == 0),
+                "lgs_sort: misaligned means2d/conic_opacity");
     const size_t need = plan_workspace(nullptr, n, capacity_pairs).bytes;
     LGS_REQUIRE(workspace && workspace_bytes >= need, "lgs_sort: workspace too small (%zu < %zu bytes)",
                 workspace_bytes, need);
@@ -1279,6 +1358,9 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     // well, the rectangles travel packed in 32 bits.
     const bool by_column = ncols <= kMaxCols;
     const bool packed = by_column && nrows <= 256;
+    // exact tile assignment on the column path (grids at most 256 tiles wide)
+    const bool exact = by_column && means2d != nullptr;
+    const SplatGeom geom{reinterpret_cast<const float2 *>(means2d), reinterpret_cast<const float4 *>(conic_opacity)};
     uint32_t *rp[2] = {reinterpret_cast<uint32_t *>(w.rect_sorted), reinterpret_cast<uint32_t *>(w.rect_sorted) + n};
 
     // 1. stable sort of all Gaussians by depth bits (positive floats order
@@ -1328,30 +1410,45 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         const int64_t stride = hist_stride(nbc);
         int cbits = 1;
         while ((1 << cbits) < ncols) ++cbits;
-        if (n > 0 && packed)
-            hipLaunchKernelGGL(col_hist_kernel<RectPacked>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0,
-                               s, rect_packed, n, ncols, w.hist, stride, w.col_pairs);
+        const dim3 hgrid((unsigned)(stride / kHistGroup));
+        if (n > 0 && packed && exact)
+            hipLaunchKernelGGL((col_hist_kernel<RectPacked, true>), hgrid, dim3(kBlock), 0, s, rect_packed, n, ncols,
+                               w.hist, stride, w.col_pairs, order, geom);
+        else if (n > 0 && packed)
+            hipLaunchKernelGGL((col_hist_kernel<RectPacked, false>), hgrid, dim3(kBlock), 0, s, rect_packed, n, ncols,
+                               w.hist, stride, w.col_pairs, order, geom);
+        else if (n > 0 && exact)
+            hipLaunchKernelGGL((col_hist_kernel<RectInt4, true>), hgrid, dim3(kBlock), 0, s, rect_int4, n, ncols,
+                               w.hist, stride, w.col_pairs, order, geom);
         else if (n > 0)
-            hipLaunchKernelGGL(col_hist_kernel<RectInt4>, dim3((unsigned)(stride / kHistGroup)), dim3(kBlock), 0,
-                               s, rect_int4, n, ncols, w.hist, stride, w.col_pairs);
+            hipLaunchKernelGGL((col_hist_kernel<RectInt4, false>), hgrid, dim3(kBlock), 0, s, rect_int4, n, ncols,
+                               w.hist, stride, w.col_pairs, order, geom);
         const int64_t nhg = n > 0 ? stride / kHistGroup : 0;      // column-histogram workgroups
         const PairTotal pt{w.col_pairs, nhg, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
         hipLaunchKernelGGL(col_rowscan_kernel, dim3(n > 0 ? ncols + 1 : 1), dim3(kBlock), 0, s, w.hist, stride, n,
                            n > 0 ? ncols : 0, w.digit_total, pt);
         const uint32_t *hs = w.hist, *ct = w.digit_total;
         const uint64_t cp = (uint64_t)capacity_pairs;
-        if (n > 0 && key16)                                   // 16-bit keys imply packed rectangles
-            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked>), dim3((unsigned)nbc),
-                               dim3(kColBlock), 0, s, order, rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits,
-                               reinterpret_cast<uint16_t *>(k0), v0);
+        const dim3 sgrid((unsigned)nbc), sblk(kColBlock);
+        uint16_t *k16 = reinterpret_cast<uint16_t *>(k0);
+        if (n > 0 && key16 && exact)                          // 16-bit keys imply packed rectangles
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked, true>), sgrid, sblk, 0, s, order,
+                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k16, v0, geom);
+        else if (n > 0 && key16)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked, false>), sgrid, sblk, 0, s, order,
+                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k16, v0, geom);
+        else if (n > 0 && packed && exact)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked, true>), sgrid, sblk, 0, s, order,
+                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
         else if (n > 0 && packed)
-            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked>), dim3((unsigned)nbc),
-                               dim3(kColBlock), 0, s, order, rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits,
-                               k0, v0);
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked, false>), sgrid, sblk, 0, s, order,
+                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
+        else if (n > 0 && exact)
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4, true>), sgrid, sblk, 0, s, order,
+                               rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
         else if (n > 0)
-            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4>), dim3((unsigned)nbc),
-                               dim3(kColBlock), 0, s, order, rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits,
-                               k0, v0);
+            hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4, false>), sgrid, sblk, 0, s, order,
+                               rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
     } else {
         // 3. pair counts in depth order, their exclusive scan (total P,
         //    overflow) and duplication in depth order
@@ -1397,11 +1494,12 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
 }
 
 extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
-                               uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs, int64_t *num_pairs,
-                               int32_t *overflow, void *workspace, size_t workspace_bytes, void *stream)
+                               const float *means2d, const float *conic_opacity, uint32_t *tile_keys,
+                               uint32_t *values, int64_t capacity_pairs, int64_t *num_pairs, int32_t *overflow,
+                               void *workspace, size_t workspace_bytes, void *stream)
 {
-    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, tile_keys, values, capacity_pairs, num_pairs,
-                          overflow, workspace, workspace_bytes, stream);
+    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, means2d, conic_opacity, tile_keys, values,
+                          capacity_pairs, num_pairs, overflow, workspace, workspace_bytes, stream);
 }
 
 extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, const int32_t *overflow,

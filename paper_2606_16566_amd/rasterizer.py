@@ -95,10 +95,13 @@ def project(cam, means3d, log_scales, quats, opacity_logits, sh) -> Projected:
 
 class Binner:
     """Keeps the pair buffers and the sort workspace between calls and grows
-    them when the pair count exceeds the capacity."""
+    them when the pair count exceeds the capacity.  exact=True: the exact
+    tile assignment (only tiles the splat's alpha >= 1/255 ellipse meets),
+    given the projected splats; else every tile of its rectangle."""
 
-    def __init__(self, capacity: int = 0):
+    def __init__(self, capacity: int = 0, exact: bool = False):
         self.capacity = int(capacity)
+        self.exact = bool(exact)
         self.ws = None
         self.keys = self.vals = None
         self.num_pairs = self.overflow = None
@@ -127,7 +130,10 @@ class Binner:
             cap = max(self.capacity, 1)
             ws_base = self.ws.data_ptr()
             ws_aligned = (ws_base + 255) & ~255
-            L.check(L.lib().lgs_sort(n, tx, ty, _p(proj.depth), _p(proj.rect), _p(self.keys), _p(self.vals), cap,
+            geo = self.exact and proj.means2d is not None
+            L.check(L.lib().lgs_sort(n, tx, ty, _p(proj.depth), _p(proj.rect),
+                                     _p(proj.means2d) if geo else None, _p(proj.conic_opacity) if geo else None,
+                                     _p(self.keys), _p(self.vals), cap,
                                      _p(self.num_pairs), _p(self.overflow), C.c_void_p(ws_aligned),
                                      self.ws.numel() - (ws_aligned - ws_base), _stream()), "lgs_sort")
             if check_overflow:

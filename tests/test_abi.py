@@ -63,7 +63,7 @@ def test_invalid_arguments_rejected_on_host():
     assert st == L.LGS_ERR_INVALID_ARG and b"null" in L.lib().lgs_last_error()
     st = L.lib().lgs_render(7, C.byref(cam), *([None] * 10))            # unknown variant
     assert st == L.LGS_ERR_INVALID_ARG
-    st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, 100, None, None, None, 0, None)
+    st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, None, None, 100, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
     st = L.lib().lgs_l1_loss(None, None, 0, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
@@ -95,7 +95,7 @@ def test_batch_and_graph_arguments_rejected_on_host():
             L.LGS_ERR_INVALID_ARG
         assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 16)) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
-    assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, 10, None, None, None, 0, None) == \
+    assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, None, None, 10, None, None, None, 0, None) == \
         L.LGS_ERR_INVALID_ARG
     assert lb.lgs_graph_begin(None) == L.LGS_ERR_INVALID_ARG
     assert lb.lgs_graph_launch(None, None) == L.LGS_ERR_INVALID_ARG

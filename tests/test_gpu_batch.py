@@ -290,3 +290,26 @@ def test_single_view_batch_equals_plain_entry_points():
     for a, b in ((vb.means2d, proj.means2d), (vb.conic_opacity, proj.conic_opacity), (vb.rgb, proj.rgb),
                  (vb.depth, proj.depth), (vb.rect, proj.rect)):
         assert torch.equal(a, b)
+
+
+def test_batch_exact_tiles_equal_rectangles():
+    """The batch in exact-tile mode: the same images bitwise and gradients up
+    to float summation order as with whole rectangles, with fewer pairs."""
+    sc = scenes.make_config(5, n=20000)
+    cams = ring_cameras([(160, 120), (203, 150), (96, 64), (33, 47)])
+    params = scene_tensors(sc)
+    rng = np.random.default_rng(9)
+    target = to_dev(rng.uniform(0, 1, size=3 * sum(c.num_pixels for c in cams)).astype(np.float32))
+    out = {}
+    for exact in (False, True):
+        vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local_q8_v4", persistent=True, lpt=True,
+                         bwd_persistent=True, exact_tiles=exact)
+        vb.fit(params)
+        vb.train_step(params, target)
+        torch.cuda.synchronize()
+        out[exact] = (vb.out_rgb.clone(), vb.out_T.clone(), int(vb.num_pairs.item()),
+                      {k: t.cpu().numpy() for k, t in vb.grads().items()})
+    assert out[True][2] < out[False][2]
+    assert torch.equal(out[True][0], out[False][0]) and torch.equal(out[True][1], out[False][1])
+    for k in out[True][3]:
+        _close_scaled(out[True][3][k], out[False][3][k], k)

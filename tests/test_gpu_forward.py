@@ -37,20 +37,41 @@ GUARD_E2E = 1e-4
 MAX_FLAGGED = 1e-3        # fraction of pixels a parity gate may leave out
 
 
-def check_vs_oracle(img, T, lid, ref, guard, label, max_flagged=MAX_FLAGGED, tol=TOL_ORACLE, pix=None):
+def check_vs_oracle(img, T, lid, ref, guard, label, lists=None, max_flagged=MAX_FLAGGED, tol=TOL_ORACLE, pix=None,
+                    at=None):
     """Colour and T within `tol` and identical last contributor on pixels
-    whose decisions are outside `guard`; at most `max_flagged` flagged.
-    `pix` selects sampled pixels ([m,2] x, y) of full-image GPU outputs."""
+    whose decisions are outside `guard`.  Flagged pixels (a decision within
+    the guard): with `lists` = (W, H, offsets, ids, splats, bg) of the oracle's
+    blend, each must match one of the oracle's alternative blends (every
+    decision within the guard taken either way, reading of the several-
+    correct-results remark), so no pixel is left out; without, they are left
+    out.  At most `max_flagged` of the pixels may be flagged.  `pix` selects
+    sampled pixels ([m,2] x, y) of full-image GPU outputs; `at` gives the
+    pixels of outputs that are already sampled."""
     if pix is not None:
         img = img[:, pix[:, 1], pix[:, 0]]
         T = T[pix[:, 1], pix[:, 0]]
         lid = lid[pix[:, 1], pix[:, 0]]
+        at = pix
     flag = O.flagged(ref["margin"], guard)
     ok = ~flag
     e_img = float(np.abs(img - ref["image"])[:, ok].max()) if ok.any() else 0.0
     e_T = float(np.abs(T - ref["T"])[ok].max()) if ok.any() else 0.0
-    print(f"  {label}: flagged {int(flag.sum())}/{flag.size} ({flag.mean():.2e}) at guard {guard:g}; "
-          f"max-abs colour {e_img:.2e}, T {e_T:.2e}", flush=True)
+    resolved = 0
+    if lists is not None and flag.any():
+        W, H, off, ids, sp, bg = lists
+        for i in zip(*np.nonzero(flag)):
+            if at is not None:
+                x, y = int(at[i[0], 0]), int(at[i[0], 1])
+                colour, t, l = img[:, i[0]], T[i[0]], lid[i[0]] if lid is not None else None
+            else:
+                y, x = int(i[0]), int(i[1])
+                colour, t, l = img[:, y, x], T[y, x], lid[y, x] if lid is not None else None
+            assert O.matches_an_alternative(W, H, off, ids, sp, bg, x, y, guard, colour, t, l, tol), \
+                (label, "flagged pixel matches no alternative", x, y)
+            resolved += 1
+    print(f"  {label}: flagged {int(flag.sum())}/{flag.size} ({flag.mean():.2e}) at guard {guard:g}, "
+          f"{resolved} matched an alternative blend; max-abs colour {e_img:.2e}, T {e_T:.2e}", flush=True)
     assert flag.mean() <= max_flagged, (label, flag.mean())
     assert e_img <= tol and e_T <= tol, (label, e_img, e_T)
     if lid is not None:
@@ -346,15 +367,18 @@ def test_end_to_end_parity(cfg, n, view):
     pr = O.project_scene(sc, view)
     ref = O.render_scene(sc, view, proj=pr, stored=True)      # the float32-stored projection
     ref64 = O.render_scene(sc, view, proj=pr)                  # the unrounded FP64 projection
+    lists = (cam.width, cam.height, ref["offsets"], ref["ids"], ref["proj"], cam.bg)
+    lists64 = (cam.width, cam.height, ref64["offsets"], ref64["ids"], ref64["proj"], cam.bg)
     imgs = {}
     for v in ("plain", "local", "local_q8", "local_q8_v4"):
         img, T, nc, (proj, b) = R.rasterize(cam, *scene_tensors(sc), variant=v)
         imgs[v] = _sync_np(img)
         lid = last_ids(b, nc, cam)
-        check_vs_oracle(imgs[v], _sync_np(T), lid, ref, GUARD_RENDER, f"{v} vs stored projection")
+        check_vs_oracle(imgs[v], _sync_np(T), lid, ref, GUARD_RENDER, f"{v} vs stored projection", lists)
         # the float32 storage of the projected mean alone can flip a decision
-        # of the unrounded projection; reported, not gated at 1e-3
-        check_vs_oracle(imgs[v], _sync_np(T), lid, ref64, GUARD_E2E, f"{v} vs FP64 projection", max_flagged=1e-2)
+        # of the unrounded projection
+        check_vs_oracle(imgs[v], _sync_np(T), lid, ref64, GUARD_E2E, f"{v} vs FP64 projection", lists64,
+                        max_flagged=1e-2)
     assert np.abs(imgs["local"] - imgs["plain"]).max() <= TOL_LADDER
     assert np.array_equal(imgs["local"], imgs["local_q8"])
     assert np.array_equal(imgs["local"], imgs["local_q8_v4"])
@@ -397,7 +421,71 @@ def test_full_size_sampled_parity():
     st = O.stored_projection(pr)
     ref = O.render_tiled(cam.width, cam.height, off, ids, st["means2d"], st["conic"], st["opacity"], st["rgb"],
                          cam.bg, pixels=pix)
-    check_vs_oracle(img, T, lid, ref, GUARD_RENDER, "c2 full size vs stored projection", pix=pix)
+    check_vs_oracle(img, T, lid, ref, GUARD_RENDER, "c2 full size vs stored projection",
+                    (cam.width, cam.height, off, ids, st, cam.bg), max_flagged=1e-2, pix=pix)
     ref64 = O.render_tiled(cam.width, cam.height, off, ids, pr["means2d"], pr["conic"], pr["opacity"], pr["rgb"],
                            cam.bg, pixels=pix)
-    check_vs_oracle(img, T, lid, ref64, GUARD_E2E, "c2 full size vs FP64 projection", max_flagged=1e-2, pix=pix)
+    check_vs_oracle(img, T, lid, ref64, GUARD_E2E, "c2 full size vs FP64 projection",
+                    (cam.width, cam.height, off, ids, pr, cam.bg), max_flagged=1e-2, pix=pix)
+
+
+# ---------------------------------------------------------------------------
+# exact tile assignment
+# ---------------------------------------------------------------------------
+def _gpu_lists(b, num_tiles):
+    rg = _sync_np(b.ranges).astype(np.int64) & 0xFFFFFFFF
+    vals = _sync_np(b.values).astype(np.int64) & 0xFFFFFFFF
+    return [vals[rg[t, 0]:rg[t, 1]] for t in range(num_tiles)]
+
+
+@pytest.mark.parametrize("seed,W,H,n,sigma", [(40, 160, 96, 6000, (0.3, 20.0)), (41, 333, 97, 3000, (0.05, 150.0)),
+                                              (42, 64, 64, 400, (2.0, 60.0))])
+def test_exact_tile_assignment_lists(seed, W, H, n, sigma):
+    """Exact mode: every tile's list is an ordered subsequence of its
+    rectangle list, holds every splat whose alpha >= 1/255 ellipse meets the
+    tile's pixel centres (the oracle's exact rule without slack), and only
+    splats whose barely larger ellipse meets the tile's square (the oracle's
+    loose rule)."""
+    cam, cen, con, op, col, dep = render_only_case(seed, W, H, n, sigma=sigma, margin=40.0)
+    vis, rect = O.footprint(W, H, cen, con, op)
+    dep = np.where(vis == 1, dep, np.float32(np.inf)).astype(np.float32)
+    off_r, ids_r = O.tile_lists(vis, dep, rect, W, H)
+    off_p, ids_p = O.tile_lists_exact(vis, dep, rect, cen, con, op, W, H, tau_rel=0.0, tau_abs=0.0, pad=0.0, clip=True)
+    off_l, ids_l = O.tile_lists_exact(vis, dep, rect, cen, con, op, W, H, **O.EXACT_LOOSE)
+    proj = projected_from(cen, con, op, col, dep, rect)
+    b = R.Binner(capacity=len(ids_r) + 64, exact=True).run(cam, proj)
+    P = int(b.num_pairs.item())
+    print(f"exact lists seed={seed}: rectangle pairs {len(ids_r)}, exact {P}, pure {len(ids_p)}, loose {len(ids_l)}",
+          flush=True)
+    assert len(ids_p) <= P <= len(ids_l) and P < len(ids_r)
+    got = _gpu_lists(b, cam.num_tiles)
+    for t in range(cam.num_tiles):
+        r = ids_r[off_r[t]:off_r[t + 1]]
+        g = got[t]
+        keep = np.isin(r, g)
+        assert np.array_equal(r[keep], g), t                      # ordered subsequence
+        assert set(ids_p[off_p[t]:off_p[t + 1]]) <= set(g.tolist()) <= set(ids_l[off_l[t]:off_l[t + 1]]), t
+
+
+@pytest.mark.parametrize("cfg,n,view", [(2, 30000, 0), (3, 60000, 0), (4, 50000, 0)])
+def test_exact_tiles_render_identically(cfg, n, view):
+    """Exact mode removes only list entries that no pixel of the tile blends:
+    images and T are bitwise those of the rectangle mode, every pixel has the
+    same last contributor, and the image matches the oracle."""
+    sc = scenes.make_config(cfg, n=n)
+    cam = sc.cameras[view]
+    ps = scene_tensors(sc)
+    res = {}
+    for exact in (False, True):
+        for v in ("plain", "local_q8_v4"):
+            img, T, nc, (proj, b) = R.rasterize(cam, *ps, variant=v, binner=R.Binner(exact=exact))
+            res[exact, v] = (_sync_np(img), _sync_np(T), last_ids(b, nc, cam), int(b.num_pairs.item()))
+    print(f"exact cfg={cfg}: pairs {res[False, 'plain'][3]} -> {res[True, 'plain'][3]}", flush=True)
+    assert res[True, "plain"][3] < res[False, "plain"][3]
+    for v in ("plain", "local_q8_v4"):
+        for k in range(3):
+            assert np.array_equal(res[False, v][k], res[True, v][k]), (v, k)
+    ref = O.render_scene(sc, view, stored=True)
+    img, T, lid, _ = res[True, "local_q8_v4"]
+    check_vs_oracle(img, T, lid, ref, GUARD_RENDER, f"exact cfg={cfg} vs stored projection",
+                    (cam.width, cam.height, ref["offsets"], ref["ids"], ref["proj"], cam.bg))
