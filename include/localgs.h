@@ -165,6 +165,25 @@ lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *de
                     void *stream);
 
 /*
+ * lgs_sort_noalloc -- lgs_sort for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same sort, same outputs, with the library's own scratch
+ * instead of a workspace argument.  The scratch is a static device array of
+ * LGS_SORT_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; a call
+ * whose lgs_sort_workspace_size(n, capacity_pairs, tiles) exceeds it returns
+ * LGS_ERR_INVALID_ARG (with the sizes in lgs_last_error()) and enqueues
+ * nothing.  The call allocates nothing (the scratch's address is looked up
+ * once per device, on the first call with that device current).  Every call
+ * on one GPU shares that GPU's scratch: calls that overlap on one GPU (other
+ * streams, other host threads) race; calls in one stream are ordered.  The
+ * scratch keeps the last call's contents; each call clears what it needs.
+ */
+#define LGS_SORT_NOALLOC_SCRATCH_BYTES (64u << 20)
+lgs_status lgs_sort_noalloc(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
+                            const float *means2d, const float *conic_opacity, uint32_t *tile_keys, uint32_t *values,
+                            int64_t capacity_pairs, int64_t *num_pairs, int32_t *overflow, void *stream);
+
+/*
  * lgs_tile_ranges -- [start, end) of every tile's run in the sorted pairs
  * (Sec. II-A, "tile ranges").  ranges [num_tiles,2] uint32 (device); tiles
  * without pairs get (0, 0), and so do all tiles if *overflow != 0.

@@ -31,7 +31,9 @@ BWD_ACCUMULATE = 0x100
 MAX_VIEWS = 16
 QUEUE_WORDS = 256
 
-EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort",
+SORT_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort", "lgs_sort_noalloc",
            "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_workspace_size",
            "lgs_l1_loss",
            "lgs_project_batch", "lgs_sort_batch", "lgs_render_batch", "lgs_render_backward_batch",
@@ -58,6 +60,7 @@ _SIG = {
     "lgs_project": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 11),
     "lgs_sort_workspace_size": (C.c_size_t, [_I64, _I64, _I32]),
     "lgs_sort": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
+    "lgs_sort_noalloc": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
     "lgs_tile_ranges": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P]),
     "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 10),
     "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 14),

@@ -18,6 +18,8 @@
 // payload of its passes when every view is at most 256 tiles wide and high
 // (coalesced, where a gather by the sorted ids would read a whole cache line
 // per 16-byte rectangle), otherwise gathered by its last pass.
+#include <mutex>
+
 #include "common.hpp"
 #include "render_common.hpp"
 
@@ -1500,6 +1502,50 @@ extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, cons
 {
     return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, means2d, conic_opacity, tile_keys, values,
                           capacity_pairs, num_pairs, overflow, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// lgs_sort_noalloc: lgs_sort on the library's own scratch.  The scratch is a
+// file-scope device array; in host code its name is not a device address, so
+// the address is looked up with hipGetSymbolAddress once per device (on the
+// first call with that device current) and only that address is passed on.
+// Every call on a device shares its array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LGS_SORT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+extern "C" lgs_status lgs_sort_noalloc(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth,
+                                       const int32_t *rect, const float *means2d, const float *conic_opacity,
+                                       uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                                       int64_t *num_pairs, int32_t *overflow, void *stream)
+{
+    LGS_REQUIRE(n >= 0 && capacity_pairs >= 0, "lgs_sort_noalloc: n and capacity_pairs must be >= 0");
+    const size_t need = plan_workspace(nullptr, n, capacity_pairs).bytes;
+    LGS_REQUIRE(need <= (size_t)LGS_SORT_NOALLOC_SCRATCH_BYTES,
+                "lgs_sort_noalloc: %lld Gaussians with a capacity of %lld pairs need %zu bytes of scratch, more "
+                "than the library's %zu; use lgs_sort with a workspace of lgs_sort_workspace_size() bytes",
+                (long long)n, (long long)capacity_pairs, need, (size_t)LGS_SORT_NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    LGS_HIP(hipGetDevice(&dev));
+    LGS_REQUIRE(dev >= 0 && dev < 64, "lgs_sort_noalloc: device index %d out of range", dev);
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (g_scratch_ptr[dev] == nullptr) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            LGS_REQUIRE(e == hipSuccess && p != nullptr, "lgs_sort_noalloc: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+            g_scratch_ptr[dev] = p;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, means2d, conic_opacity, tile_keys, values,
+                          capacity_pairs, num_pairs, overflow, ptr, (size_t)LGS_SORT_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 extern "C" lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, const int32_t *overflow,

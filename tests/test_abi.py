@@ -74,6 +74,21 @@ def test_invalid_arguments_rejected_on_host():
     assert L.lib().lgs_l1_workspace_size() >= 8
 
 
+def test_sort_noalloc_rejects_sizes_beyond_its_scratch():
+    """Checked on the host before any HIP call: runs without a GPU."""
+    L = _lib()
+    lb = L.lib()
+    n = 4_000_000
+    assert lb.lgs_sort_workspace_size(n, n, 64) > L.SORT_NOALLOC_SCRATCH_BYTES
+    assert lb.lgs_sort_workspace_size(10_000, 50_000, 256) <= L.SORT_NOALLOC_SCRATCH_BYTES
+    st = lb.lgs_sort_noalloc(n, 8, 8, None, None, None, None, None, None, n, None, None, None)
+    assert st == L.LGS_ERR_INVALID_ARG
+    msg = lb.lgs_last_error()
+    assert b"scratch" in msg and str(L.SORT_NOALLOC_SCRATCH_BYTES).encode() in msg
+    assert lb.lgs_sort_noalloc(-1, 8, 8, None, None, None, None, None, None, 0, None, None, None) == \
+        L.LGS_ERR_INVALID_ARG
+
+
 def test_variant_codes():
     from paper_2606_16566_amd import rasterizer as R
     L = _lib()
