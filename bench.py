@@ -31,7 +31,6 @@ import argparse
 import json
 import math
 import os
-import subprocess
 import sys
 import time
 from concurrent.futures import ThreadPoolExecutor
@@ -105,18 +104,25 @@ def tensors(sc, torch):
     return [torch.from_numpy(a).to(dev) for a in (sc.means3d, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh)]
 
 
-def gpu_clock_mhz():
-    """Current shader clock (MHz) from rocm-smi, or None."""
+def gpu_clock_mhz(torch):
+    """Current shader clock (MHz) from the amdgpu driver's sysfs table of
+    shader clock levels (the active level is starred), or None.  Read from a
+    file so that no child process is started after the GPU is initialised."""
+    paths = []
     try:
-        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20).stdout
-    except (OSError, subprocess.SubprocessError):
-        return None
-    for line in out.splitlines():
-        if "sclk" in line and "Mhz" in line:
-            try:
-                return float(line.split("(")[-1].split("Mhz")[0])
-            except ValueError:
-                pass
+        p = torch.cuda.get_device_properties(0)
+        paths.append(f"/sys/bus/pci/devices/{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:{p.pci_device_id:02x}.0"
+                     "/pp_dpm_sclk")
+    except (AttributeError, RuntimeError):
+        pass
+    for path in paths:
+        try:
+            with open(path) as f:
+                for line in f:
+                    if line.rstrip().endswith("*"):
+                        return float(line.split(":", 1)[1].lower().split("mhz")[0])
+        except (OSError, ValueError, IndexError):
+            pass
     return None
 
 
@@ -523,8 +529,7 @@ def train_workload(label, sc, cams, args, torch, target_seed, steps=None, fwd_to
             vb.backward_render(stats=sb)
             s, sb = s.cpu().numpy(), sb.cpu().numpy()
             t_fwd = kernel_times(vb.blend, max(5, steps // 2), torch)["median_ms"]
-            for t in (vb.g_means2d, vb.g_conic, vb.g_opacity, vb.g_rgb):
-                t.zero_()
+            vb.g_splats.zero_()
             t_bwd = kernel_times(lambda: vb.backward_render(accumulate=True), max(5, steps // 2), torch)["median_ms"]
             E, K, V, n = vb.V * vb.n, vb.K, vb.V, vb.n
             st = ent["stages_ms"]
@@ -617,7 +622,7 @@ def main():
     model, avail = host_cpu()
     workers = max(1, min(12, avail - 2))
     orc = OracleSamples(workers) if use_cpu else None
-    clock0 = gpu_clock_mhz()
+    clock0 = gpu_clock_mhz(torch)
 
     # scenes (host) and oracle jobs, submitted first so the oracle works while the GPU does
     log("generating scenes")
@@ -677,7 +682,7 @@ def main():
         head = train_workload(scenes.CONFIG_NAMES[5], sc[5], sc[5].cameras, args, torch, 105, steps=args.steps,
                               fwd_too=True)
         configs["c5"] = head
-    clock1 = gpu_clock_mhz()
+    clock1 = gpu_clock_mhz(torch)
     log("GPU work done; waiting for the oracle")
     cpu = None
     if cpu_fut is not None:

@@ -36,6 +36,31 @@ extern "C" {
 
 #define LGS_TILE 16
 
+/*
+ * Projected splat record: LGS_SPLAT_FLOATS floats (64 bytes) per Gaussian
+ * (per view in a batch), written by lgs_project and read by the sort's exact
+ * tile assignment, the render and the backward:
+ *   [0..3]   a, b, c, o   conic (inverse 2D covariance, with a 0.3 px^2
+ *                         low-pass added to the covariance) and opacity
+ *   [4..5]   x, y         projected mean in pixels
+ *   [6..8]   r, g, b      view-dependent colour, clamped at 0
+ *   [9..15]  unused: never read; lgs_project writes them as zero, so that
+ *            every record is written as one whole 64-byte sector
+ * Record arrays must be 16-byte aligned; with 64-byte alignment (any
+ * hipMalloc'd base) every record is one 64-byte memory sector, so that the
+ * render's and the backward's gathers, whose addresses follow the depth
+ * order of each tile's list, read one sector per (tile, Gaussian) instead of
+ * one per attribute array.
+ *
+ * Gradient record: LGS_GRAD_FLOATS floats (36 bytes, packed) per element,
+ * dL/d (a, b, c, o, x, y, r, g, b) in the order of the splat record's first
+ * nine floats.  The backward adds its per-(tile, Gaussian) sums into it with
+ * atomics (one or two cache lines per record) after clearing it; packed, the
+ * clear writes no padding.  4-byte alignment.
+ */
+#define LGS_SPLAT_FLOATS 16
+#define LGS_GRAD_FLOATS 9
+
 typedef enum {
     LGS_OK = 0,
     LGS_ERR_INVALID_ARG = 1,
@@ -108,10 +133,9 @@ const char *lgs_version(void);
  *   [n] (opacity = sigmoid), sh [n,(sh_degree+1)^2,3] real SH coefficients.
  *   sh_degree in 0..3.
  * Outputs (device):
- *   means2d [n,2]         projected mean in pixels
- *   conic_opacity [n,4]   (a, b, c, o): inverse 2D covariance (with a 0.3 px^2
- *                         low-pass added to the covariance) and opacity
- *   rgb [n,3]             view-dependent colour, clamped at 0
+ *   splats [n,LGS_SPLAT_FLOATS] projected splat records (conic, opacity,
+ *                         mean, colour; layout at LGS_SPLAT_FLOATS); culled
+ *                         Gaussians get an all-zero record
  *   depth [n]             depth key: the float32 rounding of camera-space z
  *   rect [n,4]            touched tiles [tx0, ty0, tx1, ty1): the tiles
  *                         holding a pixel centre of the alpha >= 1/255 ellipse;
@@ -122,8 +146,7 @@ const char *lgs_version(void);
 lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
                        const float *means3d, const float *log_scales, const float *quats,
                        const float *opacity_logits, const float *sh,
-                       float *means2d, float *conic_opacity, float *rgb, float *depth,
-                       int32_t *rect, void *stream);
+                       float *splats, float *depth, int32_t *rect, void *stream);
 
 /*
  * lgs_sort -- duplication of every visible Gaussian into one (tile, id) pair
@@ -139,9 +162,8 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * (tile << 32 | depth bits) keys emitted in id order.
  *
  * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
- * means2d [n,2], conic_opacity [n,4] (from lgs_project): NULL (both) to give
- *   each Gaussian every tile of its rectangle, else the exact tile
- *   assignment: only the tiles whose pixel-centre square its alpha >= 1/255
+ * splats [n,LGS_SPLAT_FLOATS] (from lgs_project): NULL to give each
+ *   Gaussian every tile of its rectangle, else the exact tile assignment: only the tiles whose pixel-centre square its alpha >= 1/255
  *   ellipse meets (the test is conservative: a float evaluation on a
  *   slightly enlarged ellipse), which removes the rectangle's corner tiles
  *   (about 20% of the pairs of round splats).  Applied on grids at most 256
@@ -159,8 +181,7 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  */
 size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int32_t num_tiles);
 lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
-                    const float *means2d, const float *conic_opacity,
-                    uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                    const float *splats, uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
                     int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                     void *stream);
 
@@ -180,8 +201,8 @@ lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *de
  */
 #define LGS_SORT_NOALLOC_SCRATCH_BYTES (64u << 20)
 lgs_status lgs_sort_noalloc(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
-                            const float *means2d, const float *conic_opacity, uint32_t *tile_keys, uint32_t *values,
-                            int64_t capacity_pairs, int64_t *num_pairs, int32_t *overflow, void *stream);
+                            const float *splats, uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                            int64_t *num_pairs, int32_t *overflow, void *stream);
 
 /*
  * lgs_tile_ranges -- [start, end) of every tile's run in the sorted pairs
@@ -198,8 +219,8 @@ lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, 
  * q = a dx^2 + 2 b dx dy + c dy^2, d = p - mean; Gaussians with
  * alpha < 1/255 are skipped; blending stops before the first Gaussian that
  * would take the transmittance T below 1e-4; C += rgb * alpha * T.
- * Inputs: ranges from lgs_tile_ranges, values from lgs_sort, projected
- * attributes from lgs_project.  `variant` is an lgs_render_variant.
+ * Inputs: ranges from lgs_tile_ranges, values from lgs_sort, the splat
+ * records from lgs_project.  `variant` is an lgs_render_variant.
  * Outputs (device): out_rgb [3,H,W] = C + T * bg; out_T [H,W] final T;
  *   out_ncontrib [H,W] 1-based position, in the tile's list, of the last
  *   blended Gaussian (0 if none).
@@ -209,16 +230,14 @@ lgs_status lgs_tile_ranges(const uint32_t *tile_keys, const int64_t *num_pairs, 
  *   [3] lane evaluations.  Counting runs a separate, slower instantiation.
  */
 lgs_status lgs_render(int32_t variant, const lgs_camera *cam, const uint32_t *ranges, const uint32_t *values,
-                      const float *means2d, const float *conic_opacity, const float *rgb,
-                      float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats, void *stream);
+                      const float *splats, float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats, void *stream);
 
 /*
  * lgs_render_backward -- gradient of L through the blending, given
  * grad_rgb = dL/d out_rgb [3,H,W] and optionally grad_T = dL/d out_T [H,W]
  * (NULL = 0).  Replays each pixel back to front from its last contributor,
- * recovering T from the stored final T.  Writes (overwrites) dL/d means2d
- * [n,2], dL/d conic (a, b, c) [n,3], dL/d opacity [n], dL/d rgb [n,3];
- * the clamp at 0.99 and all skip / stop decisions are held fixed.
+ * recovering T from the stored final T.  Writes (overwrites) the gradient
+ * records g_splats [n,LGS_GRAD_FLOATS] (see LGS_GRAD_FLOATS); the clamp at 0.99 and all skip / stop decisions are held fixed.
  * `variant` is LGS_RENDER_PLAIN or LGS_RENDER_LOCAL (hoisted, culled), the
  * latter optionally with LGS_RENDER_Q8 (8x8 wavefront quadrants for the
  * culling), either with LGS_RENDER_FP32 when the forward ran a single-
@@ -234,24 +253,22 @@ lgs_status lgs_render(int32_t variant, const lgs_camera *cam, const uint32_t *ra
  */
 #define LGS_BWD_ACCUMULATE 0x100
 lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam, int64_t n, const uint32_t *ranges,
-                               const uint32_t *values, const float *means2d, const float *conic_opacity,
-                               const float *rgb, const float *out_T, const int32_t *out_ncontrib,
-                               const float *grad_rgb, const float *grad_T,
-                               float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
-                               void *stream);
+                               const uint32_t *values, const float *splats, const float *out_T,
+                               const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
+                               float *g_splats, void *stream);
 
 /*
  * lgs_project_backward -- chain rule from the projected attributes back to
  * the raw parameters of lgs_project (same inputs, plus its rect output to
- * know which Gaussians were culled).  Writes (overwrites) d_means3d [n,3],
+ * know which Gaussians were culled), given the gradient records g_splats
+ * [n,LGS_GRAD_FLOATS].  Writes (overwrites) d_means3d [n,3],
  * d_log_scales [n,3], d_quats [n,4], d_opacity_logits [n],
  * d_sh [n,(deg+1)^2,3]; culled Gaussians get zero.
  */
 lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_degree,
                                 const float *means3d, const float *log_scales, const float *quats,
                                 const float *opacity_logits, const float *sh, const int32_t *rect,
-                                const float *g_means2d, const float *g_conic, const float *g_opacity,
-                                const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                const float *g_splats, float *d_means3d, float *d_log_scales,
                                 float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
 
 /*
@@ -259,8 +276,8 @@ lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_deg
  * differ) of one Gaussian set in single launches, the paper's stages applied
  * to each view unchanged (Sec. II-A, Sec. III).  Layouts:
  *   - per-Gaussian projected arrays are view-major: element e = v * n + i
- *     (means2d [V*n,2], conic_opacity [V*n,4], rgb [V*n,3], depth [V*n],
- *     rect [V*n,4] and their gradients);
+ *     (splats [V*n,LGS_SPLAT_FLOATS], depth [V*n], rect [V*n,4] and the
+ *     gradient records);
  *   - tiles of all views form one global index space: view v owns tiles
  *     [T_v, T_v + tiles_x(v) * tiles_y(v)) with T_v the sum of the tile
  *     counts of the views before it; pair values are element ids e;
@@ -277,16 +294,14 @@ lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_deg
 lgs_status lgs_project_batch(const lgs_camera *cams, int32_t num_views, int64_t n, int32_t sh_degree,
                              const float *means3d, const float *log_scales, const float *quats,
                              const float *opacity_logits, const float *sh,
-                             float *means2d, float *conic_opacity, float *rgb, float *depth,
-                             int32_t *rect, void *stream);
+                             float *splats, float *depth, int32_t *rect, void *stream);
 
 /* lgs_sort over num_views * n_per_view elements; tiles_x / tiles_y are host
  * arrays [num_views].  The workspace size is
  * lgs_sort_workspace_size(num_views * n_per_view, capacity_pairs, total tiles). */
 lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
                           int64_t n_per_view, const float *depth, const int32_t *rect,
-                          const float *means2d, const float *conic_opacity,
-                          uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                          const float *splats, uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
                           int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                           void *stream);
 
@@ -303,8 +318,7 @@ lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32
  *   lgs_tile_order) giving the tile of each queue position, or of each
  *   workgroup without a queue.  Outputs do not depend on the order. */
 lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num_views,
-                            const uint32_t *ranges, const uint32_t *values,
-                            const float *means2d, const float *conic_opacity, const float *rgb,
+                            const uint32_t *ranges, const uint32_t *values, const float *splats,
                             float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
                             uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
                             void *stream);
@@ -320,8 +334,7 @@ lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num
  * stats: device uint64[8] as for lgs_render.  A verification aid (one atomic
  * per tested entry); the other variants leave masks untouched. */
 lgs_status lgs_render_debug(int32_t variant, const lgs_camera *cams, int32_t num_views,
-                            const uint32_t *ranges, const uint32_t *values,
-                            const float *means2d, const float *conic_opacity, const float *rgb,
+                            const uint32_t *ranges, const uint32_t *values, const float *splats,
                             float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
                             uint32_t *masks, void *stream);
 
@@ -354,11 +367,9 @@ lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *o
  * The gradients do not depend on the order or the schedule beyond float
  * summation order. */
 lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, int32_t num_views, int64_t n_elem,
-                                     const uint32_t *ranges, const uint32_t *values, const float *means2d,
-                                     const float *conic_opacity, const float *rgb, const float *out_T,
-                                     const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
-                                     float *g_means2d, float *g_conic, float *g_opacity, float *g_rgb,
-                                     const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
+                                     const uint32_t *ranges, const uint32_t *values, const float *splats,
+                                     const float *out_T, const int32_t *out_ncontrib, const float *grad_rgb,
+                                     const float *grad_T, float *g_splats, const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
                                      uint64_t *stats, void *stream);
 
 /* lgs_project_backward of a batch: the view-major gradients of the projected
@@ -367,8 +378,7 @@ lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, in
 lgs_status lgs_project_backward_batch(const lgs_camera *cams, int32_t num_views, int64_t n, int32_t sh_degree,
                                       const float *means3d, const float *log_scales, const float *quats,
                                       const float *opacity_logits, const float *sh, const int32_t *rect,
-                                      const float *g_means2d, const float *g_conic, const float *g_opacity,
-                                      const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                      const float *g_splats, float *d_means3d, float *d_log_scales,
                                       float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
 
 /*

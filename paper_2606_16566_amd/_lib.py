@@ -32,6 +32,8 @@ MAX_VIEWS = 16
 QUEUE_WORDS = 256
 
 SORT_NOALLOC_SCRATCH_BYTES = 64 << 20
+SPLAT_FLOATS = 16   # floats per projected splat record (64 bytes)
+GRAD_FLOATS = 9     # floats per packed gradient record
 
 EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_size", "lgs_sort", "lgs_sort_noalloc",
            "lgs_tile_ranges", "lgs_render", "lgs_render_backward", "lgs_project_backward", "lgs_l1_workspace_size",
@@ -57,25 +59,25 @@ _I32 = C.c_int32
 _SIG = {
     "lgs_last_error": (C.c_char_p, []),
     "lgs_version": (C.c_char_p, []),
-    "lgs_project": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 11),
+    "lgs_project": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 9),
     "lgs_sort_workspace_size": (C.c_size_t, [_I64, _I64, _I32]),
-    "lgs_sort": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
-    "lgs_sort_noalloc": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
+    "lgs_sort": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
+    "lgs_sort_noalloc": (C.c_int, [_I64, _I32, _I32, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
     "lgs_tile_ranges": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P]),
-    "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 10),
-    "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 14),
-    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 16),
+    "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 8),
+    "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 9),
+    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 13),
     "lgs_l1_workspace_size": (C.c_size_t, []),
     "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
-    "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 11),
-    "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _P, _P, _I64, _P, _P,
+    "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 9),
+    "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _P, _I64, _P, _P,
                                  _P, C.c_size_t, _P]),
-    "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9 + [_P, _P, _I32, _P]),
-    "lgs_render_debug": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 11),
+    "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 7 + [_P, _P, _I32, _P]),
+    "lgs_render_debug": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9),
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
-    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 15 + [_I32, _P, _P]),
-    "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 16),
+    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 10 + [_I32, _P, _P]),
+    "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 13),
     "lgs_graph_begin": (C.c_int, [_P]),
     "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
     "lgs_graph_launch": (C.c_int, [_P, _P]),

@@ -67,10 +67,13 @@ class ViewBatch:
         E = V * self.n
         f32, i32, dev = torch.float32, torch.int32, self.dev
         z = lambda *shape, dtype=f32: torch.zeros(shape, dtype=dtype, device=dev)
-        # projected attributes and their gradients, view-major [V*n, ...]
-        self.means2d, self.conic_opacity, self.rgb = z(E, 2), z(E, 4), z(E, 3)
+        # projected splat records [V*n, SPLAT_FLOATS] and gradient records
+        # [V*n, GRAD_FLOATS], view-major, with named views of their fields
+        self.splats, self.g_splats = z(E, L.SPLAT_FLOATS), z(E, L.GRAD_FLOATS)
+        self.conic_opacity, self.means2d, self.rgb = self.splats[:, 0:4], self.splats[:, 4:6], self.splats[:, 6:9]
+        self.g_conic, self.g_opacity = self.g_splats[:, 0:3], self.g_splats[:, 3]
+        self.g_means2d, self.g_rgb = self.g_splats[:, 4:6], self.g_splats[:, 6:9]
         self.depth, self.rect = z(E), z(E, 4, dtype=i32)
-        self.g_means2d, self.g_conic, self.g_opacity, self.g_rgb = z(E, 2), z(E, 3), z(E), z(E, 3)
         # raw-parameter gradients [n, ...], summed over views
         self.d_means3d, self.d_log_scales, self.d_quats = z(self.n, 3), z(self.n, 3), z(self.n, 4)
         self.d_logits, self.d_sh = z(self.n), z(self.n, self.K, 3)
@@ -182,8 +185,8 @@ class ViewBatch:
         lb, s = L.lib(), _stream()
         means3d, log_scales, quats, logits, sh = params
         L.check(lb.lgs_project_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales), _p(quats),
-                                     _p(logits), _p(sh), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
-                                     _p(self.depth), _p(self.rect), s), "lgs_project_batch")
+                                     _p(logits), _p(sh), _p(self.splats), _p(self.depth), _p(self.rect), s),
+                "lgs_project_batch")
 
     def sort(self):
         """Enqueue the pair sort and the tile ranges of all views."""
@@ -191,8 +194,7 @@ class ViewBatch:
         ws, wsb = _aligned(self.ws)
         ex = self.exact_tiles
         L.check(lb.lgs_sort_batch(self.V, self.tiles_x, self.tiles_y, self.n, _p(self.depth), _p(self.rect),
-                                  _p(self.means2d) if ex else None, _p(self.conic_opacity) if ex else None,
-                                  _p(self.keys), _p(self.vals), self.capacity, _p(self.num_pairs), _p(self.overflow),
+                                  _p(self.splats) if ex else None, _p(self.keys), _p(self.vals), self.capacity, _p(self.num_pairs), _p(self.overflow),
                                   ws, wsb, s), "lgs_sort_batch")
         L.check(lb.lgs_tile_ranges(_p(self.keys), _p(self.num_pairs), _p(self.overflow), self.capacity,
                                    self.num_tiles, _p(self.ranges), s), "lgs_tile_ranges")
@@ -217,8 +219,7 @@ class ViewBatch:
         lb, s = L.lib(), _stream()
         order = _p(self.order) if self.lpt else None
         L.check(lb.lgs_render_batch(self.variant, self.cam_arr, self.V, _p(self.ranges), _p(self.vals),
-                                    _p(self.means2d), _p(self.conic_opacity), _p(self.rgb), _p(self.out_rgb),
-                                    _p(self.out_T), _p(self.out_nc), _p(stats),
+                                    _p(self.splats), _p(self.out_rgb), _p(self.out_T), _p(self.out_nc), _p(stats),
                                     _p(self.queue) if self.persistent else None, order, self.blocks_per_cu, s),
                 "lgs_render_batch")
 
@@ -249,10 +250,8 @@ class ViewBatch:
         if self.bwd_lpt and not self._fwd_lpt():
             self.tile_order(force=True)                  # the forward did not compute it
         L.check(lb.lgs_render_backward_batch(bv, self.cam_arr, self.V, self.V * self.n, _p(self.ranges),
-                                             _p(self.vals), _p(self.means2d), _p(self.conic_opacity), _p(self.rgb),
-                                             _p(self.out_T), _p(self.out_nc), _p(g), _p(grad_T), _p(self.g_means2d),
-                                             _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
-                                             _p(self.order) if self.bwd_lpt else None,
+                                             _p(self.vals), _p(self.splats), _p(self.out_T), _p(self.out_nc), _p(g),
+                                             _p(grad_T), _p(self.g_splats), _p(self.order) if self.bwd_lpt else None,
                                              _p(self.bwd_queue) if self.bwd_persistent else None,
                                              self.bwd_blocks_per_cu, _p(stats), s),
                 "lgs_render_backward_batch")
@@ -263,8 +262,7 @@ class ViewBatch:
         lb, s = L.lib(), _stream()
         means3d, log_scales, quats, logits, sh = params
         L.check(lb.lgs_project_backward_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales),
-                                              _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_means2d),
-                                              _p(self.g_conic), _p(self.g_opacity), _p(self.g_rgb),
+                                              _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_splats),
                                               _p(self.d_means3d), _p(self.d_log_scales), _p(self.d_quats),
                                               _p(self.d_logits), _p(self.d_sh), s), "lgs_project_backward_batch")
 

@@ -20,6 +20,13 @@ constexpr float kAlphaMax = 0.99f;       // opacity clamp (Sec. III-D-1)
 constexpr double kTMin = 1e-4;           // termination threshold (Alg. 1)
 constexpr double kLowpass = 0.3;         // 2D covariance dilation, px^2
 constexpr double kGuard = 1.3;           // Jacobian evaluated inside 1.3x the frustum
+// projected splat record: float4 (a, b, c, o), float4 (x, y, r, g), float b
+// at float 8, zero padding; one 64-byte sector per element.  Gradient
+// record: the same nine floats, packed.
+constexpr int kSplatF = LGS_SPLAT_FLOATS;
+constexpr int kSplatV = kSplatF / 4;     // float4 slots per record
+constexpr int kGradF = LGS_GRAD_FLOATS;
+static_assert(kSplatF == 16 && kGradF == 9, "record layouts");
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.6931471805599453094;
 // Footprint slack: tiles are assigned for the ellipse q <= tau*(1+rel)+abs,
@@ -111,6 +118,27 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+// record e of a splat (or gradient) record array
+__device__ __forceinline__ const float4 *splat_rec(const float *s, uint64_t e)
+{
+    return reinterpret_cast<const float4 *>(s) + e * kSplatV;
+}
+
+__device__ __forceinline__ float4 *splat_rec(float *s, uint64_t e)
+{
+    return reinterpret_cast<float4 *>(s) + e * kSplatV;
+}
+
+// the whole record as four 16-byte stores (one full sector)
+__device__ __forceinline__ void store_splat(float *s, uint64_t e, float4 co, float4 mr, float b)
+{
+    float4 *r = splat_rec(s, e);
+    r[0] = co;
+    r[1] = mr;
+    r[2] = make_float4(b, 0.f, 0.f, 0.f);
+    r[3] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
 
 // fill kernel used instead of hipMemsetAsync so that every clear is an
 // ordinary kernel node (graph-capture friendly)

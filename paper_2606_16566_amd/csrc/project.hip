@@ -59,11 +59,16 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y)
     }
 }
 
-// g = sum_k w[k] grad Y_k at (x, y, z): the weighted gradient of the basis,
-// accumulated term by term so that no per-basis gradient table is held.
-template <int DEG>
-__device__ __forceinline__ void sh_grad_dir(double x, double y, double z, const double *w, double *g)
+// g = sum_k w(k) grad Y_k at (x, y, z): the weighted gradient of the basis,
+// accumulated term by term so that no per-basis gradient table is held; the
+// weights come from a callable, evaluated where each is used (no table of
+// them either).
+template <int DEG, typename WF>
+__device__ __forceinline__ void sh_grad_dir(double x, double y, double z, WF &&wf, double *g)
 {
+    double w[16];
+#pragma unroll
+    for (int k = 1; k < (DEG + 1) * (DEG + 1); ++k) w[k] = wf(k);
     const ShConst k = sh_consts();
     double gx = 0.0, gy = 0.0, gz = 0.0;
     if (DEG >= 1) {
@@ -96,7 +101,8 @@ struct Proj {
     bool visible;
     double m[3], s[3], qn[4], qlen, o;
     double t[3];
-    double R[3][3], M[3][3], S3[3][3];
+    double R[3][3];
+    double TM[2][3];         // T M with M = R diag(s): Sigma2 = TM TM^T + low-pass
     double u, v;             // clamped tangent-plane coordinates
     bool uc, vc;             // clamp active
     double J00, J02, J11, J12;
@@ -142,11 +148,6 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const float *l
     P.R[1][0] = 2.0 * (x * y + w * z); P.R[1][1] = 1.0 - 2.0 * (x * x + z * z); P.R[1][2] = 2.0 * (y * z - w * x);
     P.R[2][0] = 2.0 * (x * z - w * y); P.R[2][1] = 2.0 * (y * z + w * x); P.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
     for (int j = 0; j < 3; ++j) P.s[j] = exp((double)ls[j]);
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) P.M[i][j] = P.R[i][j] * P.s[j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            P.S3[i][j] = P.M[i][0] * P.M[j][0] + P.M[i][1] * P.M[j][1] + P.M[i][2] * P.M[j][2];
     const double fx = cam.fx, fy = cam.fy;
     const double limx = kGuard * (double)cam.tanx, limy = kGuard * (double)cam.tany;
     const double tz = P.t[2], rz = 1.0 / tz;
@@ -160,13 +161,13 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const float *l
         P.T[0][j] = P.J00 * (double)V[0 * 4 + j] + P.J02 * (double)V[2 * 4 + j];
         P.T[1][j] = P.J11 * (double)V[1 * 4 + j] + P.J12 * (double)V[2 * 4 + j];
     }
-    double TS[2][3];
+    // Sigma2 = T Sigma3 T^T + low-pass with Sigma3 = M M^T: Sigma2 = (T M)(T M)^T
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 3; ++j)
-            TS[i][j] = P.T[i][0] * P.S3[0][j] + P.T[i][1] * P.S3[1][j] + P.T[i][2] * P.S3[2][j];
-    P.X = TS[0][0] * P.T[0][0] + TS[0][1] * P.T[0][1] + TS[0][2] * P.T[0][2] + kLowpass;
-    P.Y = TS[1][0] * P.T[1][0] + TS[1][1] * P.T[1][1] + TS[1][2] * P.T[1][2] + kLowpass;
-    P.Z = TS[0][0] * P.T[1][0] + TS[0][1] * P.T[1][1] + TS[0][2] * P.T[1][2];
+            P.TM[i][j] = (P.T[i][0] * P.R[0][j] + P.T[i][1] * P.R[1][j] + P.T[i][2] * P.R[2][j]) * P.s[j];
+    P.X = P.TM[0][0] * P.TM[0][0] + P.TM[0][1] * P.TM[0][1] + P.TM[0][2] * P.TM[0][2] + kLowpass;
+    P.Y = P.TM[1][0] * P.TM[1][0] + P.TM[1][1] * P.TM[1][1] + P.TM[1][2] * P.TM[1][2] + kLowpass;
+    P.Z = P.TM[0][0] * P.TM[1][0] + P.TM[0][1] * P.TM[1][1] + P.TM[0][2] * P.TM[1][2];
     P.det = P.X * P.Y - P.Z * P.Z;
     if (!(P.det > 0.0)) return false;
     const double id = 1.0 / P.det;
@@ -246,8 +247,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
                                                           const float *__restrict__ log_scales,
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
-                                                          const float *__restrict__ sh, float2 *__restrict__ means2d,
-                                                          float4 *__restrict__ conic_opacity, float *__restrict__ rgb,
+                                                          const float *__restrict__ sh, float *__restrict__ splats,
                                                           float *__restrict__ depth, int4 *__restrict__ rect)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
@@ -272,9 +272,8 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
         int4 r = make_int4(0, 0, 0, 0);
         const bool vis = sh_ok && project_geometry(cam, m3, ls, qt, logit, P) && footprint(cam, P, r);
         if (!vis) {
-            means2d[o] = make_float2(0.f, 0.f);
-            conic_opacity[o] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rgb[3 * o] = 0.f; rgb[3 * o + 1] = 0.f; rgb[3 * o + 2] = 0.f;
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            store_splat(splats, (uint64_t)o, z, z, 0.f);
             depth[o] = INFINITY;
             rect[o] = make_int4(0, 0, 0, 0);
             continue;
@@ -287,9 +286,9 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
         }
-        means2d[o] = make_float2((float)P.mx, (float)P.my);
-        conic_opacity[o] = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
-        for (int ch = 0; ch < 3; ++ch) rgb[3 * o + ch] = (float)fmax(col[ch], 0.0);
+        store_splat(splats, (uint64_t)o, make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o),
+                    make_float4((float)P.mx, (float)P.my, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0)),
+                    (float)fmax(col[2], 0.0));
         depth[o] = (float)P.t[2];
         rect[o] = r;
     }
@@ -317,35 +316,46 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
     if (g2.x == 0.f && g2.y == 0.f && g_con[0] == 0.f && g_con[1] == 0.f && g_con[2] == 0.f && g_op == 0.f
         && g_col[0] == 0.f && g_col[1] == 0.f && g_col[2] == 0.f)
         return;
+    if (!((r.z > r.x) && (r.w > r.y))) return;
+    // The colour's gradient first: it needs only the view direction, so its
+    // basis and weights are dead before the projection's intermediates are
+    // recomputed below (fewer registers live at once).
+    double gm[3] = {0.0, 0.0, 0.0};
+    {
+        const double d0 = (double)m3[0] - (double)cam.campos[0], d1 = (double)m3[1] - (double)cam.campos[1],
+                     d2 = (double)m3[2] - (double)cam.campos[2];
+        const double dlen = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        double dir[3] = {0.0, 0.0, 1.0};
+        if (dlen > 0.0) { dir[0] = d0 / dlen; dir[1] = d1 / dlen; dir[2] = d2 / dlen; }
+        double gcol[3] = {g_col[0], g_col[1], g_col[2]};
+        // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
+        double Y[K];
+        sh_eval<DEG>(dir[0], dir[1], dir[2], Y);
+        for (int ch = 0; ch < 3; ++ch) {
+            double val = 0.5;
+            for (int k = 0; k < K; ++k) val += (double)shi[3 * k + ch] * Y[k];
+            if (val < 0.0) gcol[ch] = 0.0;
+        }
+        // re-read the coefficients from LDS below rather than keeping all 3K
+        // of them in registers across the passes (a compiler barrier only)
+        __asm__ volatile("" ::: "memory");
+        for (int k = 0; k < K; ++k)
+            for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] += (float)(gcol[ch] * Y[k]);
+        // dL/d dir = sum_k (sum_ch gcol_ch sh_k,ch) grad Y_k
+        double gdir[3];
+        sh_grad_dir<DEG>(dir[0], dir[1], dir[2], [&](int k) {
+            return gcol[0] * (double)shi[3 * k] + gcol[1] * (double)shi[3 * k + 1] + gcol[2] * (double)shi[3 * k + 2];
+        }, gdir);
+        if (dlen > 0.0) {
+            const double dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
+            for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - dir[k] * dd) / dlen;
+        }
+    }
     Proj P;
-    const bool vis = (r.z > r.x) && (r.w > r.y) && project_geometry(cam, m3, ls, qt, logit, P);
-    if (!vis) return;
+    if (!project_geometry(cam, m3, ls, qt, logit, P)) return;
     const double gmx = g2.x, gmy = g2.y;
     const double ga = g_con[0], gb = g_con[1], gc = g_con[2];
     const double go = g_op;
-    double gcol[3] = {g_col[0], g_col[1], g_col[2]};
-
-    // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
-    double Y[K];
-    sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
-    for (int ch = 0; ch < 3; ++ch) {
-        double val = 0.5;
-        for (int k = 0; k < K; ++k) val += (double)shi[3 * k + ch] * Y[k];
-        if (val < 0.0) gcol[ch] = 0.0;
-    }
-    // dL/d dir = sum_k (sum_ch gcol_ch sh_k,ch) grad Y_k
-    double wk[K];
-    for (int k = 0; k < K; ++k)
-        wk[k] = gcol[0] * (double)shi[3 * k] + gcol[1] * (double)shi[3 * k + 1] + gcol[2] * (double)shi[3 * k + 2];
-    double gdir[3];
-    sh_grad_dir<DEG>(P.dir[0], P.dir[1], P.dir[2], wk, gdir);
-    for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] += (float)(gcol[ch] * Y[k]);
-    double gm[3] = {0.0, 0.0, 0.0};
-    if (P.dlen > 0.0) {
-        const double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
-        for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - P.dir[k] * dd) / P.dlen;
-    }
 
     // opacity = sigmoid(logit)
     acc.logit += go * P.o * (1.0 - P.o);
@@ -355,20 +365,17 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
     const double gX = ga * (-P.Y * P.Y * id2) + gb * (P.Z * P.Y * id2) + gc * (id - P.X * P.Y * id2);
     const double gY = ga * (id - P.Y * P.X * id2) + gb * (P.Z * P.X * id2) + gc * (-P.X * P.X * id2);
     const double gZ = ga * (2.0 * P.Y * P.Z * id2) + gb * (-id - 2.0 * P.Z * P.Z * id2) + gc * (2.0 * P.X * P.Z * id2);
-    // symmetric gradient of Sigma2 = T Sigma3 T^T (+ low-pass)
+    // symmetric gradient of Sigma2 = TM TM^T (+ low-pass), TM = T M:
+    // dL/dTM = 2 G2 TM, then dL/dT = dL/dTM M^T and dL/dM = T^T dL/dTM
     const double G2[2][2] = {{gX, 0.5 * gZ}, {0.5 * gZ, gY}};
-    // dL/dSigma3 = T^T G2 T
-    double GT[2][3];
+    double gTM[2][3];
     for (int i2 = 0; i2 < 2; ++i2)
-        for (int j = 0; j < 3; ++j) GT[i2][j] = G2[i2][0] * P.T[0][j] + G2[i2][1] * P.T[1][j];
-    double G3[3][3];
-    for (int k = 0; k < 3; ++k)
-        for (int j = 0; j < 3; ++j) G3[k][j] = P.T[0][k] * GT[0][j] + P.T[1][k] * GT[1][j];
-    // dL/dT = 2 G2 T Sigma3
+        for (int j = 0; j < 3; ++j) gTM[i2][j] = 2.0 * (G2[i2][0] * P.TM[0][j] + G2[i2][1] * P.TM[1][j]);
     double gT[2][3];
     for (int i2 = 0; i2 < 2; ++i2)
-        for (int j = 0; j < 3; ++j)
-            gT[i2][j] = 2.0 * (GT[i2][0] * P.S3[0][j] + GT[i2][1] * P.S3[1][j] + GT[i2][2] * P.S3[2][j]);
+        for (int k = 0; k < 3; ++k)
+            gT[i2][k] = gTM[i2][0] * P.R[k][0] * P.s[0] + gTM[i2][1] * P.R[k][1] * P.s[1]
+                        + gTM[i2][2] * P.R[k][2] * P.s[2];
     // T = J W: dL/dJ[i][k] = sum_j gT[i][j] W[k][j]
     const float *V = cam.view;
     double gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
@@ -396,11 +403,11 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
         gm[k] += (double)V[0 * 4 + k] * gt[0] + (double)V[1 * 4 + k] * gt[1] + (double)V[2 * 4 + k] * gt[2];
     for (int k = 0; k < 3; ++k) acc.m[k] += gm[k];
 
-    // Sigma3 = M M^T, M = R diag(s): dL/dM = 2 G3 M
+    // M = R diag(s): dL/dR[a][b] = dL/dM[a][b] s[b], dL/ds[b] = sum_a dL/dM[a][b] R[a][b]
     double gR[3][3], gs[3] = {0.0, 0.0, 0.0};
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b) {
-            const double gM = 2.0 * (G3[a][0] * P.M[0][b] + G3[a][1] * P.M[1][b] + G3[a][2] * P.M[2][b]);
+            const double gM = P.T[0][a] * gTM[0][b] + P.T[1][a] * gTM[1][b];
             gR[a][b] = gM * P.s[b];
             gs[b] += gM * P.R[a][b];
         }
@@ -455,10 +462,8 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
                                                           const float *__restrict__ sh, const int4 *__restrict__ rect,
-                                                          const float2 *__restrict__ g_means2d,
-                                                          const float *__restrict__ g_conic,
-                                                          const float *__restrict__ g_opacity,
-                                                          const float *__restrict__ g_rgb, float *__restrict__ d_means3d,
+                                                          const float *__restrict__ g_splats,
+                                                          float *__restrict__ d_means3d,
                                                           float *__restrict__ d_log_scales, float *__restrict__ d_quats,
                                                           float *__restrict__ d_logits, float *__restrict__ d_sh)
 {
@@ -484,10 +489,11 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
         RawGrad acc = {};
         for (int v = 0; v < cb.V; ++v) {
             const int64_t o = (int64_t)v * n + i;
-            const float gc3[3] = {g_conic[3 * o], g_conic[3 * o + 1], g_conic[3 * o + 2]};
-            const float gr3[3] = {g_rgb[3 * o], g_rgb[3 * o + 1], g_rgb[3 * o + 2]};
-            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], g_means2d[o], gc3, g_opacity[o], gr3,
-                                   acc, dslot);
+            const float *gr = g_splats + (uint64_t)o * kGradF;
+            const float gc3[3] = {gr[0], gr[1], gr[2]};
+            const float gr3[3] = {gr[6], gr[7], gr[8]};
+            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], make_float2(gr[4], gr[5]), gc3, gr[3],
+                                   gr3, acc, dslot);
         }
         for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
         for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)acc.q[k];
@@ -513,8 +519,8 @@ static bool cams_from(const lgs_camera *cameras, int32_t V, CamBatch &cb)
 
 extern "C" lgs_status lgs_project_batch(const lgs_camera *cameras, int32_t num_views, int64_t n, int32_t sh_degree,
                                         const float *means3d, const float *log_scales, const float *quats,
-                                        const float *opacity_logits, const float *sh, float *means2d,
-                                        float *conic_opacity, float *rgb, float *depth, int32_t *rect, void *stream)
+                                        const float *opacity_logits, const float *sh, float *splats, float *depth,
+                                        int32_t *rect, void *stream)
 {
     CamBatch cb;
     LGS_REQUIRE(cams_from(cameras, num_views, cb), "lgs_project: invalid camera(s) or num_views not in 1..%d",
@@ -523,18 +529,16 @@ extern "C" lgs_status lgs_project_batch(const lgs_camera *cameras, int32_t num_v
     LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project: sh_degree must be 0..3");
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh, "lgs_project: null input");
-    LGS_REQUIRE(means2d && conic_opacity && rgb && depth && rect, "lgs_project: null output");
-    LGS_REQUIRE(((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0) && ((uintptr_t)rect % 16 == 0)
-                    && ((uintptr_t)sh % 16 == 0) && ((uintptr_t)quats % 16 == 0),
-                "lgs_project: means2d must be 8-byte and conic_opacity/rect/sh/quats 16-byte aligned");
+    LGS_REQUIRE(splats && depth && rect, "lgs_project: null output");
+    LGS_REQUIRE(((uintptr_t)splats % 16 == 0) && ((uintptr_t)rect % 16 == 0) && ((uintptr_t)sh % 16 == 0)
+                    && ((uintptr_t)quats % 16 == 0),
+                "lgs_project: splats/rect/sh/quats must be 16-byte aligned");
     hipStream_t s = as_stream(stream);
     const dim3 grid(grid_for(n, 256)), block(256);
-    auto *m2 = reinterpret_cast<float2 *>(means2d);
-    auto *co = reinterpret_cast<float4 *>(conic_opacity);
     auto *rc = reinterpret_cast<int4 *>(rect);
 #define LGS_PF(D)                                                                                                 \
     hipLaunchKernelGGL(project_fwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \
-                       sh, m2, co, rgb, depth, rc)
+                       sh, splats, depth, rc)
     switch (sh_degree) {
     case 0: LGS_PF(0); break;
     case 1: LGS_PF(1); break;
@@ -548,18 +552,16 @@ extern "C" lgs_status lgs_project_batch(const lgs_camera *cameras, int32_t num_v
 
 extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t sh_degree, const float *means3d,
                                   const float *log_scales, const float *quats, const float *opacity_logits,
-                                  const float *sh, float *means2d, float *conic_opacity, float *rgb, float *depth,
-                                  int32_t *rect, void *stream)
+                                  const float *sh, float *splats, float *depth, int32_t *rect, void *stream)
 {
-    return lgs_project_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, means2d,
-                             conic_opacity, rgb, depth, rect, stream);
+    return lgs_project_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, splats, depth,
+                             rect, stream);
 }
 
 extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int32_t num_views, int64_t n,
                                                  int32_t sh_degree, const float *means3d, const float *log_scales,
                                                  const float *quats, const float *opacity_logits, const float *sh,
-                                                 const int32_t *rect, const float *g_means2d, const float *g_conic,
-                                                 const float *g_opacity, const float *g_rgb, float *d_means3d,
+                                                 const int32_t *rect, const float *g_splats, float *d_means3d,
                                                  float *d_log_scales, float *d_quats, float *d_opacity_logits,
                                                  float *d_sh, void *stream)
 {
@@ -570,18 +572,17 @@ extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int3
     LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project_backward: sh_degree must be 0..3");
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh && rect, "lgs_project_backward: null input");
-    LGS_REQUIRE(g_means2d && g_conic && g_opacity && g_rgb, "lgs_project_backward: null gradient input");
+    LGS_REQUIRE(g_splats != nullptr, "lgs_project_backward: null gradient input");
     LGS_REQUIRE(d_means3d && d_log_scales && d_quats && d_opacity_logits && d_sh, "lgs_project_backward: null output");
-    LGS_REQUIRE(((uintptr_t)g_means2d % 8 == 0) && ((uintptr_t)rect % 16 == 0) && ((uintptr_t)sh % 16 == 0)
+    LGS_REQUIRE(((uintptr_t)g_splats % 4 == 0) && ((uintptr_t)rect % 16 == 0) && ((uintptr_t)sh % 16 == 0)
                     && ((uintptr_t)d_sh % 16 == 0) && ((uintptr_t)quats % 16 == 0),
-                "lgs_project_backward: g_means2d must be 8-byte and rect/sh/d_sh/quats 16-byte aligned");
+                "lgs_project_backward: rect/sh/d_sh/quats must be 16-byte and g_splats 4-byte aligned");
     hipStream_t s = as_stream(stream);
     const dim3 grid(grid_for(n, 128)), block(128);
     auto *rc = reinterpret_cast<const int4 *>(rect);
-    auto *gm = reinterpret_cast<const float2 *>(g_means2d);
 #define LGS_PB(D)                                                                                                   \
     hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \
-                       sh, rc, gm, g_conic, g_opacity, g_rgb, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
+                       sh, rc, g_splats, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
     switch (sh_degree) {
     case 0: LGS_PB(0); break;
     case 1: LGS_PB(1); break;
@@ -596,11 +597,10 @@ extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int3
 extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, int32_t sh_degree,
                                            const float *means3d, const float *log_scales, const float *quats,
                                            const float *opacity_logits, const float *sh, const int32_t *rect,
-                                           const float *g_means2d, const float *g_conic, const float *g_opacity,
-                                           const float *g_rgb, float *d_means3d, float *d_log_scales,
+                                           const float *g_splats, float *d_means3d, float *d_log_scales,
                                            float *d_quats, float *d_opacity_logits, float *d_sh, void *stream)
 {
     return lgs_project_backward_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, rect,
-                                      g_means2d, g_conic, g_opacity, g_rgb, d_means3d, d_log_scales, d_quats,
+                                      g_splats, d_means3d, d_log_scales, d_quats,
                                       d_opacity_logits, d_sh, stream);
 }

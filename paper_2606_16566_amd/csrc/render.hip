@@ -83,10 +83,11 @@ __global__ __launch_bounds__(kBlock) void render_block_kernel(RenderArgs args)
         // cooperative staging: one list entry per lane
         if ((int)threadIdx.x < nb) {
             const uint32_t g = args.values[base + threadIdx.x];
-            const float2 m = args.means2d[g];
-            const float4 co = args.conic_opacity[g];
+            const float4 *rec = splat_rec(args.splats, g);
+            const float4 co = rec[0], mr = rec[1];
+            const float2 m = make_float2(mr.x, mr.y);
             const float lo = __builtin_amdgcn_logf(co.w);   // v_log_f32 (log2)
-            s_c[threadIdx.x] = make_float4(args.rgb[3 * g], args.rgb[3 * g + 1], args.rgb[3 * g + 2], 0.f);
+            s_c[threadIdx.x] = make_float4(mr.z, mr.w, reinterpret_cast<const float *>(rec + 2)[0], 0.f);
             if constexpr (HOISTED) {
                 s_e[threadIdx.x] = hoist<R>(m, co, lo, tc.ox, tc.oy);
             } else {
@@ -166,14 +167,17 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
     for (uint32_t base = range.x; wave_live && base < range.y; base += 64) {
         const uint32_t j = base + __lane_id();
         bool hit = false;
-        uint32_t g = 0;
+        const float4 *rec = nullptr;
         float2 m = make_float2(0.f, 0.f);
         float4 co = make_float4(0.f, 0.f, 0.f, 1.f);
+        float2 rg = make_float2(0.f, 0.f);
         float lo = 0.f;
         if (j < range.y) {
-            g = args.values[j];
-            m = args.means2d[g];
-            co = args.conic_opacity[g];
+            rec = splat_rec(args.splats, args.values[j]);
+            co = rec[0];
+            const float4 mr = rec[1];
+            m = make_float2(mr.x, mr.y);
+            rg = make_float2(mr.z, mr.w);
             lo = __builtin_amdgcn_logf(co.w);
             hit = strip_hit(co.x, co.y, co.z, lo, (float)sx0 - m.x, (float)sx1 - m.x, (float)sy0 - m.y,
                             (float)sy1 - m.y);
@@ -187,7 +191,7 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
         if (hit) {
             const int slot = __popcll(bits & lt);
             s_e[slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
-            s_c[slot] = make_float4(args.rgb[3 * g], args.rgb[3 * g + 1], args.rgb[3 * g + 2],
+            s_c[slot] = make_float4(rg.x, rg.y, reinterpret_cast<const float *>(rec + 2)[0],
                                     __int_as_float((int)(j - range.x + 1)));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -347,8 +351,8 @@ using namespace lgs;
 
 namespace {
 lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views, const uint32_t *ranges,
-                        const uint32_t *values, const float *means2d, const float *conic_opacity, const float *rgb,
-                        float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
+                        const uint32_t *values, const float *splats, float *out_rgb, float *out_T,
+                        int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
                         const uint32_t *tile_order, int32_t blocks_per_cu, uint32_t *masks, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_batch: num_views must be 1..%d",
@@ -365,11 +369,10 @@ lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_
                     && (variant & ~(0xF | LGS_RENDER_FP32 | LGS_RENDER_Q8 | LGS_RENDER_VOTE4 | LGS_RENDER_GLOBAL)) == 0,
                 "lgs_render: unknown variant %d", variant);
     LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
-    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && (means2d == nullptr || (uintptr_t)means2d % 8 == 0)
-                    && (conic_opacity == nullptr || (uintptr_t)conic_opacity % 16 == 0),
-                "lgs_render: misaligned ranges/means2d/conic_opacity");
-    render::RenderArgs a = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb,
-                                             out_T, out_ncontrib, stats);
+    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)splats % 16 == 0),
+                "lgs_render: ranges must be 8-byte and splats 16-byte aligned");
+    render::RenderArgs a = render::make_args(cams, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib,
+                                             stats);
     hipStream_t s = as_stream(stream);
     a.order = tile_order;                     // queue position -> tile, or workgroup -> tile
     a.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
@@ -406,31 +409,30 @@ lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_
 }  // namespace
 
 extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
-                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
-                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
-                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
-                                       const uint32_t *tile_order, int32_t blocks_per_cu, void *stream)
+                                       const uint32_t *ranges, const uint32_t *values, const float *splats,
+                                       float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
+                                       uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
+                                       void *stream)
 {
-    return render_batch(variant, cameras, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
-                        out_ncontrib, stats, queue, tile_order, blocks_per_cu, nullptr, stream);
+    return render_batch(variant, cameras, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats,
+                        queue, tile_order, blocks_per_cu, nullptr, stream);
 }
 
 extern "C" lgs_status lgs_render_debug(int32_t variant, const lgs_camera *cameras, int32_t num_views,
-                                       const uint32_t *ranges, const uint32_t *values, const float *means2d,
-                                       const float *conic_opacity, const float *rgb, float *out_rgb, float *out_T,
-                                       int32_t *out_ncontrib, uint64_t *stats, uint32_t *masks, void *stream)
+                                       const uint32_t *ranges, const uint32_t *values, const float *splats,
+                                       float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
+                                       uint32_t *masks, void *stream)
 {
     LGS_REQUIRE(stats != nullptr && masks != nullptr, "lgs_render_debug: stats and masks are required");
-    return render_batch(variant, cameras, num_views, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
-                        out_ncontrib, stats, nullptr, nullptr, 0, masks, stream);
+    return render_batch(variant, cameras, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats,
+                        nullptr, nullptr, 0, masks, stream);
 }
 
 extern "C" lgs_status lgs_render(int32_t variant, const lgs_camera *camera, const uint32_t *ranges,
-                                 const uint32_t *values, const float *means2d, const float *conic_opacity,
-                                 const float *rgb, float *out_rgb, float *out_T, int32_t *out_ncontrib,
-                                 uint64_t *stats, void *stream)
+                                 const uint32_t *values, const float *splats, float *out_rgb, float *out_T,
+                                 int32_t *out_ncontrib, uint64_t *stats, void *stream)
 {
     LGS_REQUIRE(camera != nullptr, "lgs_render: invalid camera");
-    return lgs_render_batch(variant, camera, 1, ranges, values, means2d, conic_opacity, rgb, out_rgb, out_T,
-                            out_ncontrib, stats, nullptr, nullptr, 0, stream);
+    return lgs_render_batch(variant, camera, 1, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats, nullptr,
+                            nullptr, 0, stream);
 }

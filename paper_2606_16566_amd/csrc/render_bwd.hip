@@ -5,9 +5,12 @@
 //   dC/dc_k      = alpha_k T_k
 //   dC/dalpha_k  = c_k T_k - R_k / (1 - alpha_k),  R_k = sum_{i>k} c_i alpha_i T_i + T_f bg
 //   dT_f/dalpha_k = -T_f / (1 - alpha_k)
+// so that, with gC = dL/dC and gT = dL/dT_f,
+//   dL/dalpha_k = T_k (gC . c_k) - G_k / (1 - alpha_k),  G_k = gC . R_k + gT T_f.
 // The replay walks each tile's list back to front from the largest last-
 // contributor position in the workgroup, recovering T_k = T_{k+1} / (1 -
-// alpha_k) from the stored final T and accumulating R_k on the way.  Through
+// alpha_k) from the stored final T and accumulating the scalar G_k on the way
+// (G_{k-1} = G_k + (gC . c_k) alpha_k T_k).  Through
 // alpha = o exp(-q/2) (unclamped): dalpha/do = alpha/o, dalpha/dq = -alpha/2,
 // dq/dmean = -2 K d, dq/d(a, b, c) = (dx^2, 2 dx dy, dy^2).
 //
@@ -19,8 +22,8 @@
 // the workgroup's LDS accumulators with one 36-lane LDS atomic, and the
 // accumulators are flushed with one global atomic per (tile, Gaussian,
 // component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
-// (hardware estimate refined by one Newton step in double); T and the
-// running colour sums stay in double, the per-pixel partials are float.
+// (hardware estimate refined by one Newton step in double); T and G stay in
+// double, the per-pixel partials are float.
 #include "common.hpp"
 
 #include "render_common.hpp"
@@ -36,8 +39,14 @@ struct BwdArgs {
     RenderArgs r;          // ranges, values, attributes, out_T, out_nc (read)
     const float *grad_rgb;
     const float *grad_T;
-    float *g_means2d, *g_conic, *g_opacity, *g_rgb;
+    float *g_splats;       // packed gradient records, kGradF floats each
 };
+
+// offset in the record of each of the nine components above
+__device__ __forceinline__ int grad_slot(int f)
+{
+    return f < 2 ? 4 + f : (f < 5 ? f - 2 : (f == 5 ? 3 : f));
+}
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v)
@@ -107,13 +116,20 @@ struct BwdStats {
     unsigned long long cand = 0, proc = 0, taken = 0;
 };
 
+// one staged list entry in LDS: every field a replay step reads, at fixed
+// offsets from one wave-uniform base address
+template <typename R>
+struct alignas(16) BwdEntry {
+    Hoisted<R> v;          // hoisted exponent coefficients (plain: v[5] = log2 o)
+    float4 co;             // a, b, c, o
+    float4 c;              // colour, 1/o
+    float2 mu;             // mean
+};
+
 template <bool LOCAL, bool Q8, typename R, bool STATS>
 __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
 {
-    __shared__ Hoisted<R> s_v[kBlock];       // hoisted exponent coefficients
-    __shared__ float4 s_co[kBlock];          // a, b, c, o
-    __shared__ float2 s_mu[kBlock];          // mean
-    __shared__ float4 s_c[kBlock];           // colour
+    __shared__ BwdEntry<R> s_e[kBlock];
     __shared__ uint32_t s_id[kBlock];
     __shared__ uint8_t s_m[kBlock];
     __shared__ float s_g[kNG][kBlock];
@@ -139,7 +155,10 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 gc2 = inside ? ba.grad_rgb[2 * HW + pc] : 0.f;
     const double gt = (inside && ba.grad_T) ? (double)ba.grad_T[p] : 0.0;
     const float *bg = a.vt.bg[tc.view];
-    double R0 = Tf * bg[0], R1 = Tf * bg[1], R2 = Tf * bg[2];
+    // G = sum_c dL/dC_c R_c + dL/dT_f T_f, R_c the colour behind the current
+    // Gaussian (initially the background seen through T_f): the only
+    // combination of the running colour sums that dL/dalpha needs
+    double G = Tf * ((double)gc0 * bg[0] + (double)gc1 * bg[1] + (double)gc2 * bg[2] + gt);
 
     int wmax = last;
 #pragma unroll
@@ -167,9 +186,11 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     auto fetch_attr = [&](int64_t be, uint32_t g) -> Attr {
         Attr at{make_float2(0.f, 0.f), make_float4(0.f, 0.f, 0.f, 1.f), 0.f, 0.f, 0.f};
         if (be > (int64_t)range.x && (int64_t)threadIdx.x < be - (int64_t)batch_start(be)) {
-            at.m = a.means2d[g];
-            at.co = a.conic_opacity[g];
-            at.r = a.rgb[3 * g]; at.gg = a.rgb[3 * g + 1]; at.b = a.rgb[3 * g + 2];
+            const float4 *rec = splat_rec(a.splats, g);
+            at.co = rec[0];
+            const float4 mr = rec[1];
+            at.m = make_float2(mr.x, mr.y);
+            at.r = mr.z; at.gg = mr.w; at.b = reinterpret_cast<const float *>(rec + 2)[0];
         }
         return at;
     };
@@ -187,12 +208,12 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             const float2 m = at_cur.m;
             const float4 co = at_cur.co;
             s_id[k] = g;
-            s_mu[k] = m;
-            s_co[k] = co;
-            s_c[k] = make_float4(at_cur.r, at_cur.gg, at_cur.b, 0.f);
+            s_e[k].mu = m;
+            s_e[k].co = co;
+            s_e[k].c = make_float4(at_cur.r, at_cur.gg, at_cur.b, __builtin_amdgcn_rcpf(co.w));
             const float lo = __builtin_amdgcn_logf(co.w);
             if (LOCAL) {
-                s_v[k] = hoist<R>(m, co, lo, tc.ox, tc.oy);
+                s_e[k].v = hoist<R>(m, co, lo, tc.ox, tc.oy);
                 // strip bits of the four wavefronts (the forward's test; the
                 // strips share their columns, so the ellipse's vertical span
                 // over them is computed once)
@@ -223,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 }
                 s_m[k] = (uint8_t)mk;
             } else {
-                s_v[k].v[5] = (R)lo;
+                s_e[k].v.v[5] = (R)lo;
                 s_m[k] = 0xF;
             }
 #pragma unroll
@@ -236,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
         id_next = fetch_id(bend - 2 * (int64_t)kBlock);
 
         // wavefront's own range: skip entries past its last contributor
-        const int wlimit = (int)min((int64_t)nb, (int64_t)range.x + wmax - (int64_t)bstart);
+        const int wlimit = __builtin_amdgcn_readfirstlane(
+            (int)min((int64_t)nb, (int64_t)range.x + wmax - (int64_t)bstart));
         for (int c0 = ((wlimit - 1) >> 6) << 6; wlimit > 0 && c0 >= 0; c0 -= 64) {
             const int j = c0 + lane;
             const bool bit = j < wlimit && ((s_m[j] >> wid) & 1u);
@@ -245,22 +267,23 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             while (bits) {
                 const int kk = 63 - __builtin_clzll(bits);
                 bits &= ~(1ull << kk);
-                const int k = c0 + kk;
+                const int k = __builtin_amdgcn_readfirstlane(c0 + kk);   // uniform: scalar addressing
+                const BwdEntry<R> &e = s_e[k];
                 const int pos1 = (int)(bstart + k - range.x) + 1;
-                const float4 co = s_co[k];
-                const float2 m = s_mu[k];
+                const float4 co = e.co;
+                const float2 m = e.mu;
                 // raw: the unclamped alpha o exp(-q/2), as the forward computed it
                 float raw;
                 bool keep;
                 if (LOCAL) {
-                    const float s32 = (float)dot_exponent(s_v[k], tc);
+                    const float s32 = (float)dot_exponent(e.v, tc);
                     raw = __builtin_amdgcn_exp2f(s32);
                     keep = s32 >= kLog2AlphaMin;
                 } else if constexpr (sizeof(R) == 8) {
                     const double dxd = (double)px - (double)m.x, dyd = (double)py - (double)m.y;
                     const double q = (double)co.x * dxd * dxd + 2.0 * (double)co.y * dxd * dyd
                                      + (double)co.z * dyd * dyd;
-                    const float s32 = (float)((double)s_v[k].v[5] - 0.5 * kLog2e * q);
+                    const float s32 = (float)((double)e.v.v[5] - 0.5 * kLog2e * q);
                     raw = __builtin_amdgcn_exp2f(s32);
                     keep = s32 >= kLog2AlphaMin;
                 } else {
@@ -277,31 +300,33 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 // Branch-free from here: a lane that does not take the Gaussian
                 // uses alpha = 0, so T (times 1/(1 - 0) = 1) and R are unchanged
                 // and every partial is zero.
-                const bool clamped = !(raw < kAlphaMax);
-                const float alf = act ? (clamped ? kAlphaMax : raw) : 0.f;
+                const bool under = raw < kAlphaMax;              // not clamped
+                const float alf = act ? (under ? raw : kAlphaMax) : 0.f;
                 const double al = (double)alf;
                 const double inv = recip(1.0 - al);
                 T = T * inv;                                     // T before this Gaussian
                 const double w = al * T;
-                const float4 f = s_c[k];
-                const double dLda = (double)gc0 * ((double)f.x * T - R0 * inv)
-                                    + (double)gc1 * ((double)f.y * T - R1 * inv)
-                                    + (double)gc2 * ((double)f.z * T - R2 * inv) - gt * Tf * inv;
-                R0 += (double)f.x * w; R1 += (double)f.y * w; R2 += (double)f.z * w;
+                const float4 f = e.c;
+                // dL/dalpha = T sum_c dL/dC_c c_c - G / (1 - alpha); then the
+                // Gaussian's own weighted colour joins G
+                const double gcc = (double)fmaf(gc2, f.z, fmaf(gc1, f.y, gc0 * f.x));
+                const double dLda = fma(T, gcc, -G * inv);
+                G = fma(gcc, w, G);
                 // the per-pixel partials are single terms (no long sums):
                 // float is enough for them; no gradient through the clamp
                 float g[kNG];
                 const float wf = (float)w;
                 g[6] = gc0 * wf; g[7] = gc1 * wf; g[8] = gc2 * wf;
-                const float dLdaf = (act && !clamped) ? (float)dLda : 0.f;
-                const float dLdq = -0.5f * alf * dLdaf;
-                const float m2 = -2.0f * dLdq;
-                g[0] = m2 * fmaf(co.x, dx, co.y * dy);
-                g[1] = m2 * fmaf(co.y, dx, co.z * dy);
-                g[2] = dLdq * dx * dx;
-                g[3] = 2.0f * dLdq * dx * dy;
-                g[4] = dLdq * dy * dy;
-                g[5] = dLdaf * raw * __builtin_amdgcn_rcpf(co.w);
+                const float dLdaf = (act && under) ? (float)dLda : 0.f;
+                const float A = alf * dLdaf;                    // -2 dL/dq
+                const float h = -0.5f * A;                      // dL/dq
+                const float hx = h * dx;
+                g[0] = A * fmaf(co.x, dx, co.y * dy);
+                g[1] = A * fmaf(co.y, dx, co.z * dy);
+                g[2] = hx * dx;
+                g[3] = 2.0f * hx * dy;
+                g[4] = h * dy * dy;
+                g[5] = dLdaf * raw * f.w;                       // dalpha/do = raw / o
                 {
                     // row sums of the nine components: even lane 2f of each
                     // row holds component f < 8, lane 1 component 8
@@ -316,17 +341,13 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
         __syncthreads();
         if ((int)threadIdx.x < nb) {
             const int k = threadIdx.x;
-            const uint32_t gid = s_id[k];
-            float v;
-            if ((v = s_g[0][k]) != 0.f) unsafeAtomicAdd(&ba.g_means2d[2 * gid], v);
-            if ((v = s_g[1][k]) != 0.f) unsafeAtomicAdd(&ba.g_means2d[2 * gid + 1], v);
-            if ((v = s_g[2][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid], v);
-            if ((v = s_g[3][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid + 1], v);
-            if ((v = s_g[4][k]) != 0.f) unsafeAtomicAdd(&ba.g_conic[3 * gid + 2], v);
-            if ((v = s_g[5][k]) != 0.f) unsafeAtomicAdd(&ba.g_opacity[gid], v);
-            if ((v = s_g[6][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid], v);
-            if ((v = s_g[7][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid + 1], v);
-            if ((v = s_g[8][k]) != 0.f) unsafeAtomicAdd(&ba.g_rgb[3 * gid + 2], v);
+            // all nine components of one (tile, Gaussian) land in one record
+            float *gr = ba.g_splats + (uint64_t)s_id[k] * kGradF;
+#pragma unroll
+            for (int f = 0; f < kNG; ++f) {
+                const float v = s_g[f][k];
+                if (v != 0.f) unsafeAtomicAdd(gr + grad_slot(f), v);
+            }
         }
     }
     };  // replay_tile
@@ -375,11 +396,9 @@ using namespace lgs;
 
 extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views,
                                                 int64_t n_elem, const uint32_t *ranges, const uint32_t *values,
-                                                const float *means2d, const float *conic_opacity, const float *rgb,
-                                                const float *out_T, const int32_t *out_ncontrib,
-                                                const float *grad_rgb, const float *grad_T, float *g_means2d,
-                                                float *g_conic, float *g_opacity, float *g_rgb,
-                                                const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
+                                                const float *splats, const float *out_T,
+                                                const int32_t *out_ncontrib, const float *grad_rgb,
+                                                const float *grad_T, float *g_splats, const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
                                                 uint64_t *stats, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_backward: num_views must be 1..%d", kMaxViews);
@@ -393,24 +412,18 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
     const bool q8 = (variant & LGS_RENDER_Q8) != 0;
     LGS_REQUIRE(n_elem >= 0, "lgs_render_backward: n < 0");
     LGS_REQUIRE(ranges && out_T && out_ncontrib && grad_rgb, "lgs_render_backward: null input");
-    LGS_REQUIRE(n_elem == 0 || (values && means2d && conic_opacity && rgb && g_means2d && g_conic && g_opacity && g_rgb),
-                "lgs_render_backward: null argument");
-    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)means2d % 8 == 0) && ((uintptr_t)conic_opacity % 16 == 0),
-                "lgs_render_backward: misaligned ranges/means2d/conic_opacity");
+    LGS_REQUIRE(n_elem == 0 || (values && splats && g_splats), "lgs_render_backward: null argument");
+    LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)splats % 16 == 0) && ((uintptr_t)g_splats % 4 == 0),
+                "lgs_render_backward: ranges must be 8-byte, splats 16-byte and g_splats 4-byte aligned");
     hipStream_t s = as_stream(stream);
-    if (!(variant & LGS_BWD_ACCUMULATE)) {
-        fill_async<float>(g_means2d, 0.f, 2 * n_elem, s);
-        fill_async<float>(g_conic, 0.f, 3 * n_elem, s);
-        fill_async<float>(g_opacity, 0.f, n_elem, s);
-        fill_async<float>(g_rgb, 0.f, 3 * n_elem, s);
-    }
+    if (!(variant & LGS_BWD_ACCUMULATE)) fill_async<float>(g_splats, 0.f, n_elem * kGradF, s);
     BwdArgs a;
-    a.r = render::make_args(cams, num_views, ranges, values, means2d, conic_opacity, rgb, nullptr, const_cast<float *>(out_T),
-                    const_cast<int32_t *>(out_ncontrib), stats);
+    a.r = render::make_args(cams, num_views, ranges, values, splats, nullptr, const_cast<float *>(out_T),
+                            const_cast<int32_t *>(out_ncontrib), stats);
     a.r.order = tile_order;
     a.r.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
     a.grad_rgb = grad_rgb; a.grad_T = grad_T;
-    a.g_means2d = g_means2d; a.g_conic = g_conic; a.g_opacity = g_opacity; a.g_rgb = g_rgb;
+    a.g_splats = g_splats;
     if (a.r.num_tiles > 0) {
         dim3 g(a.r.num_tiles);
         if (queue != nullptr) {
@@ -436,12 +449,10 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
 }
 
 extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *camera, int64_t n, const uint32_t *ranges,
-                                          const uint32_t *values, const float *means2d, const float *conic_opacity,
-                                          const float *rgb, const float *out_T, const int32_t *out_ncontrib,
-                                          const float *grad_rgb, const float *grad_T, float *g_means2d, float *g_conic,
-                                          float *g_opacity, float *g_rgb, void *stream)
+                                          const uint32_t *values, const float *splats, const float *out_T,
+                                          const int32_t *out_ncontrib, const float *grad_rgb, const float *grad_T,
+                                          float *g_splats, void *stream)
 {
-    return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, means2d, conic_opacity, rgb, out_T,
-                                     out_ncontrib, grad_rgb, grad_T, g_means2d, g_conic, g_opacity, g_rgb, nullptr,
-                                     nullptr, 0, nullptr, stream);
+    return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, splats, out_T, out_ncontrib, grad_rgb,
+                                     grad_T, g_splats, nullptr, nullptr, 0, nullptr, stream);
 }

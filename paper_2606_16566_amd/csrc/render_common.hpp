@@ -32,9 +32,7 @@ constexpr int kQueueStride = 32;                 // uint32 words between counter
 struct RenderArgs {
     const uint2 *ranges;
     const uint32_t *values;
-    const float2 *means2d;
-    const float4 *conic_opacity;
-    const float *rgb;
+    const float *splats;        // projected splat records
     float *out_rgb;
     float *out_T;
     int32_t *out_nc;
@@ -70,15 +68,12 @@ inline void fill_views(ViewTable &vt, const Cam *cams, int V)
 }
 
 inline RenderArgs make_args(const Cam *cams, int V, const uint32_t *ranges, const uint32_t *values,
-                            const float *means2d, const float *conic_opacity, const float *rgb, float *out_rgb,
-                            float *out_T, int32_t *out_nc, uint64_t *stats)
+                            const float *splats, float *out_rgb, float *out_T, int32_t *out_nc, uint64_t *stats)
 {
     RenderArgs a;
     a.ranges = reinterpret_cast<const uint2 *>(ranges);
     a.values = values;
-    a.means2d = reinterpret_cast<const float2 *>(means2d);
-    a.conic_opacity = reinterpret_cast<const float4 *>(conic_opacity);
-    a.rgb = rgb;
+    a.splats = splats;
     a.out_rgb = out_rgb; a.out_T = out_T; a.out_nc = out_nc;
     a.stats = reinterpret_cast<unsigned long long *>(stats);
     a.queue = nullptr;

@@ -764,11 +764,10 @@ struct Splat {
     float mx, my, a, b, c, lo;
 };
 
-__device__ __forceinline__ Splat load_splat(const float2 *__restrict__ means2d, const float4 *__restrict__ co,
-                                            uint32_t g)
+__device__ __forceinline__ Splat load_splat(const float *__restrict__ splats, uint32_t g)
 {
-    const float2 m = means2d[g];
-    const float4 k = co[g];
+    const float4 *rec = splat_rec(splats, g);
+    const float4 k = rec[0], m = rec[1];
     return Splat{m.x, m.y, k.x, k.y, k.z, __builtin_amdgcn_logf(k.w)};
 }
 
@@ -787,8 +786,7 @@ __device__ __forceinline__ int2 exact_rows(const Splat &g, int col)
 
 // geometry of the splats (view-major element ids), or none: rectangles only
 struct SplatGeom {
-    const float2 *means2d;
-    const float4 *conic_opacity;
+    const float *splats;
 };
 
 // Per-block column counts: hist[c * stride + b] = pairs of column c among the
@@ -822,7 +820,7 @@ __global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_
                 if (q.z > q.x && q.w > q.y) {
                     if constexpr (EXACT) {
                         // each column its own row count: a difference pair per column
-                        const Splat sp = load_splat(geom.means2d, geom.conic_opacity, order[r]);
+                        const Splat sp = load_splat(geom.splats, order[r]);
                         for (int col = q.x; col < q.z; ++col) {
                             const int2 rr = exact_rows(sp, col);
                             const int h = min(rr.y, q.w - 1) - max(rr.x, q.y) + 1;
@@ -960,7 +958,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
         s_row[t] = (uint32_t)(tg.row_off[v] + q.y);
         npairs = has ? (uint32_t)(q.z - q.x) * (uint32_t)(q.w - q.y) : 0u;
         if constexpr (EXACT) {
-            if (has) s_sp[t] = load_splat(geom.means2d, geom.conic_opacity, g);
+            if (has) s_sp[t] = load_splat(geom.splats, g);
             s_y0[t] = q.y;
         }
     }
@@ -1304,8 +1302,8 @@ extern "C" size_t lgs_sort_workspace_size(int64_t n, int64_t capacity_pairs, int
 
 extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32_t *tiles_y,
                                      int64_t n_per_view, const float *depth, const int32_t *rect,
-                                     const float *means2d, const float *conic_opacity,
-                                     uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                                     const float *splats, uint32_t *tile_keys, uint32_t *values,
+                                     int64_t capacity_pairs,
                                      int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
                                      void *stream)
 {
@@ -1341,11 +1339,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     LGS_REQUIRE(((uintptr_t)tile_keys % 16 == 0) && ((uintptr_t)values % 16 == 0),
                 "lgs_sort: tile_keys and values must be 16-byte aligned");
     LGS_REQUIRE(rect == nullptr || (uintptr_t)rect % 16 == 0, "lgs_sort: rect must be 16-byte aligned");
-    LGS_REQUIRE((means2d == nullptr) == (conic_opacity == nullptr),
-                "lgs_sort: means2d and conic_opacity go together (both or neither)");
-    LGS_REQUIRE((means2d == nullptr || (uintptr_t)means2d % 8 == 0)
-                    && (conic_opacity == nullptr || (uintptr_t)conic_opacity % 16 == 0),
-                "lgs_sort: misaligned means2d/conic_opacity");
+    LGS_REQUIRE((uintptr_t)splats % 16 == 0, "lgs_sort: splats must be 16-byte aligned");
     const size_t need = plan_workspace(nullptr, n, capacity_pairs).bytes;
     LGS_REQUIRE(workspace && workspace_bytes >= need, "lgs_sort: workspace too small (%zu < %zu bytes)",
                 workspace_bytes, need);
@@ -1361,8 +1355,8 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     const bool by_column = ncols <= kMaxCols;
     const bool packed = by_column && nrows <= 256;
     // exact tile assignment on the column path (grids at most 256 tiles wide)
-    const bool exact = by_column && means2d != nullptr;
-    const SplatGeom geom{reinterpret_cast<const float2 *>(means2d), reinterpret_cast<const float4 *>(conic_opacity)};
+    const bool exact = by_column && splats != nullptr;
+    const SplatGeom geom{splats};
     uint32_t *rp[2] = {reinterpret_cast<uint32_t *>(w.rect_sorted), reinterpret_cast<uint32_t *>(w.rect_sorted) + n};
 
     // 1. stable sort of all Gaussians by depth bits (positive floats order
@@ -1496,11 +1490,11 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
 }
 
 extern "C" lgs_status lgs_sort(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth, const int32_t *rect,
-                               const float *means2d, const float *conic_opacity, uint32_t *tile_keys,
-                               uint32_t *values, int64_t capacity_pairs, int64_t *num_pairs, int32_t *overflow,
-                               void *workspace, size_t workspace_bytes, void *stream)
+                               const float *splats, uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                               int64_t *num_pairs, int32_t *overflow, void *workspace, size_t workspace_bytes,
+                               void *stream)
 {
-    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, means2d, conic_opacity, tile_keys, values,
+    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, splats, tile_keys, values,
                           capacity_pairs, num_pairs, overflow, workspace, workspace_bytes, stream);
 }
 
@@ -1519,8 +1513,8 @@ void *g_scratch_ptr[64] = {};
 }  // namespace
 
 extern "C" lgs_status lgs_sort_noalloc(int64_t n, int32_t tiles_x, int32_t tiles_y, const float *depth,
-                                       const int32_t *rect, const float *means2d, const float *conic_opacity,
-                                       uint32_t *tile_keys, uint32_t *values, int64_t capacity_pairs,
+                                       const int32_t *rect, const float *splats, uint32_t *tile_keys,
+                                       uint32_t *values, int64_t capacity_pairs,
                                        int64_t *num_pairs, int32_t *overflow, void *stream)
 {
     LGS_REQUIRE(n >= 0 && capacity_pairs >= 0, "lgs_sort_noalloc: n and capacity_pairs must be >= 0");
@@ -1544,7 +1538,7 @@ extern "C" lgs_status lgs_sort_noalloc(int64_t n, int32_t tiles_x, int32_t tiles
         }
         ptr = g_scratch_ptr[dev];
     }
-    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, means2d, conic_opacity, tile_keys, values,
+    return lgs_sort_batch(1, &tiles_x, &tiles_y, n, depth, rect, splats, tile_keys, values,
                           capacity_pairs, num_pairs, overflow, ptr, (size_t)LGS_SORT_NOALLOC_SCRATCH_BYTES, stream);
 }
 

@@ -60,11 +60,51 @@ def _req(t, dtype, name):
 
 @dataclass
 class Projected:
-    means2d: torch.Tensor        # [n,2]
-    conic_opacity: torch.Tensor  # [n,4]
-    rgb: torch.Tensor            # [n,3]
+    splats: torch.Tensor         # [n, SPLAT_FLOATS] records: a b c o | x y | r g b | unused
     depth: torch.Tensor          # [n]
     rect: torch.Tensor           # [n,4] int32
+
+    @property
+    def conic_opacity(self):     # [n,4] view
+        return None if self.splats is None else self.splats[:, 0:4]
+
+    @property
+    def means2d(self):           # [n,2] view
+        return None if self.splats is None else self.splats[:, 4:6]
+
+    @property
+    def rgb(self):               # [n,3] view
+        return None if self.splats is None else self.splats[:, 6:9]
+
+
+def pack_splats(means2d, conic_opacity, rgb) -> torch.Tensor:
+    """Splat records [n, SPLAT_FLOATS] from separate attribute tensors [n,2],
+    [n,4], [n,3] (on their device; unused floats zero)."""
+    n = means2d.shape[0]
+    s = torch.zeros((n, L.SPLAT_FLOATS), dtype=torch.float32, device=means2d.device)
+    s[:, 0:4] = conic_opacity
+    s[:, 4:6] = means2d
+    s[:, 6:9] = rgb
+    return s
+
+
+def pack_grads(means2d, conic, opacity, rgb) -> dict:
+    """Gradient records (as grad_views) from separate tensors [n,2], [n,3],
+    [n], [n,3] on their device."""
+    n = means2d.shape[0]
+    g = torch.zeros((n, L.GRAD_FLOATS), dtype=torch.float32, device=means2d.device)
+    g[:, 0:3] = conic
+    g[:, 3] = opacity
+    g[:, 4:6] = means2d
+    g[:, 6:9] = rgb
+    return grad_views(g)
+
+
+def grad_views(g_splats: torch.Tensor) -> dict:
+    """Named views of gradient records [n, GRAD_FLOATS] (the splat record's
+    first nine fields, packed); 'splats' is the record tensor itself."""
+    return dict(splats=g_splats, conic=g_splats[:, 0:3], opacity=g_splats[:, 3], means2d=g_splats[:, 4:6],
+                rgb=g_splats[:, 6:9])
 
 
 @dataclass
@@ -84,12 +124,11 @@ def project(cam, means3d, log_scales, quats, opacity_logits, sh) -> Projected:
                   (opacity_logits, "opacity_logits"), (sh, "sh")):
         _req(t, torch.float32, nm)
     deg = int(round(sh.shape[1] ** 0.5)) - 1
-    out = Projected(torch.empty((n, 2), device=dev), torch.empty((n, 4), device=dev),
-                    torch.empty((n, 3), device=dev), torch.empty(n, device=dev),
+    out = Projected(torch.empty((n, L.SPLAT_FLOATS), device=dev), torch.empty(n, device=dev),
                     torch.empty((n, 4), device=dev, dtype=torch.int32))
     L.check(L.lib().lgs_project(C.byref(L.camera_struct(cam)), n, deg, _p(means3d), _p(log_scales), _p(quats),
-                                _p(opacity_logits), _p(sh), _p(out.means2d), _p(out.conic_opacity),
-                                _p(out.rgb), _p(out.depth), _p(out.rect), _stream()), "lgs_project")
+                                _p(opacity_logits), _p(sh), _p(out.splats), _p(out.depth), _p(out.rect),
+                                _stream()), "lgs_project")
     return out
 
 
@@ -130,9 +169,8 @@ class Binner:
             cap = max(self.capacity, 1)
             ws_base = self.ws.data_ptr()
             ws_aligned = (ws_base + 255) & ~255
-            geo = self.exact and proj.means2d is not None
-            L.check(L.lib().lgs_sort(n, tx, ty, _p(proj.depth), _p(proj.rect),
-                                     _p(proj.means2d) if geo else None, _p(proj.conic_opacity) if geo else None,
+            geo = self.exact and proj.splats is not None
+            L.check(L.lib().lgs_sort(n, tx, ty, _p(proj.depth), _p(proj.rect), _p(proj.splats) if geo else None,
                                      _p(self.keys), _p(self.vals), cap,
                                      _p(self.num_pairs), _p(self.overflow), C.c_void_p(ws_aligned),
                                      self.ws.numel() - (ws_aligned - ws_base), _stream()), "lgs_sort")
@@ -155,21 +193,19 @@ def render(variant, cam, binned: Binned, proj: Projected, stats: torch.Tensor | 
     T = torch.empty((H, W), device=dev)
     nc = torch.empty((H, W), device=dev, dtype=torch.int32)
     L.check(L.lib().lgs_render(variant_code(variant), C.byref(L.camera_struct(cam)), _p(binned.ranges),
-                               _p(binned.values), _p(proj.means2d), _p(proj.conic_opacity), _p(proj.rgb),
-                               _p(img), _p(T), _p(nc), _p(stats), _stream()), "lgs_render")
+                               _p(binned.values), _p(proj.splats), _p(img), _p(T), _p(nc), _p(stats), _stream()),
+            "lgs_render")
     return img, T, nc
 
 
 def render_backward(variant, cam, binned: Binned, proj: Projected, T, nc, grad_rgb, grad_T=None):
     n = proj.depth.shape[0]
     dev = proj.depth.device
-    g = dict(means2d=torch.empty((n, 2), device=dev), conic=torch.empty((n, 3), device=dev),
-             opacity=torch.empty(n, device=dev), rgb=torch.empty((n, 3), device=dev))
+    g = grad_views(torch.empty((n, L.GRAD_FLOATS), device=dev))
     _req(grad_rgb, torch.float32, "grad_rgb")
     L.check(L.lib().lgs_render_backward(variant_code(variant), C.byref(L.camera_struct(cam)), n, _p(binned.ranges),
-                                        _p(binned.values), _p(proj.means2d), _p(proj.conic_opacity), _p(proj.rgb),
-                                        _p(T), _p(nc), _p(grad_rgb), _p(grad_T), _p(g["means2d"]), _p(g["conic"]),
-                                        _p(g["opacity"]), _p(g["rgb"]), _stream()), "lgs_render_backward")
+                                        _p(binned.values), _p(proj.splats), _p(T), _p(nc), _p(grad_rgb),
+                                        _p(grad_T), _p(g["splats"]), _stream()), "lgs_render_backward")
     return g
 
 
@@ -180,8 +216,8 @@ def project_backward(cam, means3d, log_scales, quats, opacity_logits, sh, rect, 
              quats=torch.empty_like(quats), opacity_logits=torch.empty_like(opacity_logits),
              sh=torch.empty_like(sh))
     L.check(L.lib().lgs_project_backward(C.byref(L.camera_struct(cam)), n, deg, _p(means3d), _p(log_scales),
-                                         _p(quats), _p(opacity_logits), _p(sh), _p(rect), _p(g["means2d"]),
-                                         _p(g["conic"]), _p(g["opacity"]), _p(g["rgb"]), _p(d["means3d"]),
+                                         _p(quats), _p(opacity_logits), _p(sh), _p(rect), _p(g["splats"]),
+                                         _p(d["means3d"]),
                                          _p(d["log_scales"]), _p(d["quats"]), _p(d["opacity_logits"]),
                                          _p(d["sh"]), _stream()), "lgs_project_backward")
     return d

@@ -22,8 +22,8 @@ def scene_tensors(sc):
 def projected_from(means2d, conic, opacity, rgb, depth, rect):
     """R.Projected from float32 screen-space attributes (render-only inputs)."""
     co = np.concatenate([np.asarray(conic, np.float32), np.asarray(opacity, np.float32)[:, None]], 1)
-    return R.Projected(to_dev(np.asarray(means2d, np.float32)), to_dev(co), to_dev(np.asarray(rgb, np.float32)),
-                       to_dev(np.asarray(depth, np.float32)), to_dev(np.asarray(rect, np.int32)))
+    splats = R.pack_splats(to_dev(np.asarray(means2d, np.float32)), to_dev(co), to_dev(np.asarray(rgb, np.float32)))
+    return R.Projected(splats, to_dev(np.asarray(depth, np.float32)), to_dev(np.asarray(rect, np.int32)))
 
 
 def last_ids(binned, nc, cam):

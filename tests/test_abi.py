@@ -53,17 +53,17 @@ def test_invalid_arguments_rejected_on_host():
     L = _lib()
     cam = L.LgsCamera()
     cam.width, cam.height, cam.fx, cam.fy = 0, 10, 100.0, 100.0          # width 0: invalid
-    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 11))
+    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 9))
     assert st == L.LGS_ERR_INVALID_ARG
     assert b"camera" in L.lib().lgs_last_error()
     cam.width = 16
-    st = L.lib().lgs_project(C.byref(cam), 10, 5, *([None] * 11))     # sh degree 5
+    st = L.lib().lgs_project(C.byref(cam), 10, 5, *([None] * 9))     # sh degree 5
     assert st == L.LGS_ERR_INVALID_ARG
-    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 11))     # null pointers
+    st = L.lib().lgs_project(C.byref(cam), 10, 0, *([None] * 9))     # null pointers
     assert st == L.LGS_ERR_INVALID_ARG and b"null" in L.lib().lgs_last_error()
-    st = L.lib().lgs_render(7, C.byref(cam), *([None] * 10))            # unknown variant
+    st = L.lib().lgs_render(7, C.byref(cam), *([None] * 8))            # unknown variant
     assert st == L.LGS_ERR_INVALID_ARG
-    st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, None, None, 100, None, None, None, 0, None)
+    st = L.lib().lgs_sort(10, 4, 4, None, None, None, None, None, 100, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
     st = L.lib().lgs_l1_loss(None, None, 0, None, None, None, 0, None)
     assert st == L.LGS_ERR_INVALID_ARG
@@ -81,11 +81,11 @@ def test_sort_noalloc_rejects_sizes_beyond_its_scratch():
     n = 4_000_000
     assert lb.lgs_sort_workspace_size(n, n, 64) > L.SORT_NOALLOC_SCRATCH_BYTES
     assert lb.lgs_sort_workspace_size(10_000, 50_000, 256) <= L.SORT_NOALLOC_SCRATCH_BYTES
-    st = lb.lgs_sort_noalloc(n, 8, 8, None, None, None, None, None, None, n, None, None, None)
+    st = lb.lgs_sort_noalloc(n, 8, 8, None, None, None, None, None, n, None, None, None)
     assert st == L.LGS_ERR_INVALID_ARG
     msg = lb.lgs_last_error()
     assert b"scratch" in msg and str(L.SORT_NOALLOC_SCRATCH_BYTES).encode() in msg
-    assert lb.lgs_sort_noalloc(-1, 8, 8, None, None, None, None, None, None, 0, None, None, None) == \
+    assert lb.lgs_sort_noalloc(-1, 8, 8, None, None, None, None, None, 0, None, None, None) == \
         L.LGS_ERR_INVALID_ARG
 
 
@@ -104,13 +104,13 @@ def test_batch_and_graph_arguments_rejected_on_host():
     for c in cams:
         c.width, c.height, c.fx, c.fy = 16, 16, 100.0, 100.0
     for nv in (0, 17):
-        assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 11)) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_batch(3, cams, nv, *([None] * 9), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 15), 0, None, None) == \
+        assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 9)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_batch(3, cams, nv, *([None] * 7), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 10), 0, None, None) == \
             L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 16)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 13)) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
-    assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, None, None, 10, None, None, None, 0, None) == \
+    assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, None, 10, None, None, None, 0, None) == \
         L.LGS_ERR_INVALID_ARG
     assert lb.lgs_graph_begin(None) == L.LGS_ERR_INVALID_ARG
     assert lb.lgs_graph_launch(None, None) == L.LGS_ERR_INVALID_ARG

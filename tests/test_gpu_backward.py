@@ -82,7 +82,8 @@ def test_project_backward_parity(cfg, n, view):
                               g32["means2d"], g32["conic"], g32["opacity"], g32["rgb"])
     ps = scene_tensors(sc)
     proj = R.project(cam, *ps)
-    got = R.project_backward(cam, *ps, proj.rect, {k: to_dev(v) for k, v in g32.items()})
+    gd = {k: to_dev(v) for k, v in g32.items()}
+    got = R.project_backward(cam, *ps, proj.rect, R.pack_grads(gd["means2d"], gd["conic"], gd["opacity"], gd["rgb"]))
     for k in ("means3d", "log_scales", "quats", "opacity_logits", "sh"):
         assert_grad_close(_np(got[k]), want[k], k, tol=1e-5)
 

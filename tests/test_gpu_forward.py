@@ -153,7 +153,7 @@ def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
     cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), W, H)
     off, ids = O.tile_lists(vis, depth, rect, W, H)
     p = len(ids)
-    proj = R.Projected(None, None, None, to_dev(depth), to_dev(rect))
+    proj = R.Projected(None, to_dev(depth), to_dev(rect))
     b = R.Binner(capacity=p + 17).run(cam, proj)
     keys = _sync_np(b.tile_keys)[:p].astype(np.int64)
     vals = _sync_np(b.values)[:p]
@@ -188,7 +188,7 @@ def test_sort_extreme_rectangles(tx, ty):
     cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), W, H)
     off, ids = O.tile_lists(vis, depth, rect, W, H)
     p = len(ids)
-    b = R.Binner(capacity=p + 5).run(cam, R.Projected(None, None, None, to_dev(depth), to_dev(rect)))
+    b = R.Binner(capacity=p + 5).run(cam, R.Projected(None, to_dev(depth), to_dev(rect)))
     assert int(b.num_pairs.item()) == p and int(b.overflow.item()) == 0
     assert np.array_equal(_sync_np(b.tile_keys)[:p].astype(np.int64), np.repeat(np.arange(tx * ty), np.diff(off)))
     assert np.array_equal(_sync_np(b.values)[:p], ids)
@@ -232,7 +232,7 @@ def test_sort_overflow_flag_and_empty():
     vis, depth, rect = _synthetic_bins(7, 2000, 20, 10)
     cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), 320, 160)
     off, ids = O.tile_lists(vis, depth, rect, 320, 160)
-    proj = R.Projected(None, None, None, to_dev(depth), to_dev(rect))
+    proj = R.Projected(None, to_dev(depth), to_dev(rect))
     binner = R.Binner(capacity=len(ids) // 3)
     b = binner.run(cam, proj, check_overflow=False)
     assert int(b.overflow.item()) == 1 and int(b.num_pairs.item()) == len(ids)
@@ -241,11 +241,11 @@ def test_sort_overflow_flag_and_empty():
     assert int(b.overflow.item()) == 0 and binner.capacity >= len(ids)
     assert np.array_equal(_sync_np(b.values)[:len(ids)], ids)
     # no Gaussian at all
-    e = R.Projected(None, None, None, to_dev(np.zeros(0, np.float32)), to_dev(np.zeros((0, 4), np.int32)))
+    e = R.Projected(None, to_dev(np.zeros(0, np.float32)), to_dev(np.zeros((0, 4), np.int32)))
     b = R.Binner(capacity=16).run(cam, e)
     assert int(b.num_pairs.item()) == 0 and np.all(_sync_np(b.ranges) == 0)
     # every Gaussian culled (depth +inf, empty rectangle)
-    c = R.Projected(None, None, None, to_dev(np.full(3000, np.inf, np.float32)), to_dev(np.zeros((3000, 4), np.int32)))
+    c = R.Projected(None, to_dev(np.full(3000, np.inf, np.float32)), to_dev(np.zeros((3000, 4), np.int32)))
     b = R.Binner(capacity=16).run(cam, c)
     assert int(b.num_pairs.item()) == 0 and int(b.overflow.item()) == 0 and np.all(_sync_np(b.ranges) == 0)
 

@@ -158,7 +158,7 @@ def test_multiview_sort_stacked_rows_synthetic():
     tys = (C.c_int32 * V)(*([ty] * V))
     d_dev, r_dev = to_dev(depth), to_dev(rect)
     p = lambda t: C.c_void_p(t.data_ptr())
-    st = lb.lgs_sort_batch(V, txs, tys, n, p(d_dev), p(r_dev), None, None, p(keys), p(vals), cap, p(npairs), p(ovf),
+    st = lb.lgs_sort_batch(V, txs, tys, n, p(d_dev), p(r_dev), None, p(keys), p(vals), cap, p(npairs), p(ovf),
                            C.c_void_p(al), ws.numel() - (al - base), C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == L.LGS_OK, lb.lgs_last_error()
     torch.cuda.synchronize()

@@ -125,7 +125,7 @@ def test_culled_entries_are_skipped_entries(variant):
     nc = torch.empty((H, W), dtype=torch.int32, device=dev)
     p = lambda t: C.c_void_p(t.data_ptr())
     st = L.lib().lgs_render_debug(R.variant_code(variant), C.byref(L.camera_struct(cam)), 1, p(b.ranges), p(b.values),
-                                  p(proj.means2d), p(proj.conic_opacity), p(proj.rgb), p(img), p(T), p(nc), p(stats),
+                                  p(proj.splats), p(img), p(T), p(nc), p(stats),
                                   p(masks), C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == L.LGS_OK, L.lib().lgs_last_error()
     torch.cuda.synchronize()

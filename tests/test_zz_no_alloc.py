@@ -48,10 +48,10 @@ def _sort(entry, n, tx, ty, depth, rect, cap):
         ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
         base = ws.data_ptr()
         aligned = (base + 255) & ~255
-        st = lb.lgs_sort(n, tx, ty, _p(d), _p(r), None, None, _p(keys), _p(vals), cap, _p(npairs), _p(ovf),
+        st = lb.lgs_sort(n, tx, ty, _p(d), _p(r), None, _p(keys), _p(vals), cap, _p(npairs), _p(ovf),
                          C.c_void_p(aligned), ws.numel() - (aligned - base), stream)
     else:
-        st = lb.lgs_sort_noalloc(n, tx, ty, _p(d), _p(r), None, None, _p(keys), _p(vals), cap, _p(npairs), _p(ovf),
+        st = lb.lgs_sort_noalloc(n, tx, ty, _p(d), _p(r), None, _p(keys), _p(vals), cap, _p(npairs), _p(ovf),
                                  stream)
     assert st == L.LGS_OK, lb.lgs_last_error()
     torch.cuda.synchronize()
@@ -87,5 +87,5 @@ def test_sort_noalloc_overflow_and_limit():
     lb = L.lib()
     big = 4_000_000
     assert lb.lgs_sort_workspace_size(big, big, 64) > L.SORT_NOALLOC_SCRATCH_BYTES
-    st = lb.lgs_sort_noalloc(big, 8, 8, None, None, None, None, None, None, big, None, None, None)
+    st = lb.lgs_sort_noalloc(big, 8, 8, None, None, None, None, None, big, None, None, None)
     assert st == L.LGS_ERR_INVALID_ARG and b"scratch" in lb.lgs_last_error()
