@@ -18,10 +18,10 @@
 // wavefront visits, in reverse, only the entries whose strip bit is set.  The
 // nine per-Gaussian partial gradients are summed over each 16-lane row with a
 // DPP reduce-scatter (no LDS traffic; each of nine lanes of a row ends with
-// one component's sum), the four row sums of all nine components are added to
-// the workgroup's LDS accumulators with one 36-lane LDS atomic, and the
-// accumulators are flushed with one global atomic per (tile, Gaussian,
-// component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
+// one component's sum), the four rows are added with two lane swaps, nine
+// lanes add the wavefront's totals to the workgroup's LDS accumulators (no
+// two on one address or bank), and the accumulators are flushed with one
+// global atomic per nonzero (tile, Gaussian, component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
 // (hardware estimate refined by one Newton step in double); T and G stay in
 // double, the per-pixel partials are float.
 #include "common.hpp"
@@ -86,6 +86,18 @@ __device__ __forceinline__ float row_sums9(const float *g)
     return rs_step<0xB1>(m, g8, b0);                                        // quad_perm [1,0,3,2]
 }
 
+// Sum of a value over the four 16-lane rows (all 64 lanes active), in every
+// lane: lane l ends with the sum of lanes l mod 16, + 16, + 32, + 48.  Two
+// gfx950 lane swaps, upper half with lower half, then odd rows with even
+// rows; each is added to its partner's copy.
+__device__ __forceinline__ float rows_total(float v)
+{
+    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
 // 1 / x for normal positive x (here 1 - alpha in [0.01, 1]): hardware
 // estimate (measured relative error 2^-24.4 on that interval) and one Newton
 // step, which squares it (measured 2^-48.7, a few ulps; exact for x = 1, so a
@@ -132,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     __shared__ BwdEntry<R> s_e[kBlock];
     __shared__ uint32_t s_id[kBlock];
     __shared__ uint8_t s_m[kBlock];
-    __shared__ float s_g[kNG][kBlock];
+    __shared__ float s_g[kNG][kBlock + 1];  // padded: the nine components of an entry in distinct banks
     __shared__ int s_max[kBlock / 64];
     __shared__ uint32_t s_pos;
 
@@ -332,22 +344,21 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                     // row holds component f < 8, lane 1 component 8
                     static_assert(kNG == 9, "row_sums9 handles nine components");
                     const int l = lane & 15;
-                    const float mine = row_sums9(g);
+                    const float tot = rows_total(row_sums9(g));
                     const int f = (l & 1) ? 8 : (l >> 1);
-                    if (((l & 1) == 0 || l == 1) && mine != 0.f) atomicAdd(&s_g[f][k], mine);
+                    if (lane < 16 && ((l & 1) == 0 || l == 1) && tot != 0.f) atomicAdd(&s_g[f][k], tot);
                 }
             }
         }
         __syncthreads();
-        if ((int)threadIdx.x < nb) {
-            const int k = threadIdx.x;
-            // all nine components of one (tile, Gaussian) land in one record
-            float *gr = ba.g_splats + (uint64_t)s_id[k] * kGradF;
-#pragma unroll
-            for (int f = 0; f < kNG; ++f) {
-                const float v = s_g[f][k];
-                if (v != 0.f) unsafeAtomicAdd(gr + grad_slot(f), v);
-            }
+        // one global atomic per nonzero (tile, Gaussian, component), work
+        // item t = 9 * entry + component: the 64 lanes of an atomic
+        // instruction cover the records of about seven entries rather than
+        // one component of 64 records
+        for (int t = threadIdx.x; t < nb * kNG; t += kBlock) {
+            const int k = t / kNG, f = t - k * kNG;
+            const float v = s_g[f][k];
+            if (v != 0.f) unsafeAtomicAdd(ba.g_splats + (uint64_t)s_id[k] * kGradF + grad_slot(f), v);
         }
     }
     };  // replay_tile
