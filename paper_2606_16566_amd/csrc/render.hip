@@ -148,6 +148,26 @@ struct WaveStats {
     unsigned long long seen = 0, eval = 0, staged = 0;
 };
 
+// one lane's list entry of a chunk: its splat record's fields (a culled or
+// past-the-end lane holds a zero-size placeholder that no test keeps)
+struct ChunkEntry {
+    float4 co;              // a, b, c, o
+    float4 mr;              // x, y, r, g
+    float b;
+};
+
+__device__ __forceinline__ ChunkEntry load_entry(const RenderArgs &a, uint32_t id, bool valid)
+{
+    ChunkEntry e{make_float4(0.f, 0.f, 0.f, 1.f), make_float4(0.f, 0.f, 0.f, 0.f), 0.f};
+    if (valid) {
+        const float4 *rec = splat_rec(a.splats, id);
+        e.co = rec[0];
+        e.mr = rec[1];
+        e.b = reinterpret_cast<const float *>(rec + 2)[0];
+    }
+    return e;
+}
+
 // One 16x4 strip of one tile, processed by one wavefront with its own LDS
 // slots (no workgroup barrier).
 template <bool UNIFORM, typename R, bool STATS, int VP>
@@ -164,20 +184,28 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
     const int sx0 = tc.sx0, sx1 = tc.sx1, sy0 = tc.sy0, sy1 = tc.sy1;
     bool wave_live = __ballot(live) != 0ull;
 
-    for (uint32_t base = range.x; wave_live && base < range.y; base += 64) {
-        const uint32_t j = base + __lane_id();
+    // Two-deep software pipeline over the chunks: while chunk i is culled and
+    // blended, the records of chunk i + 1 (by ids already in registers) and
+    // the ids of chunk i + 2 are in flight.
+    // (positions in 64 bits: no wrap near the end of a 32-bit pair range)
+    const uint32_t lane = __lane_id();
+    const uint64_t end = range.y;
+    auto load_id = [&](uint64_t b) -> uint32_t { return b + lane < end ? args.values[b + lane] : 0u; };
+    ChunkEntry nxt = load_entry(args, load_id(range.x), (uint64_t)range.x + lane < end);
+    uint32_t id_next = load_id((uint64_t)range.x + 64);
+
+    for (uint64_t base64 = range.x; wave_live && base64 < end; base64 += 64) {
+        const uint32_t base = (uint32_t)base64;
+        const uint32_t j = base + lane;
+        const ChunkEntry cur = nxt;
+        nxt = load_entry(args, id_next, base64 + 64 + lane < end);
+        id_next = load_id(base64 + 128);
         bool hit = false;
-        const float4 *rec = nullptr;
-        float2 m = make_float2(0.f, 0.f);
-        float4 co = make_float4(0.f, 0.f, 0.f, 1.f);
-        float2 rg = make_float2(0.f, 0.f);
+        const float4 co = cur.co;
+        const float2 m = make_float2(cur.mr.x, cur.mr.y);
         float lo = 0.f;
-        if (j < range.y) {
-            rec = splat_rec(args.splats, args.values[j]);
-            co = rec[0];
-            const float4 mr = rec[1];
-            m = make_float2(mr.x, mr.y);
-            rg = make_float2(mr.z, mr.w);
+        const bool in_list = base64 + lane < end;
+        if (in_list) {
             lo = __builtin_amdgcn_logf(co.w);
             hit = strip_hit(co.x, co.y, co.z, lo, (float)sx0 - m.x, (float)sx1 - m.x, (float)sy0 - m.y,
                             (float)sy1 - m.y);
@@ -186,13 +214,12 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
         const int cnt = __popcll(bits);
         if (STATS) st.staged += cnt;
         // culling record: this wavefront tested entry j (bit w) and kept it (bit 4 + w)
-        if (STATS && args.masks != nullptr && j < range.y)
+        if (STATS && args.masks != nullptr && in_list)
             atomicOr(&args.masks[j], (1u << tc.wid) | (hit ? (16u << tc.wid) : 0u));
         if (hit) {
             const int slot = __popcll(bits & lt);
             s_e[slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
-            s_c[slot] = make_float4(rg.x, rg.y, reinterpret_cast<const float *>(rec + 2)[0],
-                                    __int_as_float((int)(j - range.x + 1)));
+            s_c[slot] = make_float4(cur.mr.z, cur.mr.w, cur.b, __int_as_float((int)(j - range.x + 1)));
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
