@@ -16,14 +16,14 @@
 //
 // The LOCAL variant reuses the forward's hoisting and wavefront culling: each
 // wavefront visits, in reverse, only the entries whose strip bit is set.  The
-// nine per-Gaussian partial gradients are summed over each 16-lane row with a
-// DPP reduce-scatter (no LDS traffic; each of nine lanes of a row ends with
-// one component's sum), the four rows are added with two lane swaps, nine
-// lanes add the wavefront's totals to the workgroup's LDS accumulators (no
-// two on one address or bank), and the accumulators are flushed with one
-// global atomic per nonzero (tile, Gaussian, component).  Per step the pixel math needs one reciprocal 1/(1 - alpha)
-// (hardware estimate refined by one Newton step in double); T and G stay in
-// double, the per-pixel partials are float.
+// nine per-Gaussian partial gradients are summed over the wavefront with lane
+// swaps across its halves and row pairs and a DPP reduce-scatter inside the
+// rows (no LDS traffic); the nine lanes holding the totals add them to the
+// workgroup's LDS accumulators (no two on one address or bank), and the
+// accumulators are flushed with one global atomic per nonzero (tile,
+// Gaussian, component).  Per step the pixel math needs one reciprocal
+// 1/(1 - alpha) (hardware estimate refined by one Newton step in double); T
+// and G stay in double, the per-pixel partials are float.
 #include "common.hpp"
 
 #include "render_common.hpp"
@@ -48,6 +48,13 @@ __device__ __forceinline__ int grad_slot(int f)
     return f < 2 ? 4 + f : (f < 5 ? f - 2 : (f == 5 ? 3 : f));
 }
 
+// exact power-of-two factor applied to each accumulated component at the
+// flush (the conic partials are summed without their -1/2, -1, -1/2)
+__device__ __forceinline__ float grad_scale(int f)
+{
+    return f == 2 || f == 4 ? -0.5f : (f == 3 ? -1.0f : 1.0f);
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_read(float v)
 {
@@ -64,38 +71,59 @@ __device__ __forceinline__ float rs_step(float x, float y, bool hi)
     return keep + dpp_read<CTRL>(send);
 }
 
-// Row sums of nine values over the 16 lanes of each row (all 64 lanes
-// active), scattered: lane l of a row ends with the sum of component
-// (l >> 1) when l is even and of component 8 when l is odd.  Components
-// 0..7 halve over the row mirror (partner l ^ 15, key bit 3), the half-row
-// mirror (l ^ 7, bit 2) and the quad swaps l ^ 2 (bit 1) and l ^ 1 (bit 0,
-// paired with component 8, which is butterfly-summed until then): 27
-// instructions instead of four butterfly adds per component.
-__device__ __forceinline__ float row_sums9(const float *g)
+// Sums over lane halves and row pairs with the gfx950 lane swaps: of two
+// values a and b, lanes 0..31 end with a summed over lanes l and l + 32 and
+// lanes 32..63 with b summed likewise (32-lane swap); or rows 0 and 2 end with
+// a summed over rows (0, 1), resp. (2, 3), and rows 1 and 3 with b (16-lane
+// swap of the odd rows of the first operand with the even rows of the second).
+__device__ __forceinline__ float halves_pair(float a, float b)
 {
-    const int l = __lane_id() & 15;
-    const bool b3 = l & 8, b2 = l & 4, b1 = l & 2, b0 = l & 1;
-    float h[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) h[j] = rs_step<0x140>(g[j], g[j + 4], b3);   // row_mirror
-    float g8 = g[8] + dpp_read<0x140>(g[8]);
-    const float k0 = rs_step<0x141>(h[0], h[2], b2), k1 = rs_step<0x141>(h[1], h[3], b2);   // row_half_mirror
-    g8 += dpp_read<0x141>(g8);
-    const float m = rs_step<0x4E>(k0, k1, b1);                              // quad_perm [2,3,0,1]
-    g8 += dpp_read<0x4E>(g8);
-    return rs_step<0xB1>(m, g8, b0);                                        // quad_perm [1,0,3,2]
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
-// Sum of a value over the four 16-lane rows (all 64 lanes active), in every
-// lane: lane l ends with the sum of lanes l mod 16, + 16, + 32, + 48.  Two
-// gfx950 lane swaps, upper half with lower half, then odd rows with even
-// rows; each is added to its partner's copy.
-__device__ __forceinline__ float rows_total(float v)
+__device__ __forceinline__ float rows_pair(float a, float b)
 {
-    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(h[0]) + __uint_as_float(h[1]);
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
+// Sums of nine values over all 64 lanes (all lanes active), scattered: lane l
+// in row r = l >> 4 at position p = l & 15 ends with the total of component
+// wave_comp(l).  Components pair up over the two halves (0|1, 2|3, 4|5, 6|7),
+// then over the row pairs, so that row r holds one of 0, 2, 1, 3 and one of
+// 4, 6, 5, 7 (and every row component 8) summed over the four rows; inside
+// the rows a DPP reduce-scatter over the row mirror (key bit 3 of p) and the
+// half-row mirror (bit 2) and butterflies over the quads finish them: 25
+// instructions.
+__device__ __forceinline__ float wave_sums9(const float *g)
+{
+    const float s01 = halves_pair(g[0], g[1]), s23 = halves_pair(g[2], g[3]);
+    const float s45 = halves_pair(g[4], g[5]), s67 = halves_pair(g[6], g[7]);
+    float t8 = halves_pair(g[8], g[8]);
+    const float q0 = rows_pair(s01, s23), q1 = rows_pair(s45, s67);
+    t8 = rows_pair(t8, t8);
+    const int p = __lane_id() & 15;
+    const float u = rs_step<0x140>(q0, q1, (p & 8) != 0);                  // row_mirror
+    t8 += dpp_read<0x140>(t8);
+    float v = rs_step<0x141>(u, t8, (p & 4) != 0);                        // row_half_mirror
+    v += dpp_read<0x4E>(v);                                                 // quad_perm [2,3,0,1]
+    v += dpp_read<0xB1>(v);                                                 // quad_perm [1,0,3,2]
+    return v;
+}
+
+// the component whose total wave_sums9 leaves in lane l; lanes 0 and 8 of
+// every row and lane 4 of row 0 hold the nine totals once each
+__device__ __forceinline__ int wave_comp(int l)
+{
+    const int r = l >> 4, p = l & 15;
+    const int c = ((r & 1) << 1) | (r >> 1);       // rows hold 0, 2, 1, 3
+    return p < 4 ? c : (p >= 8 && p < 12 ? 4 + c : 8);
+}
+
+__device__ __forceinline__ bool wave_owner(int l)
+{
+    return (l & 7) == 0 || l == 4;
 }
 
 // 1 / x for normal positive x (here 1 - alpha in [0.01, 1]): hardware
@@ -330,23 +358,21 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 const float wf = (float)w;
                 g[6] = gc0 * wf; g[7] = gc1 * wf; g[8] = gc2 * wf;
                 const float dLdaf = (act && under) ? (float)dLda : 0.f;
-                const float A = alf * dLdaf;                    // -2 dL/dq
-                const float h = -0.5f * A;                      // dL/dq
-                const float hx = h * dx;
-                g[0] = A * fmaf(co.x, dx, co.y * dy);
-                g[1] = A * fmaf(co.y, dx, co.z * dy);
-                g[2] = hx * dx;
-                g[3] = 2.0f * hx * dy;
-                g[4] = h * dy * dy;
+                // A = alpha dL/dalpha = -2 dL/dq; the conic partials are
+                // accumulated as A (dx^2, dx dy, dy^2) and scaled by
+                // (-1/2, -1, -1/2) once per entry in the flush
+                const float A = alf * dLdaf;
+                const float Ax = A * dx, Ay = A * dy;
+                g[0] = fmaf(co.x, Ax, co.y * Ay);
+                g[1] = fmaf(co.y, Ax, co.z * Ay);
+                g[2] = Ax * dx;
+                g[3] = Ax * dy;
+                g[4] = Ay * dy;
                 g[5] = dLdaf * raw * f.w;                       // dalpha/do = raw / o
                 {
-                    // row sums of the nine components: even lane 2f of each
-                    // row holds component f < 8, lane 1 component 8
-                    static_assert(kNG == 9, "row_sums9 handles nine components");
-                    const int l = lane & 15;
-                    const float tot = rows_total(row_sums9(g));
-                    const int f = (l & 1) ? 8 : (l >> 1);
-                    if (lane < 16 && ((l & 1) == 0 || l == 1) && tot != 0.f) atomicAdd(&s_g[f][k], tot);
+                    static_assert(kNG == 9, "wave_sums9 handles nine components");
+                    const float tot = wave_sums9(g);
+                    if (wave_owner(lane) && tot != 0.f) atomicAdd(&s_g[wave_comp(lane)][k], tot);
                 }
             }
         }
@@ -357,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
         // one component of 64 records
         for (int t = threadIdx.x; t < nb * kNG; t += kBlock) {
             const int k = t / kNG, f = t - k * kNG;
-            const float v = s_g[f][k];
+            const float v = s_g[f][k] * grad_scale(f);
             if (v != 0.f) unsafeAtomicAdd(ba.g_splats + (uint64_t)s_id[k] * kGradF + grad_slot(f), v);
         }
     }
