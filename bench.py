@@ -171,11 +171,13 @@ def timed_graph(step, steps, warmup, torch):
 def stage_times(vb, params, target, steps, warmup, torch, bwd):
     """Per-stage HIP-event times of eager steps on the launching stream
     (lists of ms): project, sort (binning + ranges), order, render[, l1,
-    bwd_render (with its gradient clears), bwd_project]."""
+    bwd_render (adding into the gradient records that the previous
+    bwd_project cleared), bwd_project (clearing them)]."""
     names = ["project", "sort", "order", "render"] + (["l1", "bwd_render", "bwd_project"] if bwd else [])
     calls = [lambda: vb.project(params), vb.sort, vb.tile_order, vb.blend]
     if bwd:
-        calls += [lambda: vb.l1(target), vb.backward_render, lambda: vb.backward_project(params)]
+        calls += [lambda: vb.l1(target), lambda: vb.backward_render(accumulate=vb.g_clear),
+                  lambda: vb.backward_project(params, clear=True)]
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
         for c in calls:

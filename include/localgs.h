@@ -264,12 +264,18 @@ lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam, int64_t n
  * [n,LGS_GRAD_FLOATS].  Writes (overwrites) d_means3d [n,3],
  * d_log_scales [n,3], d_quats [n,4], d_opacity_logits [n],
  * d_sh [n,(deg+1)^2,3]; culled Gaussians get zero.
+ * flags: 0, or LGS_PROJ_BWD_CLEAR to set every nonzero gradient record it
+ * reads back to zero, so that the records are all zero afterwards and the
+ * next lgs_render_backward can add into them (LGS_BWD_ACCUMULATE) without
+ * clearing them first: the clear costs only the records that were written.
  */
+#define LGS_PROJ_BWD_CLEAR 0x1
 lgs_status lgs_project_backward(const lgs_camera *cam, int64_t n, int32_t sh_degree,
                                 const float *means3d, const float *log_scales, const float *quats,
                                 const float *opacity_logits, const float *sh, const int32_t *rect,
-                                const float *g_splats, float *d_means3d, float *d_log_scales,
-                                float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
+                                float *g_splats, float *d_means3d, float *d_log_scales,
+                                float *d_quats, float *d_opacity_logits, float *d_sh, int32_t flags,
+                                void *stream);
 
 /*
  * Multi-view batches.  A batch renders up to LGS_MAX_VIEWS cameras (sizes may
@@ -374,12 +380,13 @@ lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, in
 
 /* lgs_project_backward of a batch: the view-major gradients of the projected
  * attributes are summed over the views into the raw-parameter gradients
- * [n, ...] (overwritten). */
+ * [n, ...] (overwritten); flags as for lgs_project_backward. */
 lgs_status lgs_project_backward_batch(const lgs_camera *cams, int32_t num_views, int64_t n, int32_t sh_degree,
                                       const float *means3d, const float *log_scales, const float *quats,
                                       const float *opacity_logits, const float *sh, const int32_t *rect,
-                                      const float *g_splats, float *d_means3d, float *d_log_scales,
-                                      float *d_quats, float *d_opacity_logits, float *d_sh, void *stream);
+                                      float *g_splats, float *d_means3d, float *d_log_scales,
+                                      float *d_quats, float *d_opacity_logits, float *d_sh, int32_t flags,
+                                      void *stream);
 
 /*
  * Step graphs: lgs_graph_begin starts capturing the calls enqueued on

@@ -27,6 +27,7 @@ RENDER_Q8 = 0x20
 RENDER_VOTE4 = 0x40
 RENDER_GLOBAL = 0x80
 BWD_ACCUMULATE = 0x100
+PROJ_BWD_CLEAR = 0x1
 
 MAX_VIEWS = 16
 QUEUE_WORDS = 256
@@ -66,7 +67,7 @@ _SIG = {
     "lgs_tile_ranges": (C.c_int, [_P, _P, _P, _I64, _I32, _P, _P]),
     "lgs_render": (C.c_int, [_I32, C.POINTER(LgsCamera)] + [_P] * 8),
     "lgs_render_backward": (C.c_int, [_I32, C.POINTER(LgsCamera), _I64] + [_P] * 9),
-    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 13),
+    "lgs_project_backward": (C.c_int, [C.POINTER(LgsCamera), _I64, _I32] + [_P] * 12 + [_I32, _P]),
     "lgs_l1_workspace_size": (C.c_size_t, []),
     "lgs_l1_loss": (C.c_int, [_P, _P, _I64, _P, _P, _P, C.c_size_t, _P]),
     "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 9),
@@ -77,7 +78,7 @@ _SIG = {
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
     "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 10 + [_I32, _P, _P]),
-    "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 13),
+    "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 12 + [_I32, _P]),
     "lgs_graph_begin": (C.c_int, [_P]),
     "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),
     "lgs_graph_launch": (C.c_int, [_P, _P]),

@@ -70,6 +70,7 @@ class ViewBatch:
         # projected splat records [V*n, SPLAT_FLOATS] and gradient records
         # [V*n, GRAD_FLOATS], view-major, with named views of their fields
         self.splats, self.g_splats = z(E, L.SPLAT_FLOATS), z(E, L.GRAD_FLOATS)
+        self.g_clear = True         # the gradient records are known to be zero
         self.conic_opacity, self.means2d, self.rgb = self.splats[:, 0:4], self.splats[:, 4:6], self.splats[:, 6:9]
         self.g_conic, self.g_opacity = self.g_splats[:, 0:3], self.g_splats[:, 3]
         self.g_means2d, self.g_rgb = self.g_splats[:, 4:6], self.g_splats[:, 6:9]
@@ -235,15 +236,18 @@ class ViewBatch:
 
     def backward(self, params, grad_rgb: torch.Tensor | None = None, grad_T: torch.Tensor | None = None):
         """Enqueue the gradient of the step into d_* (raw parameters, summed
-        over views).  grad_rgb defaults to self.grad_rgb (set by l1)."""
+        over views).  grad_rgb defaults to self.grad_rgb (set by l1).  The
+        projection's backward clears the gradient records it reads, so the
+        next step's blend backward adds into zero records without a clear."""
         self._check(params)
-        self.backward_render(grad_rgb, grad_T)
-        self.backward_project(params)
+        self.backward_render(grad_rgb, grad_T, accumulate=self.g_clear)
+        self.backward_project(params, clear=True)
 
     def backward_render(self, grad_rgb: torch.Tensor | None = None, grad_T: torch.Tensor | None = None,
                         stats: torch.Tensor | None = None, accumulate: bool = False):
         """Enqueue the blend's backward into the projected gradients g_*
         (overwritten, or added to with accumulate=True)."""
+        self.g_clear = False
         lb, s = L.lib(), _stream()
         g = self.grad_rgb if grad_rgb is None else _req(grad_rgb, torch.float32, "grad_rgb")
         bv = backward_variant(self.variant) | (L.BWD_ACCUMULATE if accumulate else 0)
@@ -256,15 +260,19 @@ class ViewBatch:
                                              self.bwd_blocks_per_cu, _p(stats), s),
                 "lgs_render_backward_batch")
 
-    def backward_project(self, params):
-        """Enqueue the projection's backward into the raw-parameter gradients."""
+    def backward_project(self, params, clear: bool = False):
+        """Enqueue the projection's backward into the raw-parameter gradients;
+        clear=True sets the gradient records back to zero as they are read."""
         self._check(params)
         lb, s = L.lib(), _stream()
         means3d, log_scales, quats, logits, sh = params
         L.check(lb.lgs_project_backward_batch(self.cam_arr, self.V, self.n, self.deg, _p(means3d), _p(log_scales),
                                               _p(quats), _p(logits), _p(sh), _p(self.rect), _p(self.g_splats),
                                               _p(self.d_means3d), _p(self.d_log_scales), _p(self.d_quats),
-                                              _p(self.d_logits), _p(self.d_sh), s), "lgs_project_backward_batch")
+                                              _p(self.d_logits), _p(self.d_sh), L.PROJ_BWD_CLEAR if clear else 0, s),
+                "lgs_project_backward_batch")
+        if clear:
+            self.g_clear = True
 
     def train_step(self, params, target_packed):
         """forward + L1 + backward, all enqueued."""

@@ -462,7 +462,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
                                                           const float *__restrict__ quats,
                                                           const float *__restrict__ logits,
                                                           const float *__restrict__ sh, const int4 *__restrict__ rect,
-                                                          const float *__restrict__ g_splats,
+                                                          float *__restrict__ g_splats, bool clear,
                                                           float *__restrict__ d_means3d,
                                                           float *__restrict__ d_log_scales, float *__restrict__ d_quats,
                                                           float *__restrict__ d_logits, float *__restrict__ d_sh)
@@ -489,10 +489,22 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
         RawGrad acc = {};
         for (int v = 0; v < cb.V; ++v) {
             const int64_t o = (int64_t)v * n + i;
-            const float *gr = g_splats + (uint64_t)o * kGradF;
-            const float gc3[3] = {gr[0], gr[1], gr[2]};
-            const float gr3[3] = {gr[6], gr[7], gr[8]};
-            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], make_float2(gr[4], gr[5]), gc3, gr[3],
+            float *gr = g_splats + (uint64_t)o * kGradF;
+            float gv[kGradF];
+            bool nz = false;
+#pragma unroll
+            for (int c = 0; c < kGradF; ++c) {
+                gv[c] = gr[c];
+                nz = nz || gv[c] != 0.f;
+            }
+            if (clear && nz) {
+                // read and cleared: the record is zero for the next backward
+#pragma unroll
+                for (int c = 0; c < kGradF; ++c) gr[c] = 0.f;
+            }
+            const float gc3[3] = {gv[0], gv[1], gv[2]};
+            const float gr3[3] = {gv[6], gv[7], gv[8]};
+            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], make_float2(gv[4], gv[5]), gc3, gv[3],
                                    gr3, acc, dslot);
         }
         for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
@@ -561,15 +573,16 @@ extern "C" lgs_status lgs_project(const lgs_camera *camera, int64_t n, int32_t s
 extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int32_t num_views, int64_t n,
                                                  int32_t sh_degree, const float *means3d, const float *log_scales,
                                                  const float *quats, const float *opacity_logits, const float *sh,
-                                                 const int32_t *rect, const float *g_splats, float *d_means3d,
+                                                 const int32_t *rect, float *g_splats, float *d_means3d,
                                                  float *d_log_scales, float *d_quats, float *d_opacity_logits,
-                                                 float *d_sh, void *stream)
+                                                 float *d_sh, int32_t flags, void *stream)
 {
     CamBatch cb;
     LGS_REQUIRE(cams_from(cameras, num_views, cb),
                 "lgs_project_backward: invalid camera(s) or num_views not in 1..%d", kMaxViews);
     LGS_REQUIRE(n >= 0, "lgs_project_backward: n < 0");
     LGS_REQUIRE(sh_degree >= 0 && sh_degree <= 3, "lgs_project_backward: sh_degree must be 0..3");
+    LGS_REQUIRE((flags & ~LGS_PROJ_BWD_CLEAR) == 0, "lgs_project_backward: unknown flags %d", flags);
     if (n == 0) return LGS_OK;
     LGS_REQUIRE(means3d && log_scales && quats && opacity_logits && sh && rect, "lgs_project_backward: null input");
     LGS_REQUIRE(g_splats != nullptr, "lgs_project_backward: null gradient input");
@@ -582,7 +595,7 @@ extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int3
     auto *rc = reinterpret_cast<const int4 *>(rect);
 #define LGS_PB(D)                                                                                                   \
     hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \
-                       sh, rc, g_splats, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
+                       sh, rc, g_splats, (flags & LGS_PROJ_BWD_CLEAR) != 0, d_means3d, d_log_scales, d_quats, d_opacity_logits, d_sh)
     switch (sh_degree) {
     case 0: LGS_PB(0); break;
     case 1: LGS_PB(1); break;
@@ -597,10 +610,11 @@ extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int3
 extern "C" lgs_status lgs_project_backward(const lgs_camera *camera, int64_t n, int32_t sh_degree,
                                            const float *means3d, const float *log_scales, const float *quats,
                                            const float *opacity_logits, const float *sh, const int32_t *rect,
-                                           const float *g_splats, float *d_means3d, float *d_log_scales,
-                                           float *d_quats, float *d_opacity_logits, float *d_sh, void *stream)
+                                           float *g_splats, float *d_means3d, float *d_log_scales,
+                                           float *d_quats, float *d_opacity_logits, float *d_sh, int32_t flags,
+                                           void *stream)
 {
     return lgs_project_backward_batch(camera, 1, n, sh_degree, means3d, log_scales, quats, opacity_logits, sh, rect,
                                       g_splats, d_means3d, d_log_scales, d_quats,
-                                      d_opacity_logits, d_sh, stream);
+                                      d_opacity_logits, d_sh, flags, stream);
 }

@@ -209,7 +209,9 @@ def render_backward(variant, cam, binned: Binned, proj: Projected, T, nc, grad_r
     return g
 
 
-def project_backward(cam, means3d, log_scales, quats, opacity_logits, sh, rect, g):
+def project_backward(cam, means3d, log_scales, quats, opacity_logits, sh, rect, g, clear: bool = False):
+    """Raw-parameter gradients from the gradient records g["splats"]; with
+    clear=True the records are zero afterwards."""
     n = means3d.shape[0]
     deg = int(round(sh.shape[1] ** 0.5)) - 1
     d = dict(means3d=torch.empty_like(means3d), log_scales=torch.empty_like(log_scales),
@@ -219,7 +221,8 @@ def project_backward(cam, means3d, log_scales, quats, opacity_logits, sh, rect, 
                                          _p(quats), _p(opacity_logits), _p(sh), _p(rect), _p(g["splats"]),
                                          _p(d["means3d"]),
                                          _p(d["log_scales"]), _p(d["quats"]), _p(d["opacity_logits"]),
-                                         _p(d["sh"]), _stream()), "lgs_project_backward")
+                                         _p(d["sh"]), L.PROJ_BWD_CLEAR if clear else 0, _stream()),
+            "lgs_project_backward")
     return d
 
 

@@ -108,7 +108,7 @@ def test_batch_and_graph_arguments_rejected_on_host():
         assert lb.lgs_render_batch(3, cams, nv, *([None] * 7), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
         assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 10), 0, None, None) == \
             L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 13)) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 12), 0, None) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
     assert lb.lgs_sort_batch(2, tx, tx, 10, None, None, None, None, None, 10, None, None, None, 0, None) == \
         L.LGS_ERR_INVALID_ARG

@@ -167,8 +167,15 @@ def test_batch_backward_equals_sum_of_views(variant, bwd_lpt, bwd_persistent, bp
                      bwd_blocks_per_cu=bpc)
     vb.fit(params)
     vb.forward(params)
-    vb.backward(params, grad_rgb=vb.pack([to_dev(g) for g in gCs]))
+    # the blend's backward and the projection's backward separately, to check
+    # the gradient records in between; the projection's backward clears them
+    vb.backward_render(grad_rgb=vb.pack([to_dev(g) for g in gCs]), accumulate=vb.g_clear)
     torch.cuda.synchronize()
+    g_records = vb.g_splats.clone()
+    vb.backward_project(params, clear=True)
+    torch.cuda.synchronize()
+    assert not bool(vb.g_splats.any()), "the projection's backward left nonzero gradient records"
+    vb.g_splats.copy_(g_records)
     want = {k: 0.0 for k in ("means3d", "log_scales", "quats", "opacity_logits", "sh")}
     for v, c in enumerate(cams):
         img, T, nc, (proj, binned) = R.rasterize(c, *params, variant=variant, binner=R.Binner(capacity=0))
@@ -185,6 +192,32 @@ def test_batch_backward_equals_sum_of_views(variant, bwd_lpt, bwd_persistent, bp
     got = vb.grads()
     for k in want:
         _close_scaled(got[k].cpu().numpy(), want[k], k)
+
+
+def test_consecutive_steps_do_not_carry_gradients():
+    """The batch's step clears the gradient records in the projection's
+    backward and the next step adds into them without a clear: two steps on
+    the same parameters give the same raw gradients (up to the order of the
+    float atomics), also when the visible set changes between steps."""
+    sc = scenes.make_config(5, n=8000)
+    cams = ring_cameras([(128, 96), (100, 100), (64, 48)])
+    params = scene_tensors(sc)
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant="local_q8_v4", bwd_persistent=True, bwd_blocks_per_cu=4)
+    vb.fit(params)
+    rng = np.random.default_rng(3)
+    target = torch.from_numpy(rng.uniform(0, 1, size=vb.out_rgb.numel()).astype(np.float32)).cuda()
+    moved = [p.clone() for p in params]
+    moved[0].add_(0.05)                          # shifts the means: another visible set
+    runs = []
+    for ps in (params, params, moved, params):
+        vb.fit(ps)
+        vb.train_step(ps, target)
+        torch.cuda.synchronize()
+        runs.append({k: v.cpu().numpy().copy() for k, v in vb.grads().items()})
+        assert vb.g_clear and not bool(vb.g_splats.any())
+    for k in runs[0]:
+        _close_scaled(runs[1][k], runs[0][k], f"{k} second step", tol=1e-5)
+        _close_scaled(runs[3][k], runs[0][k], f"{k} after a different visible set", tol=1e-5)
 
 
 def test_step_graph_replays_match_eager():
