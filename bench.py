@@ -28,6 +28,7 @@ is launched on); `rooflines` gives every stage against its bound.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -46,12 +47,13 @@ PEAK_HBM_GBS = 8000.0
 # colour, T update, termination compare
 OPS_PER_PAIR = 14
 # per replayed (pixel, Gaussian) step of the backward blend: 5 FMA exponent,
-# exp, floor select and clamp (2), 1/(1 - alpha) (2), T recovery, w = alpha T,
-# dL/dalpha (12 for the colour terms, 2 for the T term), 3 FMA running
-# colour sums, 23 for the nine partials (dx, dy, the chain through the conic
-# quadratic and opacity), 9 additions of the partials into the per-Gaussian
-# sums
-OPS_PER_BWD_STEP = 61
+# exp, floor select and clamp (2), 1/(1 - alpha) (2), T recovery and
+# w = alpha T (2), dL/dalpha = T (gC . c) - G / (1 - alpha) (5), the update
+# of the scalar G = gC . R + gT T_f (1), 17 for the nine partials (dx, dy,
+# alpha dL/dalpha and its products with dx and dy, the chain to the mean, the
+# conic and the opacity, the colour gradient) and 9 additions of the
+# partials into the per-Gaussian sums
+OPS_PER_BWD_STEP = 44
 
 SAMPLE_PIXELS = 3000
 GUARD_STORED = 1e-5      # decision guard against the float32-stored projection
@@ -221,6 +223,40 @@ def valu_roof(name, lane_units, ops, ms, what):
     return {"kernel": name, "bound": "alu", "achieved": t, "peak": PEAK_VALU_TOPS,
             "unit": "T lane-ops/s (full-rate VALU)", "frac": t / PEAK_VALU_TOPS, "lane_units": int(lane_units),
             "ops_per_unit": ops, "ms": ms, "per_unit": what}
+
+
+# HBM bytes per launch of the headline step's dominant kernel, from two
+# rocprofv3 --pmc runs of `bench.py --only c5 --local-only` (FETCH_SIZE, then
+# WRITE_SIZE, each scaled by what it reads for a 512 MiB device-to-device copy:
+# x2.0 and x1.0); valid only while the kernel's sources hash to the values the
+# counters were taken on, else the roofline's traffic is null
+MEASURED_TRAFFIC = {
+    "render_bwd_kernel": {
+        "sources": ["include/localgs.h", "paper_2606_16566_amd/csrc/common.hpp",
+                    "paper_2606_16566_amd/csrc/render_common.hpp", "paper_2606_16566_amd/csrc/render_bwd.hip"],
+        "sha256": None,
+        "read_bytes": None,
+        "write_bytes": None,
+        "profile": "profiles/train_clustered-10M-16views_hbm_counters.md",
+    },
+}
+
+
+def sources_sha256(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when no
+    counters were taken on its current sources."""
+    e = MEASURED_TRAFFIC.get(kernel)
+    if e is None or e["sha256"] is None or sources_sha256(e["sources"]) != e["sha256"]:
+        return None
+    return float(e["read_bytes"] + e["write_bytes"])
 
 
 def proj_bytes(n, K, V):
@@ -702,7 +738,7 @@ def main():
         roofs = head["rooflines"]
         dom = max(roofs, key=lambda k: roofs[k]["ms"])
         roof = dict(roofs[dom])
-        roof["traffic"] = None
+        roof["traffic"] = measured_traffic(roof["kernel"])
         workload = "clustered-10M-16views-mixed forward+backward (16 views, one captured graph per step)"
         cfg = {"workload": workload, "gaussians": int(sc[5].n), "sh_degree": int(sc[5].sh_degree),
                "views": head["views"], "pixels": head["pixels"], "pairs": head["pairs"], "tuned": head["tuned"]}

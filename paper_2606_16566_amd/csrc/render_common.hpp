@@ -194,10 +194,11 @@ __device__ __forceinline__ R dot_exponent(const Hoisted<R> &h, const TileCtx<R> 
 // cases for the bottom), then an interval test against [y0, y1].
 // Evaluated in float on a slightly larger ellipse, tau' = tau (1 + 1e-3) +
 // 1e-2: the enlargement exceeds every float rounding error of the test (the
-// product b^2 is split exactly so det keeps full relative accuracy, and the
-// square-root arguments stay >= c (tau' - tau) at the true tangent points),
-// so a Gaussian that can reach alpha >= 1/255 at a pixel of the strip is
-// never culled.
+// product b^2 is split exactly so det keeps full relative accuracy, the
+// square-root arguments stay >= c (tau' - tau) at the true tangent points,
+// and the hardware reciprocal and square root used for the quotients are
+// within 1 ulp), so a Gaussian that can reach alpha >= 1/255 at a pixel of
+// the strip is never culled.
 // Vertical extent [ymin, ymax] of that enlarged ellipse over the columns
 // [x0, x1]; false when it misses the columns entirely.  A degenerate conic
 // (not positive definite) gives the whole line.
@@ -215,27 +216,28 @@ __device__ __forceinline__ bool column_span(float a, float b, float c, float lo,
         ymax = INFINITY;
         return true;
     }
-    const float dy = sqrtf(a * tau / det);
+    const float rc = __builtin_amdgcn_rcpf(c);
+    const float dy = __builtin_amdgcn_sqrtf(a * tau * __builtin_amdgcn_rcpf(det));
     const float bdy = b * dy;
     if (-bdy < a * x0) {                       // case A: peak left of the columns
         const float arg = c * tau - det * x0 * x0;
         if (arg < 0.0f) return false;
-        ymax = (-b * x0 + sqrtf(arg)) / c;
+        ymax = (-b * x0 + __builtin_amdgcn_sqrtf(arg)) * rc;
     } else if (-bdy > a * x1) {                // case B: peak right of the columns
         const float arg = c * tau - det * x1 * x1;
         if (arg < 0.0f) return false;
-        ymax = (-b * x1 + sqrtf(arg)) / c;
+        ymax = (-b * x1 + __builtin_amdgcn_sqrtf(arg)) * rc;
     } else {
         ymax = dy;                             // case C: peak inside
     }
     if (bdy < a * x0) {                        // mirrored cases for the bottom
         const float arg = c * tau - det * x0 * x0;
         if (arg < 0.0f) return false;
-        ymin = (-b * x0 - sqrtf(arg)) / c;
+        ymin = (-b * x0 - __builtin_amdgcn_sqrtf(arg)) * rc;
     } else if (bdy > a * x1) {
         const float arg = c * tau - det * x1 * x1;
         if (arg < 0.0f) return false;
-        ymin = (-b * x1 - sqrtf(arg)) / c;
+        ymin = (-b * x1 - __builtin_amdgcn_sqrtf(arg)) * rc;
     } else {
         ymin = -dy;
     }
