@@ -112,6 +112,7 @@ struct Proj {
     double a, b, c;          // conic
     double mx, my;           // projected mean
     double dir[3], dlen;     // unit view direction and |mean - campos|
+    double tau;              // footprint level 2 ln(255 o)
 };
 
 // true if none of the k floats is inf or NaN (exponent bits all ones), with
@@ -123,13 +124,36 @@ __device__ __forceinline__ bool all_finite(const float *p, int k)
     return bad == 0;
 }
 
-// Geometry of the projection (no colour).  Returns false if culled before
-// the footprint test.
-__device__ bool project_geometry(const Cam &cam, const float *m3, const float *ls, const float *qt, float logit,
-                                 Proj &P)
+// The view-independent part of a Gaussian's projection: finiteness of its
+// parameters, the normalised quaternion, the scales, the opacity and the
+// footprint level tau = 2 ln(255 o); computed once per Gaussian and reused
+// for every view of a batch (each is a transcendental in double).
+struct GaussPre {
+    bool ok;                 // parameters finite and quaternion nonzero
+    double qn[4], qlen, s[3], o, tau;
+};
+
+__device__ __forceinline__ GaussPre gauss_pre(const float *m3, const float *ls, const float *qt, float logit)
 {
-    const bool finite = all_finite(m3, 3) & all_finite(ls, 3) & all_finite(qt, 4) & all_finite(&logit, 1);
-    if (!finite) return false;
+    GaussPre g;
+    g.ok = all_finite(m3, 3) & all_finite(ls, 3) & all_finite(qt, 4) & all_finite(&logit, 1);
+    const double q0 = qt[0], q1 = qt[1], q2 = qt[2], q3 = qt[3];
+    const double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    g.ok = g.ok && n2 > 0.0;
+    g.qlen = sqrt(n2);
+    const double inv = 1.0 / g.qlen;
+    g.qn[0] = q0 * inv; g.qn[1] = q1 * inv; g.qn[2] = q2 * inv; g.qn[3] = q3 * inv;
+    for (int j = 0; j < 3; ++j) g.s[j] = exp((double)ls[j]);
+    g.o = 1.0 / (1.0 + exp(-(double)logit));
+    g.tau = 2.0 * log(255.0 * g.o);
+    return g;
+}
+
+// Geometry of the projection (no colour) for one view.  Returns false if
+// culled before the footprint test.
+__device__ bool project_geometry(const Cam &cam, const float *m3, const GaussPre &G, Proj &P)
+{
+    if (!G.ok) return false;
     const float *V = cam.view;
     for (int i = 0; i < 3; ++i) P.m[i] = m3[i];
     // camera-space position; this FMA order defines the depth key
@@ -137,21 +161,17 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const float *l
         P.t[k] = fma((double)V[4 * k + 2], P.m[2], fma((double)V[4 * k + 1], P.m[1],
                  fma((double)V[4 * k + 0], P.m[0], (double)V[4 * k + 3])));
     if (!(P.t[2] > (double)cam.znear)) return false;
-    double q0 = qt[0], q1 = qt[1], q2 = qt[2], q3 = qt[3];
-    double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
-    if (!(n2 > 0.0)) return false;
-    P.qlen = sqrt(n2);
-    double inv = 1.0 / P.qlen;
-    double w = q0 * inv, x = q1 * inv, y = q2 * inv, z = q3 * inv;
+    P.qlen = G.qlen;
+    const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
     P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
     P.R[0][0] = 1.0 - 2.0 * (y * y + z * z); P.R[0][1] = 2.0 * (x * y - w * z); P.R[0][2] = 2.0 * (x * z + w * y);
     P.R[1][0] = 2.0 * (x * y + w * z); P.R[1][1] = 1.0 - 2.0 * (x * x + z * z); P.R[1][2] = 2.0 * (y * z - w * x);
     P.R[2][0] = 2.0 * (x * z - w * y); P.R[2][1] = 2.0 * (y * z + w * x); P.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
-    for (int j = 0; j < 3; ++j) P.s[j] = exp((double)ls[j]);
+    for (int j = 0; j < 3; ++j) P.s[j] = G.s[j];
     const double fx = cam.fx, fy = cam.fy;
     const double limx = kGuard * (double)cam.tanx, limy = kGuard * (double)cam.tany;
     const double tz = P.t[2], rz = 1.0 / tz;
-    double u = P.t[0] / tz, v = P.t[1] / tz;
+    double u = P.t[0] * rz, v = P.t[1] * rz;
     P.uc = false; P.vc = false;
     if (u < -limx) { u = -limx; P.uc = true; } else if (u > limx) { u = limx; P.uc = true; }
     if (v < -limy) { v = -limy; P.vc = true; } else if (v > limy) { v = limy; P.vc = true; }
@@ -174,18 +194,23 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const float *l
     P.a = P.Y * id; P.b = -P.Z * id; P.c = P.X * id;
     P.mx = fx * P.t[0] * rz + (double)cam.cx;
     P.my = fy * P.t[1] * rz + (double)cam.cy;
-    P.o = 1.0 / (1.0 + exp(-(double)logit));
+    P.o = G.o;
+    P.tau = G.tau;
     double d0 = P.m[0] - (double)cam.campos[0], d1 = P.m[1] - (double)cam.campos[1], d2 = P.m[2] - (double)cam.campos[2];
     P.dlen = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    if (P.dlen > 0.0) { P.dir[0] = d0 / P.dlen; P.dir[1] = d1 / P.dlen; P.dir[2] = d2 / P.dlen; }
-    else { P.dir[0] = 0.0; P.dir[1] = 0.0; P.dir[2] = 1.0; }
+    if (P.dlen > 0.0) {
+        const double il = 1.0 / P.dlen;
+        P.dir[0] = d0 * il; P.dir[1] = d1 * il; P.dir[2] = d2 * il;
+    } else {
+        P.dir[0] = 0.0; P.dir[1] = 0.0; P.dir[2] = 1.0;
+    }
     return true;
 }
 
 // Tile rectangle of the footprint; false if it covers no pixel centre.
 __device__ bool footprint(const Cam &cam, const Proj &P, int4 &rect)
 {
-    double tau = 2.0 * log(255.0 * P.o);
+    const double tau = P.tau;
     if (!(tau > 0.0)) return false;
     double tm = tau * (1.0 + kFootRel) + kFootAbs;
     double rx = sqrt(tm * P.X) + kFootPx, ry = sqrt(tm * P.Y) + kFootPx;
@@ -265,12 +290,13 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     const float logit = logits[i];
     const float *shi = s_sh[wid] + __lane_id() * sh_stride(3 * K);
     const bool sh_ok = all_finite(shi, 3 * K);
+    const GaussPre G = gauss_pre(m3, ls, qt, logit);
     for (int v = 0; v < cb.V; ++v) {
         const Cam &cam = cb.cam[v];
         const int64_t o = (int64_t)v * n + i;
         Proj P;
         int4 r = make_int4(0, 0, 0, 0);
-        const bool vis = sh_ok && project_geometry(cam, m3, ls, qt, logit, P) && footprint(cam, P, r);
+        const bool vis = sh_ok && project_geometry(cam, m3, G, P) && footprint(cam, P, r);
         if (!vis) {
             const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
             store_splat(splats, (uint64_t)o, z, z, 0.f);
@@ -303,8 +329,8 @@ struct RawGrad {
 // parameters, shi its SH coefficients and dshi the slot accumulating
 // dL/d sh; g* are this view's gradients of the projected attributes.
 template <int DEG>
-__device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m3, const float *ls, const float *qt,
-                                                  float logit, const float *shi, const int4 r, const float2 g2,
+__device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m3, const GaussPre &G,
+                                                  const float *shi, const int4 r, const float2 g2,
                                                   const float *g_con, float g_op, const float *g_col, RawGrad &acc,
                                                   float *dshi)
 {
@@ -326,7 +352,8 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
                      d2 = (double)m3[2] - (double)cam.campos[2];
         const double dlen = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         double dir[3] = {0.0, 0.0, 1.0};
-        if (dlen > 0.0) { dir[0] = d0 / dlen; dir[1] = d1 / dlen; dir[2] = d2 / dlen; }
+        const double il = dlen > 0.0 ? 1.0 / dlen : 0.0;
+        if (dlen > 0.0) { dir[0] = d0 * il; dir[1] = d1 * il; dir[2] = d2 * il; }
         double gcol[3] = {g_col[0], g_col[1], g_col[2]};
         // colour: rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
         double Y[K];
@@ -348,11 +375,11 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
         }, gdir);
         if (dlen > 0.0) {
             const double dd = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-            for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - dir[k] * dd) / dlen;
+            for (int k = 0; k < 3; ++k) gm[k] += (gdir[k] - dir[k] * dd) * il;
         }
     }
     Proj P;
-    if (!project_geometry(cam, m3, ls, qt, logit, P)) return;
+    if (!project_geometry(cam, m3, G, P)) return;
     const double gmx = g2.x, gmy = g2.y;
     const double ga = g_con[0], gb = g_con[1], gc = g_con[2];
     const double go = g_op;
@@ -424,10 +451,11 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
                    + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     // normalisation q / |q|
     const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
-    acc.q[0] += (gq[0] - w * dq) / P.qlen;
-    acc.q[1] += (gq[1] - x * dq) / P.qlen;
-    acc.q[2] += (gq[2] - y * dq) / P.qlen;
-    acc.q[3] += (gq[3] - z * dq) / P.qlen;
+    const double iq = 1.0 / P.qlen;
+    acc.q[0] += (gq[0] - w * dq) * iq;
+    acc.q[1] += (gq[1] - x * dq) * iq;
+    acc.q[2] += (gq[2] - y * dq) * iq;
+    acc.q[3] += (gq[3] - z * dq) * iq;
 }
 
 
@@ -486,6 +514,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
         const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
         const float logit = logits[i];
         const float *shi = s_sh[wid] + __lane_id() * P;
+        const GaussPre G = gauss_pre(m3, ls, qt, logit);
         RawGrad acc = {};
         for (int v = 0; v < cb.V; ++v) {
             const int64_t o = (int64_t)v * n + i;
@@ -504,8 +533,8 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
             }
             const float gc3[3] = {gv[0], gv[1], gv[2]};
             const float gr3[3] = {gv[6], gv[7], gv[8]};
-            project_bwd_accum<DEG>(cb.cam[v], m3, ls, qt, logit, shi, rect[o], make_float2(gv[4], gv[5]), gc3, gv[3],
-                                   gr3, acc, dslot);
+            project_bwd_accum<DEG>(cb.cam[v], m3, G, shi, rect[o], make_float2(gv[4], gv[5]), gc3, gv[3], gr3, acc,
+                                   dslot);
         }
         for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
         for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)acc.q[k];
