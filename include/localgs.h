@@ -322,12 +322,24 @@ lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, const int32
  * tile_order: NULL to hand out tiles in index order (XCD-banded for one
  *   workgroup per tile), else a device permutation [total tiles] (e.g. from
  *   lgs_tile_order) giving the tile of each queue position, or of each
- *   workgroup without a queue.  Outputs do not depend on the order. */
+ *   workgroup without a queue.  Outputs do not depend on the order.
+ * used_masks: NULL, or device uint64 [used_mask_words] (at least
+ *   lgs_used_mask_words(capacity of the pair buffers, total tiles)): the LOCAL
+ *   variant then records, per wavefront sub-tile and chunk of 64 list
+ *   entries, which entries some pixel of the sub-tile blended (alpha >= 1/255
+ *   before its termination), for lgs_render_backward_batch.  Chunks that a
+ *   sub-tile never reached (it had terminated) are not written.  Other
+ *   variants ignore it. */
 lgs_status lgs_render_batch(int32_t variant, const lgs_camera *cams, int32_t num_views,
                             const uint32_t *ranges, const uint32_t *values, const float *splats,
                             float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
                             uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
-                            void *stream);
+                            uint64_t *used_masks, int64_t used_mask_words, void *stream);
+
+/* Words of the used-entry masks for pair buffers of capacity_pairs pairs and
+ * num_tiles tiles (4 sub-tile planes of capacity_pairs / 64 + num_tiles + 1
+ * words each; 0 for invalid arguments). */
+int64_t lgs_used_mask_words(int64_t capacity_pairs, int32_t num_tiles);
 
 /* lgs_render_debug -- lgs_render_batch's statistics instantiation (one
  * workgroup per tile, tiles in index order) that also records the culling
@@ -370,13 +382,19 @@ lgs_status lgs_tile_order(const uint32_t *ranges, int32_t num_tiles, uint32_t *o
  *   culling), [1] steps replayed (some lane takes the Gaussian), [2] (pixel,
  *   Gaussian) pairs taken, [3] lane evaluations (64 per replayed step).
  *   Counting runs a separate, slower instantiation.
+ * used_masks: NULL, or the used-entry masks that the LOCAL forward of these
+ *   same pair lists recorded (lgs_render_batch with the same sub-tile shape,
+ *   LGS_RENDER_Q8 or not): the replay then visits exactly those entries
+ *   instead of testing every entry its culling keeps (the same gradients,
+ *   less work).  Requires variant LOCAL.
  * The gradients do not depend on the order or the schedule beyond float
  * summation order. */
 lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camera *cams, int32_t num_views, int64_t n_elem,
                                      const uint32_t *ranges, const uint32_t *values, const float *splats,
                                      const float *out_T, const int32_t *out_ncontrib, const float *grad_rgb,
-                                     const float *grad_T, float *g_splats, const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
-                                     uint64_t *stats, void *stream);
+                                     const float *grad_T, float *g_splats, const uint32_t *tile_order,
+                                     uint32_t *queue, int32_t blocks_per_cu, uint64_t *stats,
+                                     const uint64_t *used_masks, int64_t used_mask_words, void *stream);
 
 /* lgs_project_backward of a batch: the view-major gradients of the projected
  * attributes are summed over the views into the raw-parameter gradients

@@ -41,7 +41,8 @@ EXPORTS = ["lgs_last_error", "lgs_version", "lgs_project", "lgs_sort_workspace_s
            "lgs_l1_loss",
            "lgs_project_batch", "lgs_sort_batch", "lgs_render_batch", "lgs_render_backward_batch",
            "lgs_project_backward_batch", "lgs_graph_begin", "lgs_graph_end", "lgs_graph_launch",
-           "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order", "lgs_render_debug"]
+           "lgs_graph_destroy", "lgs_tile_order_workspace_size", "lgs_tile_order", "lgs_render_debug",
+           "lgs_used_mask_words"]
 
 
 class LgsCamera(C.Structure):
@@ -73,11 +74,13 @@ _SIG = {
     "lgs_project_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 9),
     "lgs_sort_batch": (C.c_int, [_I32, C.POINTER(_I32), C.POINTER(_I32), _I64, _P, _P, _P, _P, _P, _I64, _P, _P,
                                  _P, C.c_size_t, _P]),
-    "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 7 + [_P, _P, _I32, _P]),
+    "lgs_render_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 7 + [_P, _P, _I32, _P, _I64, _P]),
+    "lgs_used_mask_words": (_I64, [_I64, _I32]),
     "lgs_render_debug": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32] + [_P] * 9),
     "lgs_tile_order_workspace_size": (C.c_size_t, [_I32]),
     "lgs_tile_order": (C.c_int, [_P, _I32, _P, _P, C.c_size_t, _P]),
-    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 10 + [_I32, _P, _P]),
+    "lgs_render_backward_batch": (C.c_int, [_I32, C.POINTER(LgsCamera), _I32, _I64] + [_P] * 10
+                                  + [_I32, _P, _P, _I64, _P]),
     "lgs_project_backward_batch": (C.c_int, [C.POINTER(LgsCamera), _I32, _I64, _I32] + [_P] * 12 + [_I32, _P]),
     "lgs_graph_begin": (C.c_int, [_P]),
     "lgs_graph_end": (C.c_int, [_P, C.POINTER(_P)]),

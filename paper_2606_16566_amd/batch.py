@@ -107,6 +107,9 @@ class ViewBatch:
         self.vals = torch.empty(cap, dtype=torch.int32, device=self.dev)
         need = L.lib().lgs_sort_workspace_size(self.V * self.n, cap, self.num_tiles)
         self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.dev)
+        # used-entry masks of the LOCAL forward, read by the backward
+        self.used = torch.empty(L.lib().lgs_used_mask_words(cap, self.num_tiles), dtype=torch.int64, device=self.dev)
+        self.used_valid = False
 
     def fit(self, params, headroom: float = 1.15) -> int:
         """Run the forward once and grow the pair buffers until the pair
@@ -162,6 +165,7 @@ class ViewBatch:
             self.exact_tiles = bool(exact_tiles)
         if variant is not None:
             self.variant = variant_code(variant)
+            self.used_valid = False            # recorded for another sub-tile shape
         if persistent is not None:
             self.persistent = bool(persistent)
         if blocks_per_cu is not None:
@@ -191,6 +195,7 @@ class ViewBatch:
 
     def sort(self):
         """Enqueue the pair sort and the tile ranges of all views."""
+        self.used_valid = False                # new lists
         lb, s = L.lib(), _stream()
         ws, wsb = _aligned(self.ws)
         ex = self.exact_tiles
@@ -219,10 +224,13 @@ class ViewBatch:
         """Enqueue the render launch itself."""
         lb, s = L.lib(), _stream()
         order = _p(self.order) if self.lpt else None
+        local = (self.variant & 0xF) == L.RENDER_LOCAL
         L.check(lb.lgs_render_batch(self.variant, self.cam_arr, self.V, _p(self.ranges), _p(self.vals),
                                     _p(self.splats), _p(self.out_rgb), _p(self.out_T), _p(self.out_nc), _p(stats),
-                                    _p(self.queue) if self.persistent else None, order, self.blocks_per_cu, s),
+                                    _p(self.queue) if self.persistent else None, order, self.blocks_per_cu,
+                                    _p(self.used) if local else None, self.used.numel(), s),
                 "lgs_render_batch")
+        self.used_valid = local
 
     def l1(self, target_packed: torch.Tensor):
         """Enqueue L = mean |images - target| (loss -> self.loss) and its
@@ -257,7 +265,8 @@ class ViewBatch:
                                              _p(self.vals), _p(self.splats), _p(self.out_T), _p(self.out_nc), _p(g),
                                              _p(grad_T), _p(self.g_splats), _p(self.order) if self.bwd_lpt else None,
                                              _p(self.bwd_queue) if self.bwd_persistent else None,
-                                             self.bwd_blocks_per_cu, _p(stats), s),
+                                             self.bwd_blocks_per_cu, _p(stats),
+                                             _p(self.used) if self.used_valid else None, self.used.numel(), s),
                 "lgs_render_backward_batch")
 
     def backward_project(self, params, clear: bool = False):

@@ -221,12 +221,27 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
             s_e[slot] = hoist<R>(m, co, lo, tc.ox, tc.oy);
             s_c[slot] = make_float4(cur.mr.z, cur.mr.w, cur.b, __int_as_float((int)(j - range.x + 1)));
         }
+        if (UNIFORM && VP > 1) {
+            // pad the list to a multiple of VP with entries that no pixel
+            // keeps (log2 alpha = -inf; position -1, never a last
+            // contributor), so that the unrolled steps need no exit test
+            const int padded = (cnt + VP - 1) / VP * VP;
+            if ((int)lane >= cnt && (int)lane < padded) {
+                Hoisted<R> z;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) z.v[c] = (R)0;
+                z.v[5] = (R)(-INFINITY);
+                s_e[lane] = z;
+                s_c[lane] = make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         const int chunk = (int)min((uint32_t)64, range.y - base);
         int consumed = chunk;
+        uint64_t used = 0;              // staged slots that some lane of the wavefront blended
         if constexpr (UNIFORM) {
             // the wave-wide vote runs once per VP Gaussians; steps after the
             // last lane has stopped change nothing (every update is masked by
@@ -236,8 +251,8 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
 #pragma unroll
                 for (int u = 0; u < VP; ++u) {
                 const int k = k0 + u;
-                if (VP > 1 && k >= cnt) break;
-                kdone = k;
+                if (VP == 1) kdone = k;
+                else if (k < cnt) kdone = k;
                 const float4 f = s_c[k];
                 const float s32 = (float)dot_exponent(s_e[k], tc);
                 const bool keep = s32 >= kLog2AlphaMin;
@@ -252,7 +267,12 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
                 T = lv ? Tn : T;
                 last = (lv && keep) ? __float_as_int(f.w) : last;
                 live = lv;
-                if (STATS) st.eval++;
+                // lanes that blended this Gaussian: exactly those whose last
+                // contributor is now this list position (one compare, mask in
+                // scalar registers)
+                if (__builtin_amdgcn_uicmp((uint32_t)last, (uint32_t)__float_as_int(f.w), 32) != 0ull)
+                    used |= 1ull << k;
+                if (STATS && k < cnt) st.eval++;
                 }
                 if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
                     wave_live = false;
@@ -286,6 +306,13 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
                 st.eval += mx;
             }
             wave_live = __ballot(live) != 0ull;
+        }
+        if (UNIFORM && args.used != nullptr) {
+            // record, by list position, the chunk's entries that some lane
+            // of this sub-tile blended (the entries its backward replays)
+            const uint64_t pos_used = __ballot(hit && ((used >> __popcll(bits & lt)) & 1ull));
+            const int64_t wd = used_word(range.x, tc.tile, base);
+            if (lane == 0 && wd < args.used_plane) args.used[(int64_t)tc.wid * args.used_plane + wd] = pos_used;
         }
         if (STATS) st.seen += consumed;
         // all lanes have read this chunk before the next one overwrites it
@@ -380,7 +407,8 @@ namespace {
 lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_views, const uint32_t *ranges,
                         const uint32_t *values, const float *splats, float *out_rgb, float *out_T,
                         int32_t *out_ncontrib, uint64_t *stats, uint32_t *queue,
-                        const uint32_t *tile_order, int32_t blocks_per_cu, uint32_t *masks, void *stream)
+                        const uint32_t *tile_order, int32_t blocks_per_cu, uint32_t *masks, uint64_t *used_masks,
+                        int64_t used_mask_words, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_batch: num_views must be 1..%d",
                 kMaxViews);
@@ -398,12 +426,16 @@ lgs_status render_batch(int32_t variant, const lgs_camera *cameras, int32_t num_
     LGS_REQUIRE(ranges && out_rgb && out_T && out_ncontrib, "lgs_render: null argument");
     LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)splats % 16 == 0),
                 "lgs_render: ranges must be 8-byte and splats 16-byte aligned");
+    LGS_REQUIRE(used_masks == nullptr || (used_mask_words >= 4 && (uintptr_t)used_masks % 8 == 0),
+                "lgs_render_batch: used_masks needs 8-byte alignment and at least 4 words");
     render::RenderArgs a = render::make_args(cams, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib,
                                              stats);
     hipStream_t s = as_stream(stream);
     a.order = tile_order;                     // queue position -> tile, or workgroup -> tile
     a.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
     a.masks = masks;
+    a.used = used_masks;
+    a.used_plane = used_masks ? used_mask_words / 4 : 0;
     const bool persistent = queue != nullptr && (v == LGS_RENDER_HOIST_CULL || v == LGS_RENDER_LOCAL);
     unsigned grid = (unsigned)a.num_tiles;
     if (persistent) {
@@ -439,10 +471,16 @@ extern "C" lgs_status lgs_render_batch(int32_t variant, const lgs_camera *camera
                                        const uint32_t *ranges, const uint32_t *values, const float *splats,
                                        float *out_rgb, float *out_T, int32_t *out_ncontrib, uint64_t *stats,
                                        uint32_t *queue, const uint32_t *tile_order, int32_t blocks_per_cu,
-                                       void *stream)
+                                       uint64_t *used_masks, int64_t used_mask_words, void *stream)
 {
     return render_batch(variant, cameras, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats,
-                        queue, tile_order, blocks_per_cu, nullptr, stream);
+                        queue, tile_order, blocks_per_cu, nullptr, used_masks, used_mask_words, stream);
+}
+
+extern "C" int64_t lgs_used_mask_words(int64_t capacity_pairs, int32_t num_tiles)
+{
+    if (capacity_pairs < 0 || num_tiles < 0) return 0;
+    return 4 * ((capacity_pairs >> 6) + (int64_t)num_tiles + 1);
 }
 
 extern "C" lgs_status lgs_render_debug(int32_t variant, const lgs_camera *cameras, int32_t num_views,
@@ -452,7 +490,7 @@ extern "C" lgs_status lgs_render_debug(int32_t variant, const lgs_camera *camera
 {
     LGS_REQUIRE(stats != nullptr && masks != nullptr, "lgs_render_debug: stats and masks are required");
     return render_batch(variant, cameras, num_views, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats,
-                        nullptr, nullptr, 0, masks, stream);
+                        nullptr, nullptr, 0, masks, nullptr, 0, stream);
 }
 
 extern "C" lgs_status lgs_render(int32_t variant, const lgs_camera *camera, const uint32_t *ranges,
@@ -461,5 +499,5 @@ extern "C" lgs_status lgs_render(int32_t variant, const lgs_camera *camera, cons
 {
     LGS_REQUIRE(camera != nullptr, "lgs_render: invalid camera");
     return lgs_render_batch(variant, camera, 1, ranges, values, splats, out_rgb, out_T, out_ncontrib, stats, nullptr,
-                            nullptr, 0, stream);
+                            nullptr, 0, nullptr, 0, stream);
 }

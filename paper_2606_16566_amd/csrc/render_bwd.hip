@@ -259,7 +259,9 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 // over them is computed once)
                 uint32_t mk = 0;
                 float ymin, ymax;
-                if constexpr (Q8) {
+                if (a.used != nullptr) {
+                    mk = 0xF;                       // the forward's used-entry masks decide below
+                } else if constexpr (Q8) {
                     // quadrant w: columns half (w & 1), rows half (w >> 1)
                     for (int hx = 0; hx < 2; ++hx) {
                         const float x0 = (float)(tx * kTile + 8 * hx) - m.x, x1 = x0 + 7.0f;
@@ -301,7 +303,19 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
             (int)min((int64_t)nb, (int64_t)range.x + wmax - (int64_t)bstart));
         for (int c0 = ((wlimit - 1) >> 6) << 6; wlimit > 0 && c0 >= 0; c0 -= 64) {
             const int j = c0 + lane;
-            const bool bit = j < wlimit && ((s_m[j] >> wid) & 1u);
+            // candidates: the entries some pixel of this sub-tile blended in
+            // the forward (its used-entry masks; an entry outside them has
+            // alpha < 1/255 or comes after termination at every pixel), else
+            // the entries the tight-box test keeps
+            bool bit = j < wlimit;
+            if (a.used != nullptr) {
+                const uint32_t p = bstart + (uint32_t)j;
+                const int64_t wd = used_word(range.x, tc.tile, p);
+                bit = bit && (wd >= a.used_plane
+                              || ((a.used[(int64_t)wid * a.used_plane + wd] >> ((p - range.x) & 63u)) & 1ull));
+            } else {
+                bit = bit && ((s_m[j] >> wid) & 1u);
+            }
             uint64_t bits = __ballot(bit);
             if (STATS) st.cand += (unsigned long long)__popcll(bits);
             while (bits) {
@@ -435,8 +449,9 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
                                                 int64_t n_elem, const uint32_t *ranges, const uint32_t *values,
                                                 const float *splats, const float *out_T,
                                                 const int32_t *out_ncontrib, const float *grad_rgb,
-                                                const float *grad_T, float *g_splats, const uint32_t *tile_order, uint32_t *queue, int32_t blocks_per_cu,
-                                                uint64_t *stats, void *stream)
+                                                const float *grad_T, float *g_splats, const uint32_t *tile_order,
+                                                uint32_t *queue, int32_t blocks_per_cu, uint64_t *stats,
+                                                const uint64_t *used_masks, int64_t used_mask_words, void *stream)
 {
     LGS_REQUIRE(num_views >= 1 && num_views <= kMaxViews, "lgs_render_backward: num_views must be 1..%d", kMaxViews);
     LGS_REQUIRE(cameras != nullptr, "lgs_render_backward: invalid camera");
@@ -452,6 +467,9 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
     LGS_REQUIRE(n_elem == 0 || (values && splats && g_splats), "lgs_render_backward: null argument");
     LGS_REQUIRE(((uintptr_t)ranges % 8 == 0) && ((uintptr_t)splats % 16 == 0) && ((uintptr_t)g_splats % 4 == 0),
                 "lgs_render_backward: ranges must be 8-byte, splats 16-byte and g_splats 4-byte aligned");
+    LGS_REQUIRE(used_masks == nullptr
+                    || (v == LGS_RENDER_LOCAL && used_mask_words >= 4 && (uintptr_t)used_masks % 8 == 0),
+                "lgs_render_backward: used_masks need the LOCAL variant, 8-byte alignment and at least 4 words");
     hipStream_t s = as_stream(stream);
     if (!(variant & LGS_BWD_ACCUMULATE)) fill_async<float>(g_splats, 0.f, n_elem * kGradF, s);
     BwdArgs a;
@@ -459,6 +477,8 @@ extern "C" lgs_status lgs_render_backward_batch(int32_t variant, const lgs_camer
                             const_cast<int32_t *>(out_ncontrib), stats);
     a.r.order = tile_order;
     a.r.global_origin = (variant & LGS_RENDER_GLOBAL) != 0;
+    a.r.used = const_cast<uint64_t *>(used_masks);
+    a.r.used_plane = used_masks ? used_mask_words / 4 : 0;
     a.grad_rgb = grad_rgb; a.grad_T = grad_T;
     a.g_splats = g_splats;
     if (a.r.num_tiles > 0) {
@@ -491,5 +511,5 @@ extern "C" lgs_status lgs_render_backward(int32_t variant, const lgs_camera *cam
                                           float *g_splats, void *stream)
 {
     return lgs_render_backward_batch(variant, camera, 1, n, ranges, values, splats, out_T, out_ncontrib, grad_rgb,
-                                     grad_T, g_splats, nullptr, nullptr, 0, nullptr, stream);
+                                     grad_T, g_splats, nullptr, nullptr, 0, nullptr, nullptr, 0, stream);
 }

@@ -42,8 +42,19 @@ struct RenderArgs {
     int num_tiles;              // all views
     int global_origin;          // hoisted basis at the image origin instead of the tile centre
     uint32_t *masks;            // statistics instantiation only: per-entry culling record, or null
+    uint64_t *used;             // per (sub-tile, chunk) masks of the entries some pixel blended, or null
+    int64_t used_plane;         // words per sub-tile plane of `used`
     ViewTable vt;
 };
+
+// Word of the used-entry masks for list position p of a tile whose list
+// starts at position a (tile index t): chunks of 64 positions from a, offset
+// by a >> 6 and the tile index so that no two tiles' chunks share a word
+// (a plane holds capacity / 64 + tiles + 1 words).
+__device__ __forceinline__ int64_t used_word(uint32_t a, int t, uint32_t p)
+{
+    return (int64_t)(a >> 6) + t + (int64_t)((p - a) >> 6);
+}
 
 inline void fill_views(ViewTable &vt, const Cam *cams, int V)
 {
@@ -80,6 +91,8 @@ inline RenderArgs make_args(const Cam *cams, int V, const uint32_t *ranges, cons
     a.order = nullptr;
     a.global_origin = 0;
     a.masks = nullptr;
+    a.used = nullptr;
+    a.used_plane = 0;
     fill_views(a.vt, cams, V);
     a.num_tiles = a.vt.tile_off[V];
     return a;

@@ -105,8 +105,8 @@ def test_batch_and_graph_arguments_rejected_on_host():
         c.width, c.height, c.fx, c.fy = 16, 16, 100.0, 100.0
     for nv in (0, 17):
         assert lb.lgs_project_batch(cams, nv, 10, 0, *([None] * 9)) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_batch(3, cams, nv, *([None] * 7), None, None, 0, None) == L.LGS_ERR_INVALID_ARG
-        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 10), 0, None, None) == \
+        assert lb.lgs_render_batch(3, cams, nv, *([None] * 7), None, None, 0, None, 0, None) == L.LGS_ERR_INVALID_ARG
+        assert lb.lgs_render_backward_batch(3, cams, nv, 10, *([None] * 10), 0, None, None, 0, None) == \
             L.LGS_ERR_INVALID_ARG
         assert lb.lgs_project_backward_batch(cams, nv, 10, 0, *([None] * 12), 0, None) == L.LGS_ERR_INVALID_ARG
     tx = (C.c_int32 * 2)(4, 0)
@@ -118,6 +118,7 @@ def test_batch_and_graph_arguments_rejected_on_host():
     assert lb.lgs_tile_order(None, 10, None, None, 0, None) == L.LGS_ERR_INVALID_ARG
     assert lb.lgs_tile_order_workspace_size(0) == 0
     assert lb.lgs_tile_order_workspace_size(1000) % 256 == 0
+    assert lb.lgs_used_mask_words(6400, 10) == 4 * (100 + 10 + 1) and lb.lgs_used_mask_words(-1, 10) == 0
 
 
 def header_arity():

@@ -274,6 +274,37 @@ def test_backward_stats_count_replayed_steps():
     assert np.array_equal(res[0][:4], res[1][:4])
 
 
+@pytest.mark.parametrize("variant,persistent", [("local_q8", True), ("local", False), ("local_q8_v4", True)])
+def test_backward_replays_exactly_the_used_entries(variant, persistent):
+    """With the forward's used-entry masks the backward visits exactly the
+    entries some pixel of each sub-tile blended: every candidate step is
+    replayed (candidates == replayed steps), the steps replayed and pairs
+    taken equal those without the masks, and the gradients agree with the
+    culling-driven replay up to the order of float atomics."""
+    sc = scenes.make_config(5, n=12000)
+    cams = ring_cameras([(160, 120), (96, 64), (203, 150)])
+    params = scene_tensors(sc)
+    vb = B.ViewBatch(cams, sc.n, sc.sh_degree, variant=variant, persistent=persistent, blocks_per_cu=2,
+                     bwd_persistent=True, bwd_blocks_per_cu=2)
+    vb.fit(params)
+    vb.forward(params)
+    assert vb.used_valid
+    rng = np.random.default_rng(11)
+    vb.grad_rgb.copy_(to_dev(rng.standard_normal(vb.grad_rgb.numel()).astype(np.float32)))
+    runs = []
+    for with_masks in (True, False):
+        vb.used_valid = with_masks
+        st = torch.zeros(8, dtype=torch.int64, device="cuda")
+        vb.backward_render(stats=st)
+        torch.cuda.synchronize()
+        runs.append((st.cpu().numpy(), vb.g_splats.cpu().numpy().astype(np.float64)))
+    (sm, gm), (sc_, gc) = runs
+    print(f"{variant}: candidates with masks {sm[0]} (replayed {sm[1]}), with culling {sc_[0]} (replayed {sc_[1]})",
+          flush=True)
+    assert sm[0] == sm[1] == sc_[1] and sm[2] == sc_[2] and sc_[0] >= sc_[1]
+    _close_scaled(gm, gc, "gradient records", tol=1e-5)
+
+
 def test_captured_step_grows_and_recaptures():
     """A captured step whose pair count outgrows its capacity (the splats
     grow between replays) overflows, and check() regrows the buffers,
