@@ -153,8 +153,9 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * per touched tile and a stable sort so that each tile's pairs are in
  * ascending (depth, id) order (Sec. II-A: prefix scan, key duplication,
  * radix sort).  Implemented as a stable radix sort of all n depth keys
- * (culled ones hold +inf and sort last) and a scan of their tile counts in
- * that order; then, for grids at most 256 tiles wide, a column pass that
+ * (culled ones hold +inf and sort last) over only the bits in which the
+ * visible keys differ (their range is taken on the device first) and a scan
+ * of their tile counts in that order; then, for grids at most 256 tiles wide, a column pass that
  * generates the pairs from the rectangles straight into tile-column order
  * (depth order kept within a column) and a stable radix sort on the tile row,
  * or, for wider grids, duplication in depth order and a stable radix sort on
@@ -162,6 +163,9 @@ lgs_status lgs_project(const lgs_camera *cam, int64_t n, int32_t sh_degree,
  * (tile << 32 | depth bits) keys emitted in id order.
  *
  * Inputs: depth [n], rect [n,4] from lgs_project; tiles_x * tiles_y tiles.
+ *   A visible Gaussian's depth is positive and finite; a depth whose bit
+ *   pattern is at or above +inf's (+inf, NaN, negative values) marks a culled
+ *   one, whose rectangle must be empty (lgs_project writes both so).
  * splats [n,LGS_SPLAT_FLOATS] (from lgs_project): NULL to give each
  *   Gaussian every tile of its rectangle, else the exact tile assignment: only the tiles whose pixel-centre square its alpha >= 1/255
  *   ellipse meets (the test is conservative: a float evaluation on a

@@ -83,7 +83,10 @@ def apply(vb, cfg):
 
 
 def workload_key(vb, num_pairs: int, family: str) -> str:
-    dev = torch.cuda.get_device_name(vb.dev)
+    # the ISA and compute-unit count identify the device (the marketing name
+    # can come back empty where the driver's name table is not installed)
+    props = torch.cuda.get_device_properties(vb.dev)
+    dev = f"{props.gcnArchName.split(':')[0]}/{props.multi_processor_count}cu"
     sizes = ",".join(f"{c.width}x{c.height}" for c in vb.cams)
     pairs = float(f"{num_pairs:.2g}")
     return f"{dev}|{family}|n={vb.n}|deg={vb.deg}|views={sizes}|pairs~{pairs:.0f}"

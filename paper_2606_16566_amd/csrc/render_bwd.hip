@@ -355,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
                 // uses alpha = 0, so T (times 1/(1 - 0) = 1) and R are unchanged
                 // and every partial is zero.
                 const bool under = raw < kAlphaMax;              // not clamped
-                const float alf = act ? (under ? raw : kAlphaMax) : 0.f;
+                // min(raw, 0.99) for raw >= 0 (as a median: no canonicalising)
+                const float alf = act ? __builtin_amdgcn_fmed3f(raw, 0.f, kAlphaMax) : 0.f;
                 const double al = (double)alf;
                 const double inv = recip(1.0 - al);
                 T = T * inv;                                     // T before this Gaussian

@@ -19,6 +19,7 @@
 // (coalesced, where a gather by the sorted ids would read a whole cache line
 // per 16-byte rectangle), otherwise gathered by its last pass.
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "render_common.hpp"
@@ -328,6 +329,96 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbi
     return match;
 }
 
+// Digit plan of the depth passes.  Only the bits in which the visible depth
+// keys differ need sorting: with lo and hi the smallest and largest key below
+// +inf's bit pattern (positive finite depths order like their bits), the
+// first pass rebases every key to key - lo, and every other key (culled:
+// +inf) to hi - lo, the largest rebased value (culled Gaussians have no tiles,
+// so where they end up among the largest keys changes no pair list); the four
+// passes split the bit length of hi - lo as evenly as they can (25 bits: 6,
+// 6, 6, 7), so that each pass has fewer distinct digits and longer digit runs
+// to write than a fixed 8 bits.  range == nullptr: keys as they are, the
+// caller's shift and width.
+constexpr uint32_t kInfBits = 0x7F800000u;
+struct DepthPlan {
+    const uint32_t *range;     // [lo, hi] (device), from depth_range_kernel
+    int pass;                  // 0..3; pass 0 rebases the keys it reads
+};
+struct DigitSel {
+    int shift, nbits;
+    uint32_t mask, lo, top;    // top = hi - lo: the rebased value of culled keys
+    bool rebase;
+    __device__ __forceinline__ uint32_t key(uint32_t k) const { return rebase ? (k < kInfBits ? k - lo : top) : k; }
+    __device__ __forceinline__ uint32_t digit(uint32_t k) const { return (key(k) >> shift) & mask; }
+};
+template <bool PLAN>
+__device__ __forceinline__ DigitSel digit_sel(const DepthPlan &dp, int shift, int nbits)
+{
+    DigitSel d{shift, nbits, nbits >= 32 ? ~0u : (1u << nbits) - 1u, 0u, 0u, false};
+    if constexpr (!PLAN) return d;
+    const uint32_t lo = dp.range[0], hi = dp.range[1];
+    const uint32_t span = hi >= lo ? hi - lo : 0u;         // no visible key: all rebase to 0
+    const int bits = span ? 32 - __builtin_clz(span) : 0;
+    // the remainder bits go to the last passes, whose digits (exponent and
+    // leading mantissa bits) take fewer distinct values than the low ones
+    auto width = [&](int p) { return bits / 4 + (p >= 4 - bits % 4 ? 1 : 0); };
+    int sh = 0;
+    for (int p = 0; p < dp.pass; ++p) sh += width(p);
+    d.shift = sh;
+    d.nbits = width(dp.pass);
+    d.mask = (1u << d.nbits) - 1u;
+    d.lo = hi >= lo ? lo : 0u;
+    d.top = span;
+    d.rebase = dp.pass == 0;
+    // uniform across the wavefront (scalar registers: the digit loops stay
+    // uniform branches)
+    d.shift = __builtin_amdgcn_readfirstlane(d.shift);
+    d.nbits = __builtin_amdgcn_readfirstlane(d.nbits);
+    d.mask = (uint32_t)__builtin_amdgcn_readfirstlane((int)d.mask);
+    d.lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)d.lo);
+    d.top = (uint32_t)__builtin_amdgcn_readfirstlane((int)d.top);
+    return d;
+}
+
+__global__ void depth_range_init_kernel(uint32_t *range)
+{
+    range[0] = 0xFFFFFFFFu;
+    range[1] = 0u;
+}
+
+// [lo, hi] of the keys below +inf's bit pattern: per-thread extremes over a
+// grid-stride loop (16-byte loads where aligned), then per wavefront, one
+// atomic pair per wavefront
+__global__ __launch_bounds__(kBlock) void depth_range_kernel(const uint32_t *__restrict__ keys, int64_t n,
+                                                             uint32_t *__restrict__ range)
+{
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    auto take = [&](uint32_t k) {
+        if (k < kInfBits) { lo = min(lo, k); hi = max(hi, k); }
+    };
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x, nth = (int64_t)gridDim.x * kBlock;
+    int64_t head = 0;
+    if (reinterpret_cast<uintptr_t>(keys) % 16 == 0) {
+        const uint4 *k4 = reinterpret_cast<const uint4 *>(keys);
+        const int64_t n4 = n / 4;
+        for (int64_t i = tid; i < n4; i += nth) {
+            const uint4 v = k4[i];
+            take(v.x); take(v.y); take(v.z); take(v.w);
+        }
+        head = n4 * 4;
+    }
+    for (int64_t i = head + tid; i < n; i += nth) take(keys[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    }
+    if (__lane_id() == 0 && lo <= hi) {
+        atomicMin(&range[0], lo);
+        atomicMax(&range[1], hi);
+    }
+}
+
 // Four consecutive keys of type KT (uint32_t or uint16_t) in one vector load.
 template <typename KT> struct Key4;
 template <> struct Key4<uint32_t> {
@@ -354,11 +445,13 @@ constexpr int kHistGroup = 4;
 
 inline int64_t hist_stride(int64_t nblocks) { return (nblocks + kHistGroup - 1) / kHistGroup * kHistGroup; }
 
-template <int ITEMS, typename KT, int COPIES, int HG>
+template <int ITEMS, typename KT, int COPIES, int HG, bool PLAN>
 __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict__ keys, int64_t n_max,
-                                                            const uint32_t *n_dev, int shift, uint32_t mask,
-                                                            uint32_t *__restrict__ hist, int64_t stride)
+                                                            const uint32_t *n_dev, int shift, int nbits,
+                                                            uint32_t *__restrict__ hist, int64_t stride,
+                                                            DepthPlan dp)
 {
+    const DigitSel ds = digit_sel<PLAN>(dp, shift, nbits);
     using V = typename Key4<KT>::V;
     constexpr int kTileN = kBlock * ITEMS;
     constexpr int kV = ITEMS / 4;                              // 4-key loads per thread and block
@@ -398,11 +491,11 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
 #pragma unroll
                 for (int r = 0; r < kV; ++r) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) atomicAdd(&my_h[(Key4<KT>::at(cur[r], e) >> shift) & mask], 1u);
+                    for (int e = 0; e < 4; ++e) atomicAdd(&my_h[ds.digit(Key4<KT>::at(cur[r], e))], 1u);
                 }
             } else {
                 const KT *kp = keys + start;
-                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&my_h[((uint32_t)kp[e] >> shift) & mask], 1u);
+                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&my_h[ds.digit((uint32_t)kp[e])], 1u);
             }
         }
         __syncthreads();
@@ -560,7 +653,7 @@ struct RowMap {
     }
 };
 
-template <int ITEMS, int NT, bool MAP, typename KT>
+template <int ITEMS, int NT, bool MAP, typename KT, bool PLAN>
 __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict__ keys_in,
                                                            const uint32_t *__restrict__ vals_in,
                                                            uint32_t *__restrict__ keys_out,
@@ -570,12 +663,12 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
                                                            const uint32_t *__restrict__ digit_total,
                                                            int64_t stride, const int4 *__restrict__ gather_src,
                                                            int4 *__restrict__ gather_dst, RowMap rows,
-                                                           AuxPayload aux)
+                                                           AuxPayload aux, DepthPlan dp)
 {
     constexpr int kW = NT / 64;                             // wavefronts per workgroup
     constexpr int kTileN = NT * ITEMS;
     constexpr int kPerWave = kTileN / kW;
-    const uint32_t mask = (1u << nbits) - 1u;
+    const DigitSel ds = digit_sel<PLAN>(dp, shift, nbits);
     __shared__ uint32_t s_wc[kW][kRadixBins];              // running, then exclusive-over-waves counts
     __shared__ uint32_t s_lbase[kRadixBins];               // block-local digit offsets
     __shared__ uint32_t s_gbase[kRadixBins];               // global digit offsets of this block
@@ -611,12 +704,16 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
         const int local = wid * kPerWave + r * 64 + lane;
         key[r] = local < count ? (uint32_t)kin[local] : 0u;
     }
+    if (ds.rebase) {                                        // after the loads: all of them in flight at once
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) key[r] = ds.key(key[r]);
+    }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
         const bool active = local < count;
-        const uint32_t d = (key[r] >> shift) & mask;
-        const uint64_t match = digit_match(active, d, nbits);
+        const uint32_t d = (key[r] >> ds.shift) & ds.mask;
+        const uint64_t match = digit_match(active, d, ds.nbits);
         const uint32_t before = active ? s_wc[wid][d] : 0u;
         const uint32_t within = (uint32_t)__popcll(match & lt);
         lp[r] = before + within;                             // rank within the wavefront's digit run
@@ -644,7 +741,7 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
     for (int r = 0; r < ITEMS; ++r) {
         const int local = wid * kPerWave + r * 64 + lane;
         if (local < count) {
-            const uint32_t d = (key[r] >> shift) & mask;
+            const uint32_t d = (key[r] >> ds.shift) & ds.mask;
             lp[r] += s_lbase[d] + s_wc[wid][d];
             s_buf[lp[r]] = key[r];
             s_dig[lp[r]] = (uint8_t)d;
@@ -1191,6 +1288,7 @@ struct SortWorkspace {
     uint64_t *col_pairs;          // pair total of each column block
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
+    uint32_t *range;              // [lo, hi] of the visible depth keys
     size_t bytes;
 };
 
@@ -1224,6 +1322,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.col_pairs = (uint64_t *)take(sizeof(uint64_t) * nb_col);
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
+    w.range = (uint32_t *)take(2 * sizeof(uint32_t));
     w.bytes = off;
     return w;
 }
@@ -1233,12 +1332,12 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
 template <int ITEMS, int SCATTER_THREADS, typename KT>
 void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                   const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
-                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows, const AuxPayload &aux, bool top)
+                  const int4 *gather_src, int4 *gather_dst, const RowMap &rows, const AuxPayload &aux, bool top,
+                  const DepthPlan &dp)
 {
     constexpr int kTileN = kBlock * ITEMS;
     const int64_t nb = (n_max + kTileN - 1) / kTileN;
     if (nb == 0) return;
-    const uint32_t mask = (1u << bits) - 1u;
     const int64_t stride = hist_stride(nb);
     // bank-staggered counter copies where digits repeat within a wavefront:
     // the top digit of a key, and long inputs (sorted pairs, stacked views)
@@ -1246,45 +1345,57 @@ void radix_pass_t(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *
     // chip counts; else kHistGroup blocks per workgroup and 16-byte writes
     const bool copies = top || ITEMS >= 16, few = nb < 2048;
     const dim3 hg((unsigned)(few ? nb : stride / kHistGroup));
-    if (copies && few)
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
-                           mask, w.hist, stride);
-    else if (copies)
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, kHistGroup>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
-                           shift, mask, w.hist, stride);
-    else if (few)
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, 1>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev, shift,
-                           mask, w.hist, stride);
-    else
-        hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, kHistGroup>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
-                           shift, mask, w.hist, stride);
-    hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
-                       kTileN, w.digit_total);
     constexpr int kScatterItems = ITEMS * kBlock / SCATTER_THREADS;   // same partition as the histogram
-    if (rows.V)
-        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true, KT>), dim3((unsigned)nb),
-                           dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
-                           n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
-                           stride, gather_src, gather_dst, rows, aux);
+    // the depth passes with a digit plan are instantiated apart, so that the
+    // others compile exactly as without one
+    auto launch = [&](auto plan) {
+        constexpr bool P = decltype(plan)::value;
+        if (copies && few)
+            hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, 1, P>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
+                               shift, bits, w.hist, stride, dp);
+        else if (copies)
+            hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 4, kHistGroup, P>), hg, dim3(kBlock), 0, s, kin, n_max,
+                               n_dev, shift, bits, w.hist, stride, dp);
+        else if (few)
+            hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, 1, P>), hg, dim3(kBlock), 0, s, kin, n_max, n_dev,
+                               shift, bits, w.hist, stride, dp);
+        else
+            hipLaunchKernelGGL((radix_hist_kernel<ITEMS, KT, 1, kHistGroup, P>), hg, dim3(kBlock), 0, s, kin, n_max,
+                               n_dev, shift, bits, w.hist, stride, dp);
+        hipLaunchKernelGGL(radix_rowscan_kernel, dim3(kRadixBins), dim3(kBlock), 0, s, w.hist, stride, n_max, n_dev,
+                           kTileN, w.digit_total);
+        if constexpr (!P) {
+            if (rows.V) {
+                hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, true, KT, false>),
+                                   dim3((unsigned)nb), dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout, n_max, n_dev,
+                                   shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride,
+                                   gather_src, gather_dst, rows, aux, dp);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false, KT, P>), dim3((unsigned)nb),
+                           dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout, n_max, n_dev, shift, bits,
+                           (const uint32_t *)w.hist, (const uint32_t *)w.digit_total, stride, gather_src, gather_dst,
+                           rows, aux, dp);
+    };
+    if (dp.range)
+        launch(std::true_type{});
     else
-        hipLaunchKernelGGL((radix_scatter_kernel<kScatterItems, SCATTER_THREADS, false, KT>), dim3((unsigned)nb),
-                           dim3(SCATTER_THREADS), 0, s, kin, vin, kout, vout,
-                           n_max, n_dev, shift, bits, (const uint32_t *)w.hist, (const uint32_t *)w.digit_total,
-                           stride, gather_src, gather_dst, rows, aux);
+        launch(std::false_type{});
 }
 
 template <typename KT>
 void radix_pass(const KT *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout, int64_t n_max,
                 const uint32_t *n_dev, int shift, int bits, const SortWorkspace &w, hipStream_t s,
                 const int4 *gather_src = nullptr, int4 *gather_dst = nullptr, const RowMap &rows = RowMap{},
-                const AuxPayload &aux = AuxPayload{}, bool top = false)
+                const AuxPayload &aux = AuxPayload{}, bool top = false, const DepthPlan &dp = DepthPlan{})
 {
     if (n_max >= kLargeRadixFrom)
         radix_pass_t<32, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src, gather_dst, rows,
-                               aux, top);
+                               aux, top, dp);
     else
         radix_pass_t<kRadixItems, 1024>(kin, vin, kout, vout, n_max, n_dev, shift, bits, w, s, gather_src,
-                                        gather_dst, rows, aux, top);
+                                        gather_dst, rows, aux, top, dp);
 }
 
 
@@ -1361,18 +1472,24 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
 
     // 1. stable sort of all Gaussians by depth bits (positive floats order
     //    like their bit patterns; culled ones hold +inf and end up last):
-    //    four 8-bit passes, the first reading the depths and implicit ids.
-    //    The rectangles follow into depth order: packed, as a payload of
-    //    every pass (the first packs them from the input, in index order),
-    //    or else gathered by the last pass.
+    //    the range of the visible keys, then four passes over the bits in
+    //    which they differ (the digit plan above), the first reading the
+    //    depths and implicit ids.  The rectangles follow into depth order:
+    //    packed, as a payload of every pass (the first packs them from the
+    //    input, in index order), or else gathered by the last pass.
     const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
+    hipLaunchKernelGGL(depth_range_init_kernel, dim3(1), dim3(1), 0, s, w.range);
+    if (n > 0)
+        hipLaunchKernelGGL(depth_range_kernel, dim3(min(1024u, grid_for(n, 4 * kBlock))),   // 4 per CU at most
+                           dim3(kBlock), 0, s, dbits, n, w.range);
     {
         AuxPayload aux{};
         if (packed) {
             aux.out = rp[0];
             aux.pack = rc;
         }
-        radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s, nullptr, nullptr, RowMap{}, aux);
+        radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s, nullptr, nullptr, RowMap{}, aux, false,
+                   DepthPlan{w.range, 0});
     }
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
@@ -1383,7 +1500,8 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         }
         const bool gather = !packed && pass == 3;
         radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
-                   gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux, pass == 3);
+                   gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux, pass == 3,
+                   DepthPlan{w.range, pass});
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     const RectPacked rect_packed{rp[1]};

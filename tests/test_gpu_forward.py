@@ -10,6 +10,8 @@ Tolerances (written here, derived in the design notes):
     depth keys and tile rectangles identical;
   * binning (sort, ranges): bitwise.
 """
+import zlib
+
 import numpy as np
 import pytest
 import torch
@@ -166,6 +168,56 @@ def test_sort_and_ranges_parity(seed, n, tx, ty, ties, wide):
     assert np.array_equal(rg[nonempty, 0], off[:-1][nonempty])
     assert np.array_equal(rg[nonempty, 1], off[1:][nonempty])
     assert np.all(rg[~nonempty] == 0)
+
+
+def _plan_depths(case, n, rng):
+    """Visible depths whose key span (largest minus smallest bit pattern)
+    sets the depth passes' digit plan: 0, 1, 24, 25 and 31 bits."""
+    f = lambda bits: np.array(bits, np.uint32).view(np.float32)
+    if case == "equal":                          # span 0: no digit bits at all
+        return np.full(n, 2.0, np.float32)
+    if case == "one_bit":                        # span 1: one pass of one bit
+        return f(0x40000000 + rng.integers(0, 2, n))
+    if case in ("span_24", "span_25"):           # span 2^24 - 1: 6, 6, 6, 6; 2^24: 7, 6, 6, 6
+        d = f(0x3F800000 + rng.integers(0, 1 << 24, n))
+        d[::97] = f(0x3F800000)
+        d[1::97] = f(0x3F800000 + (1 << 24) - (case == "span_24"))
+        return d
+    # span 31 bits: +0 and the smallest subnormal up to the largest finite
+    d = np.exp(rng.uniform(np.log(1e-37), np.log(3e38), n)).astype(np.float32)
+    d[::101] = 0.0
+    d[1::101] = f(1)
+    d[2::101] = np.finfo(np.float32).max
+    return d
+
+
+@pytest.mark.parametrize("case,n", [("equal", 5000), ("one_bit", 20000), ("span_24", 20000), ("span_25", 20000),
+                                    ("span_31", 20000), ("span_31", 4300000), ("single_visible", 3000)])
+def test_sort_depth_plans(case, n):
+    """The depth passes sort only the bits in which the visible depth keys
+    differ: pair lists bitwise equal to the oracle's for key spans from 0 to
+    31 bits, in both radix tiers, with culled Gaussians mixed in."""
+    rng = np.random.default_rng(zlib.crc32(case.encode()) + n)
+    tx, ty = 40, 23
+    vis, _, rect = _synthetic_bins(int(rng.integers(1 << 30)), n, tx, ty, ties=True)
+    if case == "single_visible":
+        vis[:] = 0
+        vis[n // 2] = 1
+        depth = np.full(n, 5.0, np.float32)
+        rect[:] = 0
+        rect[n // 2] = (3, 4, 9, 7)
+    else:
+        depth = _plan_depths(case, n, rng)
+    depth = np.where(vis > 0, depth, np.float32(np.inf)).astype(np.float32)
+    print(f"sort depth plan {case} n={n}", flush=True)
+    W, H = 16 * tx, 16 * ty
+    cam = scenes.look_at_camera((0, 0, 0), (0, 0, 1), W, H)
+    off, ids = O.tile_lists(vis, depth, rect, W, H)
+    p = len(ids)
+    b = R.Binner(capacity=p + 9).run(cam, R.Projected(None, to_dev(depth), to_dev(rect)))
+    assert int(b.num_pairs.item()) == p and int(b.overflow.item()) == 0
+    assert np.array_equal(_sync_np(b.tile_keys)[:p].astype(np.int64), np.repeat(np.arange(tx * ty), np.diff(off)))
+    assert np.array_equal(_sync_np(b.values)[:p], ids)
 
 
 @pytest.mark.parametrize("tx,ty", [(256, 256), (256, 257)])
