@@ -516,24 +516,36 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
         const float *shi = s_sh[wid] + __lane_id() * P;
         const GaussPre G = gauss_pre(m3, ls, qt, logit);
         RawGrad acc = {};
-        for (int v = 0; v < cb.V; ++v) {
+        // view v + 1's gradient record and rectangle are loaded while view v
+        // is accumulated
+        float gn[kGradF];
+        int4 rn;
+        auto fetch = [&](int v) {
             const int64_t o = (int64_t)v * n + i;
-            float *gr = g_splats + (uint64_t)o * kGradF;
+            const float *gr = g_splats + (uint64_t)o * kGradF;
+#pragma unroll
+            for (int c = 0; c < kGradF; ++c) gn[c] = gr[c];
+            rn = rect[o];
+        };
+        fetch(0);
+        for (int v = 0; v < cb.V; ++v) {
             float gv[kGradF];
+#pragma unroll
+            for (int c = 0; c < kGradF; ++c) gv[c] = gn[c];
+            const int4 rv = rn;
+            if (v + 1 < cb.V) fetch(v + 1);
             bool nz = false;
 #pragma unroll
-            for (int c = 0; c < kGradF; ++c) {
-                gv[c] = gr[c];
-                nz = nz || gv[c] != 0.f;
-            }
+            for (int c = 0; c < kGradF; ++c) nz = nz || gv[c] != 0.f;
             if (clear && nz) {
                 // read and cleared: the record is zero for the next backward
+                float *gr = g_splats + ((uint64_t)v * n + i) * kGradF;
 #pragma unroll
                 for (int c = 0; c < kGradF; ++c) gr[c] = 0.f;
             }
             const float gc3[3] = {gv[0], gv[1], gv[2]};
             const float gr3[3] = {gv[6], gv[7], gv[8]};
-            project_bwd_accum<DEG>(cb.cam[v], m3, G, shi, rect[o], make_float2(gv[4], gv[5]), gc3, gv[3], gr3, acc,
+            project_bwd_accum<DEG>(cb.cam[v], m3, G, shi, rv, make_float2(gv[4], gv[5]), gc3, gv[3], gr3, acc,
                                    dslot);
         }
         for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
