@@ -341,7 +341,7 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbi
 // caller's shift and width.
 constexpr uint32_t kInfBits = 0x7F800000u;
 struct DepthPlan {
-    const uint32_t *range;     // [lo, hi] (device), from depth_range_kernel
+    const uint32_t *range;     // [lo, hi] (device), from the range kernels
     int pass;                  // 0..3; pass 0 rebases the keys it reads
 };
 struct DigitSel {
@@ -380,18 +380,35 @@ __device__ __forceinline__ DigitSel digit_sel(const DepthPlan &dp, int shift, in
     return d;
 }
 
-__global__ void depth_range_init_kernel(uint32_t *range)
+// [lo, hi] of the keys below +inf's bit pattern, in two steps without
+// atomics (thousands of atomics on one address would serialise): per
+// workgroup over a grid-stride loop (16-byte loads where aligned) into
+// parts[workgroup], then one workgroup over the parts.
+constexpr int kRangeParts = 1024;                          // workgroups of the first step, at most
+constexpr int64_t kPlanFrom = 1 << 20;                     // Gaussians from which the depth passes take the plan
+
+__device__ __forceinline__ void range_reduce(uint32_t &lo, uint32_t &hi, uint2 *s_part)
 {
-    range[0] = 0xFFFFFFFFu;
-    range[1] = 0u;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    }
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (__lane_id() == 0) s_part[wid] = make_uint2(lo, hi);
+    __syncthreads();
+    lo = 0xFFFFFFFFu;
+    hi = 0u;
+    for (int w = 0; w < nw; ++w) {
+        lo = min(lo, s_part[w].x);
+        hi = max(hi, s_part[w].y);
+    }
 }
 
-// [lo, hi] of the keys below +inf's bit pattern: per-thread extremes over a
-// grid-stride loop (16-byte loads where aligned), then per wavefront, one
-// atomic pair per wavefront
 __global__ __launch_bounds__(kBlock) void depth_range_kernel(const uint32_t *__restrict__ keys, int64_t n,
-                                                             uint32_t *__restrict__ range)
+                                                             uint2 *__restrict__ parts)
 {
+    __shared__ uint2 s_part[kBlock / 64];
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     auto take = [&](uint32_t k) {
         if (k < kInfBits) { lo = min(lo, k); hi = max(hi, k); }
@@ -401,21 +418,41 @@ __global__ __launch_bounds__(kBlock) void depth_range_kernel(const uint32_t *__r
     if (reinterpret_cast<uintptr_t>(keys) % 16 == 0) {
         const uint4 *k4 = reinterpret_cast<const uint4 *>(keys);
         const int64_t n4 = n / 4;
-        for (int64_t i = tid; i < n4; i += nth) {
+        int64_t i = tid;
+        for (; i + 3 * nth < n4; i += 4 * nth) {             // four loads in flight
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = k4[i + u * nth];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) { take(v[u].x); take(v[u].y); take(v[u].z); take(v[u].w); }
+        }
+        for (; i < n4; i += nth) {
             const uint4 v = k4[i];
             take(v.x); take(v.y); take(v.z); take(v.w);
         }
         head = n4 * 4;
     }
     for (int64_t i = head + tid; i < n; i += nth) take(keys[i]);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+    range_reduce(lo, hi, s_part);
+    if (threadIdx.x == 0) parts[blockIdx.x] = make_uint2(lo, hi);
+}
+
+// range = [lo, hi] over parts[0, nparts); (0xFFFFFFFF, 0) when there is no
+// visible key (or no part)
+__global__ __launch_bounds__(kRangeParts) void depth_range_final_kernel(const uint2 *__restrict__ parts,
+                                                                        int nparts, uint32_t *__restrict__ range)
+{
+    __shared__ uint2 s_part[kRangeParts / 64];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    if ((int)threadIdx.x < nparts) {
+        const uint2 p = parts[threadIdx.x];
+        lo = p.x;
+        hi = p.y;
     }
-    if (__lane_id() == 0 && lo <= hi) {
-        atomicMin(&range[0], lo);
-        atomicMax(&range[1], hi);
+    range_reduce(lo, hi, s_part);
+    if (threadIdx.x == 0) {
+        range[0] = lo;
+        range[1] = hi;
     }
 }
 
@@ -1289,6 +1326,7 @@ struct SortWorkspace {
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
     uint32_t *range;              // [lo, hi] of the visible depth keys
+    uint2 *range_parts;           // per-workgroup extremes of the range's first step
     size_t bytes;
 };
 
@@ -1323,6 +1361,7 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
     w.range = (uint32_t *)take(2 * sizeof(uint32_t));
+    w.range_parts = (uint2 *)take(kRangeParts * sizeof(uint2));
     w.bytes = off;
     return w;
 }
@@ -1478,10 +1517,15 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     //    packed, as a payload of every pass (the first packs them from the
     //    input, in index order), or else gathered by the last pass.
     const uint32_t *dbits = reinterpret_cast<const uint32_t *>(depth);
-    hipLaunchKernelGGL(depth_range_init_kernel, dim3(1), dim3(1), 0, s, w.range);
-    if (n > 0)
-        hipLaunchKernelGGL(depth_range_kernel, dim3(min(1024u, grid_for(n, 4 * kBlock))),   // 4 per CU at most
-                           dim3(kBlock), 0, s, dbits, n, w.range);
+    // the plan from 2^20 Gaussians up; below, its two extra launches cost more
+    // than the narrower digits save, and the passes take 8 bits each
+    const bool plan = n >= kPlanFrom;
+    if (plan) {
+        const int nparts = (int)min((unsigned)kRangeParts, grid_for(n, 4 * kBlock));
+        hipLaunchKernelGGL(depth_range_kernel, dim3((unsigned)nparts), dim3(kBlock), 0, s, dbits, n, w.range_parts);
+        hipLaunchKernelGGL(depth_range_final_kernel, dim3(1), dim3(kRangeParts), 0, s, (const uint2 *)w.range_parts,
+                           nparts, w.range);
+    }
     {
         AuxPayload aux{};
         if (packed) {
@@ -1489,7 +1533,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
             aux.pack = rc;
         }
         radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s, nullptr, nullptr, RowMap{}, aux, false,
-                   DepthPlan{w.range, 0});
+                   DepthPlan{plan ? w.range : nullptr, 0});
     }
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
@@ -1501,7 +1545,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         const bool gather = !packed && pass == 3;
         radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
                    gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux, pass == 3,
-                   DepthPlan{w.range, pass});
+                   DepthPlan{plan ? w.range : nullptr, pass});
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     const RectPacked rect_packed{rp[1]};

@@ -191,12 +191,14 @@ def _plan_depths(case, n, rng):
     return d
 
 
-@pytest.mark.parametrize("case,n", [("equal", 5000), ("one_bit", 20000), ("span_24", 20000), ("span_25", 20000),
-                                    ("span_31", 20000), ("span_31", 4300000), ("single_visible", 3000)])
+@pytest.mark.parametrize("case,n", [("equal", 1100000), ("one_bit", 1100000), ("span_24", 1100000),
+                                    ("span_25", 1100000), ("span_31", 1100000), ("span_31", 4300000),
+                                    ("single_visible", 1100000), ("span_25", 20000)])
 def test_sort_depth_plans(case, n):
-    """The depth passes sort only the bits in which the visible depth keys
-    differ: pair lists bitwise equal to the oracle's for key spans from 0 to
-    31 bits, in both radix tiers, with culled Gaussians mixed in."""
+    """From 2^20 Gaussians the depth passes sort only the bits in which the
+    visible depth keys differ: pair lists bitwise equal to the oracle's for
+    key spans from 0 to 31 bits, in both radix tiers, with culled Gaussians
+    mixed in (and once below 2^20, with 8-bit passes)."""
     rng = np.random.default_rng(zlib.crc32(case.encode()) + n)
     tx, ty = 40, 23
     vis, _, rect = _synthetic_bins(int(rng.integers(1 << 30)), n, tx, ty, ties=True)
