@@ -341,20 +341,22 @@ __device__ __forceinline__ uint64_t digit_match(bool active, uint32_t d, int nbi
 // caller's shift and width.
 constexpr uint32_t kInfBits = 0x7F800000u;
 struct DepthPlan {
-    const uint32_t *range;     // [lo, hi] (device), from the range kernels
+    const uint32_t *range;     // [lo, hi, visible count] (device), from the range kernels
     int pass;                  // 0..3; pass 0 rebases the keys it reads
+    bool drop;                 // pass 0 leaves the culled keys out (the later passes take the visible count)
 };
 struct DigitSel {
     int shift, nbits;
     uint32_t mask, lo, top;    // top = hi - lo: the rebased value of culled keys
-    bool rebase;
+    bool rebase, drop;
     __device__ __forceinline__ uint32_t key(uint32_t k) const { return rebase ? (k < kInfBits ? k - lo : top) : k; }
     __device__ __forceinline__ uint32_t digit(uint32_t k) const { return (key(k) >> shift) & mask; }
+    __device__ __forceinline__ bool keep(uint32_t k) const { return !drop || k < kInfBits; }   // k: as read
 };
 template <bool PLAN>
 __device__ __forceinline__ DigitSel digit_sel(const DepthPlan &dp, int shift, int nbits)
 {
-    DigitSel d{shift, nbits, nbits >= 32 ? ~0u : (1u << nbits) - 1u, 0u, 0u, false};
+    DigitSel d{shift, nbits, nbits >= 32 ? ~0u : (1u << nbits) - 1u, 0u, 0u, false, false};
     if constexpr (!PLAN) return d;
     const uint32_t lo = dp.range[0], hi = dp.range[1];
     const uint32_t span = hi >= lo ? hi - lo : 0u;         // no visible key: all rebase to 0
@@ -370,6 +372,7 @@ __device__ __forceinline__ DigitSel digit_sel(const DepthPlan &dp, int shift, in
     d.lo = hi >= lo ? lo : 0u;
     d.top = span;
     d.rebase = dp.pass == 0;
+    d.drop = dp.drop && dp.pass == 0;
     // uniform across the wavefront (scalar registers: the digit loops stay
     // uniform branches)
     d.shift = __builtin_amdgcn_readfirstlane(d.shift);
@@ -387,31 +390,34 @@ __device__ __forceinline__ DigitSel digit_sel(const DepthPlan &dp, int shift, in
 constexpr int kRangeParts = 1024;                          // workgroups of the first step, at most
 constexpr int64_t kPlanFrom = 1 << 20;                     // Gaussians from which the depth passes take the plan
 
-__device__ __forceinline__ void range_reduce(uint32_t &lo, uint32_t &hi, uint2 *s_part)
+__device__ __forceinline__ void range_reduce(uint32_t &lo, uint32_t &hi, uint32_t &cnt, uint4 *s_part)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, off, 64));
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, off, 64));
+        cnt += (uint32_t)__shfl_xor((int)cnt, off, 64);
     }
     const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (__lane_id() == 0) s_part[wid] = make_uint2(lo, hi);
+    if (__lane_id() == 0) s_part[wid] = make_uint4(lo, hi, cnt, 0u);
     __syncthreads();
     lo = 0xFFFFFFFFu;
     hi = 0u;
+    cnt = 0u;
     for (int w = 0; w < nw; ++w) {
         lo = min(lo, s_part[w].x);
         hi = max(hi, s_part[w].y);
+        cnt += s_part[w].z;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void depth_range_kernel(const uint32_t *__restrict__ keys, int64_t n,
-                                                             uint2 *__restrict__ parts)
+                                                             uint4 *__restrict__ parts)
 {
-    __shared__ uint2 s_part[kBlock / 64];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    __shared__ uint4 s_part[kBlock / 64];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, cnt = 0u;
     auto take = [&](uint32_t k) {
-        if (k < kInfBits) { lo = min(lo, k); hi = max(hi, k); }
+        if (k < kInfBits) { lo = min(lo, k); hi = max(hi, k); ++cnt; }
     };
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x, nth = (int64_t)gridDim.x * kBlock;
     int64_t head = 0;
@@ -433,26 +439,28 @@ __global__ __launch_bounds__(kBlock) void depth_range_kernel(const uint32_t *__r
         head = n4 * 4;
     }
     for (int64_t i = head + tid; i < n; i += nth) take(keys[i]);
-    range_reduce(lo, hi, s_part);
-    if (threadIdx.x == 0) parts[blockIdx.x] = make_uint2(lo, hi);
+    range_reduce(lo, hi, cnt, s_part);
+    if (threadIdx.x == 0) parts[blockIdx.x] = make_uint4(lo, hi, cnt, 0u);
 }
 
-// range = [lo, hi] over parts[0, nparts); (0xFFFFFFFF, 0) when there is no
-// visible key (or no part)
-__global__ __launch_bounds__(kRangeParts) void depth_range_final_kernel(const uint2 *__restrict__ parts,
+// range = [lo, hi, visible count] over parts[0, nparts); lo, hi =
+// (0xFFFFFFFF, 0) when there is no visible key (or no part)
+__global__ __launch_bounds__(kRangeParts) void depth_range_final_kernel(const uint4 *__restrict__ parts,
                                                                         int nparts, uint32_t *__restrict__ range)
 {
-    __shared__ uint2 s_part[kRangeParts / 64];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    __shared__ uint4 s_part[kRangeParts / 64];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u, cnt = 0u;
     if ((int)threadIdx.x < nparts) {
-        const uint2 p = parts[threadIdx.x];
+        const uint4 p = parts[threadIdx.x];
         lo = p.x;
         hi = p.y;
+        cnt = p.z;
     }
-    range_reduce(lo, hi, s_part);
+    range_reduce(lo, hi, cnt, s_part);
     if (threadIdx.x == 0) {
         range[0] = lo;
         range[1] = hi;
+        range[2] = cnt;
     }
 }
 
@@ -528,11 +536,17 @@ __global__ __launch_bounds__(kBlock) void radix_hist_kernel(const KT *__restrict
 #pragma unroll
                 for (int r = 0; r < kV; ++r) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) atomicAdd(&my_h[ds.digit(Key4<KT>::at(cur[r], e))], 1u);
+                    for (int e = 0; e < 4; ++e) {
+                        const uint32_t k = Key4<KT>::at(cur[r], e);
+                        if (!PLAN || ds.keep(k)) atomicAdd(&my_h[ds.digit(k)], 1u);
+                    }
                 }
             } else {
                 const KT *kp = keys + start;
-                for (int e = threadIdx.x; e < cnt; e += kBlock) atomicAdd(&my_h[ds.digit((uint32_t)kp[e])], 1u);
+                for (int e = threadIdx.x; e < cnt; e += kBlock) {
+                    const uint32_t k = (uint32_t)kp[e];
+                    if (!PLAN || ds.keep(k)) atomicAdd(&my_h[ds.digit(k)], 1u);
+                }
             }
         }
         __syncthreads();
@@ -741,14 +755,27 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
         const int local = wid * kPerWave + r * 64 + lane;
         key[r] = local < count ? (uint32_t)kin[local] : 0u;
     }
+    // item r takes part: in the block, and (first planned pass with a drop)
+    // not culled; the other instantiations test the block bound alone
+    uint32_t livem = 0u;
+    if constexpr (PLAN) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const int local = wid * kPerWave + r * 64 + lane;
+            livem |= (local < count && ds.keep(key[r]) ? 1u : 0u) << r;
+        }
+    }
+    auto live = [&](int r) -> bool {
+        if constexpr (PLAN) return (livem >> r) & 1u;
+        else return wid * kPerWave + r * 64 + lane < count;
+    };
     if (ds.rebase) {                                        // after the loads: all of them in flight at once
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) key[r] = ds.key(key[r]);
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int local = wid * kPerWave + r * 64 + lane;
-        const bool active = local < count;
+        const bool active = live(r);
         const uint32_t d = (key[r] >> ds.shift) & ds.mask;
         const uint64_t match = digit_match(active, d, ds.nbits);
         const uint32_t before = active ? s_wc[wid][d] : 0u;
@@ -759,6 +786,7 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
     }
     __syncthreads();
     // digit t: prefix over wavefronts, block total, exclusive scan over digits
+    uint32_t ntot;
     {
         uint32_t run = 0;
         if (t < kRadixBins) {
@@ -769,15 +797,15 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
                 run += c;
             }
         }
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan<uint32_t, kW>(run, tot, s_tot);
+        const uint32_t ex = block_exclusive_scan<uint32_t, kW>(run, ntot, s_tot);
         if (t < kRadixBins) s_lbase[t] = ex;
     }
+    // elements staged in digit order: all of the block's, or its kept ones
+    const int placed = PLAN ? (int)ntot : count;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int local = wid * kPerWave + r * 64 + lane;
-        if (local < count) {
+        if (live(r)) {
             const uint32_t d = (key[r] >> ds.shift) & ds.mask;
             lp[r] += s_lbase[d] + s_wc[wid][d];
             s_buf[lp[r]] = key[r];
@@ -796,7 +824,7 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int i = threadIdx.x + r * NT;
-        if (i < count) {
+        if (i < placed) {
             const uint32_t d = s_dig[i];
             const uint32_t k = s_buf[i];
             keys_out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = MAP ? rows.tile_of(k, s_map) : k;
@@ -805,14 +833,13 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const int local = wid * kPerWave + r * 64 + lane;
-        if (local < count) s_buf[lp[r]] = val[r];
+        if (live(r)) s_buf[lp[r]] = val[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const int i = threadIdx.x + r * NT;
-        if (i < count) {
+        if (i < placed) {
             const uint32_t d = s_dig[i];
             const uint32_t pos = s_gbase[d] + (uint32_t)i - s_lbase[d];
             const uint32_t v = s_buf[i];
@@ -832,14 +859,13 @@ __global__ __launch_bounds__(NT) void radix_scatter_kernel(const KT *__restrict_
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
-            const int local = wid * kPerWave + r * 64 + lane;
-            if (local < count) s_buf[lp[r]] = x[r];
+            if (live(r)) s_buf[lp[r]] = x[r];
         }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
             const int i = threadIdx.x + r * NT;
-            if (i < count) {
+            if (i < placed) {
                 const uint32_t d = s_dig[i];
                 aux.out[s_gbase[d] + (uint32_t)i - s_lbase[d]] = s_buf[i];
             }
@@ -928,11 +954,12 @@ struct SplatGeom {
 // workgroup counts kHistGroup consecutive blocks (one 16-byte write per
 // column) and writes their pair total to block_pairs[workgroup].
 template <typename RIN, bool EXACT>
-__global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_t n, int ncols,
-                                                          uint32_t *__restrict__ hist, int64_t stride,
+__global__ __launch_bounds__(kBlock) void col_hist_kernel(const RIN rect, int64_t n_max, const uint32_t *n_dev,
+                                                          int ncols, uint32_t *__restrict__ hist, int64_t stride,
                                                           uint64_t *__restrict__ block_pairs,
                                                           const uint32_t *__restrict__ order, SplatGeom geom)
 {
+    const int64_t n = live_count(n_max, n_dev);              // Gaussians in the depth order
     __shared__ uint32_t s_d[kMaxCols + 1];
     __shared__ uint32_t s_warp[kWaves];
     __shared__ uint64_t s_pairs[kHistGroup];
@@ -1049,7 +1076,8 @@ __global__ __launch_bounds__(kBlock) void col_rowscan_kernel(uint32_t *__restric
 // written.
 template <int ITEMS, typename KT, typename RIN, bool EXACT>
 __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
-    const uint32_t *__restrict__ order, const RIN rect, uint64_t cap, TileGrids tg, int64_t n,
+    const uint32_t *__restrict__ order, const RIN rect, uint64_t cap, TileGrids tg, int64_t n_max,
+    const uint32_t *n_dev,
     const uint32_t *__restrict__ hist_scan, const uint32_t *__restrict__ col_total, int64_t stride, int ncols,
     int nbits, KT *__restrict__ keys_out, uint32_t *__restrict__ vals_out, SplatGeom geom)
 {
@@ -1075,6 +1103,7 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
     __shared__ Splat s_sp[EXACT ? NT : 1];
     __shared__ int s_y0[EXACT ? NT : 1];
     constexpr uint32_t kNone = 0xFFFFFFFFu;                // key of a candidate the ellipse misses
+    const int64_t n = live_count(n_max, n_dev);              // Gaussians in the depth order
     const int64_t first = (int64_t)blockIdx.x * NT;
     if (first >= n) return;
     const int cnt = (int)min((int64_t)NT, n - first);
@@ -1325,8 +1354,8 @@ struct SortWorkspace {
     uint64_t *col_pairs;          // pair total of each column block
     uint32_t *n_eff;              // min(P, cap)
     uint64_t *p_total;            // P
-    uint32_t *range;              // [lo, hi] of the visible depth keys
-    uint2 *range_parts;           // per-workgroup extremes of the range's first step
+    uint32_t *range;              // [lo, hi, count] of the visible depth keys
+    uint4 *range_parts;           // per-workgroup extremes and counts of the range's first step
     size_t bytes;
 };
 
@@ -1360,8 +1389,8 @@ SortWorkspace plan_workspace(char *base, int64_t n, int64_t cap)
     w.col_pairs = (uint64_t *)take(sizeof(uint64_t) * nb_col);
     w.n_eff = (uint32_t *)take(sizeof(uint32_t));
     w.p_total = (uint64_t *)take(sizeof(uint64_t));
-    w.range = (uint32_t *)take(2 * sizeof(uint32_t));
-    w.range_parts = (uint2 *)take(kRangeParts * sizeof(uint2));
+    w.range = (uint32_t *)take(4 * sizeof(uint32_t));
+    w.range_parts = (uint4 *)take(kRangeParts * sizeof(uint4));
     w.bytes = off;
     return w;
 }
@@ -1523,9 +1552,14 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
     if (plan) {
         const int nparts = (int)min((unsigned)kRangeParts, grid_for(n, 4 * kBlock));
         hipLaunchKernelGGL(depth_range_kernel, dim3((unsigned)nparts), dim3(kBlock), 0, s, dbits, n, w.range_parts);
-        hipLaunchKernelGGL(depth_range_final_kernel, dim3(1), dim3(kRangeParts), 0, s, (const uint2 *)w.range_parts,
+        hipLaunchKernelGGL(depth_range_final_kernel, dim3(1), dim3(kRangeParts), 0, s, (const uint4 *)w.range_parts,
                            nparts, w.range);
     }
+    // on the column path the planned first pass also leaves the culled
+    // Gaussians out: the later passes and the column pass take the visible
+    // count (culled ones have no tiles, and nothing else reads their place)
+    const bool drop = plan && by_column;
+    const uint32_t *n_vis = drop ? w.range + 2 : nullptr;
     {
         AuxPayload aux{};
         if (packed) {
@@ -1533,7 +1567,7 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
             aux.pack = rc;
         }
         radix_pass(dbits, nullptr, w.dk[0], w.dv[0], n, nullptr, 0, 8, w, s, nullptr, nullptr, RowMap{}, aux, false,
-                   DepthPlan{plan ? w.range : nullptr, 0});
+                   DepthPlan{plan ? w.range : nullptr, 0, drop});
     }
     for (int pass = 1; pass < 4; ++pass) {
         const int a = (pass - 1) & 1;
@@ -1543,9 +1577,9 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
             aux.out = rp[a ^ 1];
         }
         const bool gather = !packed && pass == 3;
-        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, nullptr, 8 * pass, 8, w, s,
+        radix_pass(w.dk[a], w.dv[a], w.dk[a ^ 1], w.dv[a ^ 1], n, n_vis, 8 * pass, 8, w, s,
                    gather ? rc : nullptr, gather ? w.rect_sorted : nullptr, RowMap{}, aux, pass == 3,
-                   DepthPlan{plan ? w.range : nullptr, pass});
+                   DepthPlan{plan ? w.range : nullptr, pass, false});
     }
     const uint32_t *order = w.dv[1];          // passes 0..3 leave the result in buffer 1
     const RectPacked rect_packed{rp[1]};
@@ -1570,16 +1604,16 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         while ((1 << cbits) < ncols) ++cbits;
         const dim3 hgrid((unsigned)(stride / kHistGroup));
         if (n > 0 && packed && exact)
-            hipLaunchKernelGGL((col_hist_kernel<RectPacked, true>), hgrid, dim3(kBlock), 0, s, rect_packed, n, ncols,
+            hipLaunchKernelGGL((col_hist_kernel<RectPacked, true>), hgrid, dim3(kBlock), 0, s, rect_packed, n, n_vis, ncols,
                                w.hist, stride, w.col_pairs, order, geom);
         else if (n > 0 && packed)
-            hipLaunchKernelGGL((col_hist_kernel<RectPacked, false>), hgrid, dim3(kBlock), 0, s, rect_packed, n, ncols,
+            hipLaunchKernelGGL((col_hist_kernel<RectPacked, false>), hgrid, dim3(kBlock), 0, s, rect_packed, n, n_vis, ncols,
                                w.hist, stride, w.col_pairs, order, geom);
         else if (n > 0 && exact)
-            hipLaunchKernelGGL((col_hist_kernel<RectInt4, true>), hgrid, dim3(kBlock), 0, s, rect_int4, n, ncols,
+            hipLaunchKernelGGL((col_hist_kernel<RectInt4, true>), hgrid, dim3(kBlock), 0, s, rect_int4, n, n_vis, ncols,
                                w.hist, stride, w.col_pairs, order, geom);
         else if (n > 0)
-            hipLaunchKernelGGL((col_hist_kernel<RectInt4, false>), hgrid, dim3(kBlock), 0, s, rect_int4, n, ncols,
+            hipLaunchKernelGGL((col_hist_kernel<RectInt4, false>), hgrid, dim3(kBlock), 0, s, rect_int4, n, n_vis, ncols,
                                w.hist, stride, w.col_pairs, order, geom);
         const int64_t nhg = n > 0 ? stride / kHistGroup : 0;      // column-histogram workgroups
         const PairTotal pt{w.col_pairs, nhg, (uint64_t)capacity_pairs, w.p_total, num_pairs, overflow, w.n_eff};
@@ -1591,22 +1625,22 @@ extern "C" lgs_status lgs_sort_batch(int32_t num_views, const int32_t *tiles_x, 
         uint16_t *k16 = reinterpret_cast<uint16_t *>(k0);
         if (n > 0 && key16 && exact)                          // 16-bit keys imply packed rectangles
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked, true>), sgrid, sblk, 0, s, order,
-                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k16, v0, geom);
+                               rect_packed, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k16, v0, geom);
         else if (n > 0 && key16)
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint16_t, RectPacked, false>), sgrid, sblk, 0, s, order,
-                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k16, v0, geom);
+                               rect_packed, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k16, v0, geom);
         else if (n > 0 && packed && exact)
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked, true>), sgrid, sblk, 0, s, order,
-                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
+                               rect_packed, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k0, v0, geom);
         else if (n > 0 && packed)
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectPacked, false>), sgrid, sblk, 0, s, order,
-                               rect_packed, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
+                               rect_packed, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k0, v0, geom);
         else if (n > 0 && exact)
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4, true>), sgrid, sblk, 0, s, order,
-                               rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
+                               rect_int4, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k0, v0, geom);
         else if (n > 0)
             hipLaunchKernelGGL((col_scatter_kernel<kColItems, uint32_t, RectInt4, false>), sgrid, sblk, 0, s, order,
-                               rect_int4, cp, tg, n, hs, ct, stride, ncols, cbits, k0, v0, geom);
+                               rect_int4, cp, tg, n, n_vis, hs, ct, stride, ncols, cbits, k0, v0, geom);
     } else {
         // 3. pair counts in depth order, their exclusive scan (total P,
         //    overflow) and duplication in depth order
