@@ -445,7 +445,7 @@ def forward_workload(label, sc, cam, args, torch, oracle=None, ladder=False, ste
     steps = steps or max(10, args.steps)
     log(f"{label}: forward workload")
     params = tensors(sc, torch)
-    vb = ViewBatch([cam], sc.n, sc.sh_degree)
+    vb = ViewBatch([cam], sc.n, sc.sh_degree, record_used=False)     # forward only: no backward follows
     px = cam.width * cam.height
     local = tune_all(vb, params, args, "local")
     plain2 = tune_all(vb, params, args, "plain", tol=2e-4)
@@ -549,7 +549,9 @@ def train_workload(label, sc, cams, args, torch, target_seed, steps=None, fwd_to
             res["tuned"][name + "_backward"] = bt["best"]
         ent = {}
         if fwd_too:
+            vb.configure(record_used=False)                       # forward only: no backward follows
             g = timed_graph(lambda: vb.forward(params), steps, args.warmup, torch)
+            vb.configure(record_used=True)
             ent["fwd"] = {"graph": g, "mpix_s": mpix(px, g["median_ms"])}
         g = timed_graph(lambda: vb.train_step(params, target), steps, args.warmup, torch)
         ent["fwd_bwd"] = {"graph": g, "mpix_s": mpix(px, g["median_ms"])}

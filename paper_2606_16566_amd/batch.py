@@ -39,11 +39,15 @@ class ViewBatch:
                    workgroups per compute unit taking tiles from a queue
     exact_tiles    exact tile assignment in the sort (only the tiles a splat's
                    alpha >= 1/255 ellipse meets), else whole rectangles
+    record_used    the LOCAL forward records which list entries each
+                   sub-tile blended, for the backward to replay exactly those
+                   (off for forward-only use: saves a compare per step)
     """
 
     def __init__(self, cams, n: int, sh_degree: int, variant="local_q8", persistent: bool = False,
                  blocks_per_cu: int = 0, lpt: bool = False, capacity: int = 0, device="cuda", bwd_lpt: bool = True,
-                 bwd_persistent: bool = False, bwd_blocks_per_cu: int = 0, exact_tiles: bool = False):
+                 bwd_persistent: bool = False, bwd_blocks_per_cu: int = 0, exact_tiles: bool = False,
+                 record_used: bool = True):
         cams = list(cams)
         if not 1 <= len(cams) <= L.MAX_VIEWS:
             raise ValueError(f"a batch holds 1..{L.MAX_VIEWS} cameras, got {len(cams)}")
@@ -56,6 +60,7 @@ class ViewBatch:
         self.persistent = bool(persistent)
         self.blocks_per_cu = int(blocks_per_cu)
         self.lpt = bool(lpt)
+        self.record_used = bool(record_used)
         self.dev = torch.device(device)
         self.cam_arr = L.camera_array(cams)
         self.tiles_x = (C.c_int32 * V)(*[c.tiles_x for c in cams])
@@ -158,11 +163,13 @@ class ViewBatch:
         self.render(stats)
 
     def configure(self, variant=None, persistent=None, blocks_per_cu=None, lpt=None, bwd_lpt=None,
-                  bwd_persistent=None, bwd_blocks_per_cu=None, exact_tiles=None):
+                  bwd_persistent=None, bwd_blocks_per_cu=None, exact_tiles=None, record_used=None):
         """Change launch settings (e.g. from the autotuner); buffers are kept
         (a change of exact_tiles changes the pair count: re-fit)."""
         if exact_tiles is not None:
             self.exact_tiles = bool(exact_tiles)
+        if record_used is not None:
+            self.record_used = bool(record_used)
         if variant is not None:
             self.variant = variant_code(variant)
             self.used_valid = False            # recorded for another sub-tile shape
@@ -224,13 +231,13 @@ class ViewBatch:
         """Enqueue the render launch itself."""
         lb, s = L.lib(), _stream()
         order = _p(self.order) if self.lpt else None
-        local = (self.variant & 0xF) == L.RENDER_LOCAL
+        rec = (self.variant & 0xF) == L.RENDER_LOCAL and self.record_used
         L.check(lb.lgs_render_batch(self.variant, self.cam_arr, self.V, _p(self.ranges), _p(self.vals),
                                     _p(self.splats), _p(self.out_rgb), _p(self.out_T), _p(self.out_nc), _p(stats),
                                     _p(self.queue) if self.persistent else None, order, self.blocks_per_cu,
-                                    _p(self.used) if local else None, self.used.numel(), s),
+                                    _p(self.used) if rec else None, self.used.numel(), s),
                 "lgs_render_batch")
-        self.used_valid = local
+        self.used_valid = rec
 
     def l1(self, target_packed: torch.Tensor):
         """Enqueue L = mean |images - target| (loss -> self.loss) and its

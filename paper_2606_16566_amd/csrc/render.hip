@@ -169,8 +169,10 @@ __device__ __forceinline__ ChunkEntry load_entry(const RenderArgs &a, uint32_t i
 }
 
 // One 16x4 strip of one tile, processed by one wavefront with its own LDS
-// slots (no workgroup barrier).
-template <bool UNIFORM, typename R, bool STATS, int VP>
+// slots (no workgroup barrier).  MASKS: record the used-entry masks (a
+// forward that a backward follows); a forward without them saves the per-step
+// compare and its scalar bookkeeping.
+template <bool UNIFORM, typename R, bool STATS, int VP, bool MASKS>
 __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileCtx<R> &tc, Hoisted<R> *s_e,
                                              float4 *s_c, WaveStats &st)
 {
@@ -270,8 +272,10 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
                 // lanes that blended this Gaussian: exactly those whose last
                 // contributor is now this list position (one compare, mask in
                 // scalar registers)
-                if (__builtin_amdgcn_uicmp((uint32_t)last, (uint32_t)__float_as_int(f.w), 32) != 0ull)
-                    used |= 1ull << k;
+                if constexpr (MASKS) {
+                    if (__builtin_amdgcn_uicmp((uint32_t)last, (uint32_t)__float_as_int(f.w), 32) != 0ull)
+                        used |= 1ull << k;
+                }
                 if (STATS && k < cnt) st.eval++;
                 }
                 if (__builtin_amdgcn_ballot_w64(live) == 0ull) {
@@ -307,7 +311,7 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
             }
             wave_live = __ballot(live) != 0ull;
         }
-        if (UNIFORM && args.used != nullptr) {
+        if constexpr (UNIFORM && MASKS) {
             // record, by list position, the chunk's entries that some lane
             // of this sub-tile blended (the entries its backward replays)
             const uint64_t pos_used = __ballot(hit && ((used >> __popcll(bits & lt)) & 1ull));
@@ -332,8 +336,10 @@ __device__ __forceinline__ void render_strip(const RenderArgs &args, const TileC
 // line): counter x hands out the four strips of queue positions x, x + 8,
 // x + 16, ..., which spreads the atomics over eight addresses and keeps the
 // strips of one tile within one XCD's L2.
-template <bool UNIFORM, typename R, bool STATS, bool Q8, int VP>
-__global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
+// (at least four wavefronts per SIMD: the allocator otherwise lets a variant
+// grow a few registers past 128 and lose a quarter of its occupancy)
+template <bool UNIFORM, typename R, bool STATS, bool Q8, int VP, bool MASKS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void render_wave_kernel(RenderArgs args)
 {
     __shared__ Hoisted<R> s_e[kBlock / 64][64];
     __shared__ float4 s_c[kBlock / 64][64];        // colour, list position in .w
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
     if (args.queue == nullptr) {
         const TileCtx<R> tc(args, args.order ? (int)args.order[blockIdx.x] : xcd_tile(blockIdx.x, args.num_tiles),
                             wid, Q8);
-        render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
+        render_strip<UNIFORM, R, STATS, VP, MASKS>(args, tc, s_e[wid], s_c[wid], st);
     } else {
         const uint32_t units = 4u * (uint32_t)args.num_tiles;
         const uint32_t x = blockIdx.x & (kQueues - 1);
@@ -356,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
             const uint32_t u = (uint32_t)u64;
             const int tile = args.order ? (int)args.order[u >> 2] : (int)(u >> 2);
             const TileCtx<R> tc(args, tile, (int)(u & 3u), Q8);
-            render_strip<UNIFORM, R, STATS, VP>(args, tc, s_e[wid], s_c[wid], st);
+            render_strip<UNIFORM, R, STATS, VP, MASKS>(args, tc, s_e[wid], s_c[wid], st);
         }
     }
     if (STATS) flush_stats<true>(args, st.seen, st.eval, st.staged);
@@ -365,8 +371,13 @@ __global__ __launch_bounds__(kBlock) void render_wave_kernel(RenderArgs args)
 template <bool UNIFORM, typename R, bool Q8, int VP>
 void launch_wave(bool stats, dim3 g, dim3 block, hipStream_t s, const RenderArgs &a)
 {
-    if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8, VP>), g, block, 0, s, a);
-    else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8, VP>), g, block, 0, s, a);
+    if (UNIFORM && a.used != nullptr) {
+        if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8, VP, UNIFORM>), g, block, 0, s, a);
+        else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8, VP, UNIFORM>), g, block, 0, s, a);
+    } else {
+        if (stats) hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, true, Q8, VP, false>), g, block, 0, s, a);
+        else hipLaunchKernelGGL((render_wave_kernel<UNIFORM, R, false, Q8, VP, false>), g, block, 0, s, a);
+    }
 }
 
 template <int V, typename R>

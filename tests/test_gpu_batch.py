@@ -303,6 +303,16 @@ def test_backward_replays_exactly_the_used_entries(variant, persistent):
           flush=True)
     assert sm[0] == sm[1] == sc_[1] and sm[2] == sc_[2] and sc_[0] >= sc_[1]
     _close_scaled(gm, gc, "gradient records", tol=1e-5)
+    # a forward that records no masks (the kernel without the per-step
+    # compare) renders the same images, and the backward then culls itself
+    img = vb.out_rgb.clone(), vb.out_T.clone(), vb.out_nc.clone()
+    vb.configure(record_used=False)
+    vb.forward(params)
+    assert not vb.used_valid
+    assert torch.equal(img[0], vb.out_rgb) and torch.equal(img[1], vb.out_T) and torch.equal(img[2], vb.out_nc)
+    vb.backward_render()
+    torch.cuda.synchronize()
+    _close_scaled(vb.g_splats.cpu().numpy().astype(np.float64), gm, "gradient records without masks", tol=1e-5)
 
 
 def test_captured_step_grows_and_recaptures():
