@@ -258,6 +258,55 @@ __device__ __forceinline__ void stage_sh(const float *__restrict__ sh, int64_t g
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Splat records of a wavefront's 64 Gaussians, stored by quads of lanes:
+// the four lanes of a quad transpose their records' 16-byte quarters among
+// themselves (two butterfly stages over lane ^ 1 and lane ^ 2), after which
+// store j writes record j of every quad whole, one quarter per lane (16 whole
+// 64-byte records per store instruction instead of one quarter of 64
+// records).  All 64 lanes take part (a record of zeros for lanes past the
+// end, which store nothing).
+template <int CTRL>
+__device__ __forceinline__ float quad_read(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// one butterfly exchange over the lane pair (p, p ^ m): of the pair of
+// quarters (a, b), a lane whose bit m is clear keeps a and receives the
+// partner's a into b; the other keeps b and receives the partner's b into a
+template <int CTRL>
+__device__ __forceinline__ void quad_swap(float &a, float &b, bool hi)
+{
+    const float r = quad_read<CTRL>(hi ? a : b);
+    a = hi ? r : a;
+    b = hi ? b : r;
+}
+
+__device__ __forceinline__ void store_splats_quad(float *s, uint64_t e, uint32_t quad_in, float4 co, float4 mr,
+                                                  float bl)
+{
+    const int p = __lane_id() & 3;
+    float q[4][4] = {{co.x, co.y, co.z, co.w}, {mr.x, mr.y, mr.z, mr.w}, {bl, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    // stage 1 over lane ^ 1: quarters (0, 1) and (2, 3) (of those only the
+    // first components are nonzero)
+    const bool h1 = (p & 1) != 0, h2 = (p & 2) != 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) quad_swap<0xB1>(q[0][c], q[1][c], h1);    // quad_perm [1,0,3,2]
+    quad_swap<0xB1>(q[2][0], q[3][0], h1);
+    // stage 2 over lane ^ 2: quarters (0, 2) and (1, 3)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        quad_swap<0x4E>(q[0][c], q[2][c], h2);                            // quad_perm [2,3,0,1]
+        quad_swap<0x4E>(q[1][c], q[3][c], h2);
+    }
+    // lane p now holds quarter p of the quad's records 0..3 (quad_in: bit j
+    // set if the quad's lane j has a Gaussian)
+    float4 *base = splat_rec(s, e - (uint64_t)p);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if ((quad_in >> j) & 1u) base[j * kSplatV + p] = make_float4(q[j][0], q[j][1], q[j][2], q[j][3]);
+}
+
 // cameras of a view batch, passed by value as a kernel argument
 struct CamBatch {
     Cam cam[kMaxViews];
@@ -281,14 +330,18 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
     if (g0 >= n) return;                                   // whole wavefront past the end
     stage_sh<3 * K>(sh, g0, (int)min((int64_t)64, n - g0), s_sh[wid]);
-    const int64_t i = g0 + __lane_id();
-    if (i >= n) return;
+    // every lane of the wavefront stays to the end (the records are stored
+    // by quads of lanes); a lane past the end computes on its wavefront's
+    // first Gaussian and stores nothing
+    const bool in = g0 + __lane_id() < n;
+    const int64_t i = in ? g0 + __lane_id() : g0;
+    const uint32_t quad_in = (uint32_t)(__ballot(in) >> (__lane_id() & ~3u)) & 0xFu;
     const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
     const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
     const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
     const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
     const float logit = logits[i];
-    const float *shi = s_sh[wid] + __lane_id() * sh_stride(3 * K);
+    const float *shi = s_sh[wid] + (in ? __lane_id() : 0) * sh_stride(3 * K);
     const bool sh_ok = all_finite(shi, 3 * K);
     const GaussPre G = gauss_pre(m3, ls, qt, logit);
     for (int v = 0; v < cb.V; ++v) {
@@ -297,26 +350,30 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
         Proj P;
         int4 r = make_int4(0, 0, 0, 0);
         const bool vis = sh_ok && project_geometry(cam, m3, G, P) && footprint(cam, P, r);
-        if (!vis) {
-            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-            store_splat(splats, (uint64_t)o, z, z, 0.f);
-            depth[o] = INFINITY;
-            rect[o] = make_int4(0, 0, 0, 0);
-            continue;
-        }
-        double Y[K];
-        sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
-        double col[3] = {0.5, 0.5, 0.5};
+        // culled: an all-zero record, depth +inf and an empty rectangle
+        float4 co = make_float4(0.f, 0.f, 0.f, 0.f), mr = co;
+        float bl = 0.f, dz = INFINITY;
+        if (vis) {
+            double Y[K];
+            sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
+            double col[3] = {0.5, 0.5, 0.5};
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+                for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+            }
+            co = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
+            mr = make_float4((float)P.mx, (float)P.my, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0));
+            bl = (float)fmax(col[2], 0.0);
+            dz = (float)P.t[2];
+        } else {
+            r = make_int4(0, 0, 0, 0);
         }
-        store_splat(splats, (uint64_t)o, make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o),
-                    make_float4((float)P.mx, (float)P.my, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0)),
-                    (float)fmax(col[2], 0.0));
-        depth[o] = (float)P.t[2];
-        rect[o] = r;
+        store_splats_quad(splats, (uint64_t)o, quad_in, co, mr, bl);
+        if (in) {
+            depth[o] = dz;
+            rect[o] = r;
+        }
     }
 }
 
