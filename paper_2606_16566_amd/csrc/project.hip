@@ -258,13 +258,15 @@ __device__ __forceinline__ void stage_sh(const float *__restrict__ sh, int64_t g
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Splat records of a wavefront's 64 Gaussians, stored by quads of lanes:
+// Splat records of a wavefront's 64 Gaussians, stored by groups of eight
+// lanes so that every store instruction writes whole 128-byte lines.  First
 // the four lanes of a quad transpose their records' 16-byte quarters among
-// themselves (two butterfly stages over lane ^ 1 and lane ^ 2), after which
-// store j writes record j of every quad whole, one quarter per lane (16 whole
-// 64-byte records per store instruction instead of one quarter of 64
-// records).  All 64 lanes take part (a record of zeros for lanes past the
-// end, which store nothing).
+// themselves (two butterfly stages over lane ^ 1 and lane ^ 2): lane p of quad
+// b then holds quarter p of records 4b .. 4b + 3.  Then the two quads of a
+// group exchange two quarters (lane ^ 4), after which store s writes records
+// 2s and 2s + 1 of every group, lanes 0-3 the one and lanes 4-7 the other.
+// All 64 lanes take part (a record of zeros for lanes past the end, which
+// store nothing).
 template <int CTRL>
 __device__ __forceinline__ float quad_read(float v)
 {
@@ -282,14 +284,20 @@ __device__ __forceinline__ void quad_swap(float &a, float &b, bool hi)
     b = hi ? b : r;
 }
 
-__device__ __forceinline__ void store_splats_quad(float *s, uint64_t e, uint32_t quad_in, float4 co, float4 mr,
-                                                  float bl)
+// the value of lane ^ 4 (within each group of 32 lanes: swizzle, xor mask 4)
+__device__ __forceinline__ float xor4_read(float v)
 {
-    const int p = __lane_id() & 3;
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (4 << 10)));
+}
+
+__device__ __forceinline__ void store_splats_oct(float *s, uint64_t e, uint32_t oct_in, float4 co, float4 mr,
+                                                 float bl)
+{
+    const int l8 = __lane_id() & 7, p = l8 & 3;
     float q[4][4] = {{co.x, co.y, co.z, co.w}, {mr.x, mr.y, mr.z, mr.w}, {bl, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-    // stage 1 over lane ^ 1: quarters (0, 1) and (2, 3) (of those only the
-    // first components are nonzero)
-    const bool h1 = (p & 1) != 0, h2 = (p & 2) != 0;
+    // quad transpose, stage 1 over lane ^ 1: quarters (0, 1) and (2, 3) (of
+    // those only the first components are nonzero)
+    const bool h1 = (p & 1) != 0, h2 = (p & 2) != 0, c1 = l8 >= 4;
 #pragma unroll
     for (int c = 0; c < 4; ++c) quad_swap<0xB1>(q[0][c], q[1][c], h1);    // quad_perm [1,0,3,2]
     quad_swap<0xB1>(q[2][0], q[3][0], h1);
@@ -299,12 +307,27 @@ __device__ __forceinline__ void store_splats_quad(float *s, uint64_t e, uint32_t
         quad_swap<0x4E>(q[0][c], q[2][c], h2);                            // quad_perm [2,3,0,1]
         quad_swap<0x4E>(q[1][c], q[3][c], h2);
     }
-    // lane p now holds quarter p of the quad's records 0..3 (quad_in: bit j
-    // set if the quad's lane j has a Gaussian)
-    float4 *base = splat_rec(s, e - (uint64_t)p);
+    // lane p of quad b now holds quarter p of records 4b + j in q[j]; the
+    // first quad of a group (c1 clear) sends q[1], q[3] and takes the second
+    // one's q[0], q[2]
+    float x[4], y[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if ((quad_in >> j) & 1u) base[j * kSplatV + p] = make_float4(q[j][0], q[j][1], q[j][2], q[j][3]);
+    for (int c = 0; c < 4; ++c) {
+        x[c] = xor4_read(c1 ? q[0][c] : q[1][c]);
+        y[c] = xor4_read(c1 ? q[2][c] : q[3][c]);
+    }
+    float4 *base = splat_rec(s, e - (uint64_t)l8);                      // record 0 of the group
+    float4 out[4];
+    out[0] = c1 ? make_float4(x[0], x[1], x[2], x[3]) : make_float4(q[0][0], q[0][1], q[0][2], q[0][3]);
+    out[1] = c1 ? make_float4(y[0], y[1], y[2], y[3]) : make_float4(q[2][0], q[2][1], q[2][2], q[2][3]);
+    out[2] = c1 ? make_float4(q[1][0], q[1][1], q[1][2], q[1][3]) : make_float4(x[0], x[1], x[2], x[3]);
+    out[3] = c1 ? make_float4(q[3][0], q[3][1], q[3][2], q[3][3]) : make_float4(y[0], y[1], y[2], y[3]);
+    // store s: record 2s + c1 of the group, quarter p (oct_in: bit k set if
+    // the group's lane k has a Gaussian)
+    const int c = c1 ? 1 : 0;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+        if ((oct_in >> (2 * s4 + c)) & 1u) base[(2 * s4 + c) * kSplatV + p] = out[s4];
 }
 
 // cameras of a view batch, passed by value as a kernel argument
@@ -331,11 +354,11 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     if (g0 >= n) return;                                   // whole wavefront past the end
     stage_sh<3 * K>(sh, g0, (int)min((int64_t)64, n - g0), s_sh[wid]);
     // every lane of the wavefront stays to the end (the records are stored
-    // by quads of lanes); a lane past the end computes on its wavefront's
+    // by groups of lanes); a lane past the end computes on its wavefront's
     // first Gaussian and stores nothing
     const bool in = g0 + __lane_id() < n;
     const int64_t i = in ? g0 + __lane_id() : g0;
-    const uint32_t quad_in = (uint32_t)(__ballot(in) >> (__lane_id() & ~3u)) & 0xFu;
+    const uint32_t oct_in = (uint32_t)(__ballot(in) >> (__lane_id() & ~7u)) & 0xFFu;
     const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
     const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
     const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
@@ -369,7 +392,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
         } else {
             r = make_int4(0, 0, 0, 0);
         }
-        store_splats_quad(splats, (uint64_t)o, quad_in, co, mr, bl);
+        store_splats_oct(splats, (uint64_t)o, oct_in, co, mr, bl);
         if (in) {
             depth[o] = dz;
             rect[o] = r;

@@ -1205,6 +1205,10 @@ __global__ __launch_bounds__(kColBlock) void col_scatter_kernel(
         for (int r = 0; r < ITEMS; ++r) key[r] = s_buf[wid * kPerWave + r * 64 + lane];
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) {
+            // a chunk is often far from full (a block of Gaussians averages
+            // fewer pairs than a chunk holds): rounds past its end are empty,
+            // and so are all later ones
+            if (__builtin_amdgcn_readfirstlane(wid * kPerWave + r * 64) >= count) break;
             const int local = wid * kPerWave + r * 64 + lane;
             const bool active = local < count && (!EXACT || key[r] != kNone);
             const uint32_t d = key[r] & dmask;
