@@ -34,6 +34,11 @@ namespace {
 using namespace render;
 
 constexpr int kNG = 9;   // mean x, y; conic a, b, c; opacity; r, g, b
+// List entries staged per batch: 224 of the workgroup's 256 threads stage
+// one each, so that the batch's LDS (entries, ids, strip bits, accumulators:
+// 30.7 KB) lets five workgroups share a CU, and the kernel is held to 96
+// registers, five wavefronts per SIMD (with 256 entries, 35 KB, four)
+constexpr int kBatch = 224;
 
 struct BwdArgs {
     RenderArgs r;          // ranges, values, attributes, out_T, out_nc (read)
@@ -167,12 +172,12 @@ struct alignas(16) BwdEntry {
 };
 
 template <bool LOCAL, bool Q8, typename R, bool STATS>
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 5))) void render_bwd_kernel(BwdArgs ba)
 {
-    __shared__ BwdEntry<R> s_e[kBlock];
-    __shared__ uint32_t s_id[kBlock];
-    __shared__ uint8_t s_m[kBlock];
-    __shared__ float s_g[kNG][kBlock + 1];  // padded: the nine components of an entry in distinct banks
+    __shared__ BwdEntry<R> s_e[kBatch];
+    __shared__ uint32_t s_id[kBatch];
+    __shared__ uint8_t s_m[kBatch];
+    __shared__ float s_g[kNG][kBatch + 1];  // padded: the nine components of an entry in distinct banks
     __shared__ int s_max[kBlock / 64];
     __shared__ uint32_t s_pos;
 
@@ -209,11 +214,11 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     const uint2 range = a.ranges[tc.tile];
     const uint32_t end = range.x + (uint32_t)bmax;
 
-    // Two-deep software pipeline over the batches (back to front, kBlock
+    // Two-deep software pipeline over the batches (back to front, kBatch
     // entries each): while batch i is replayed, thread t holds the attributes
     // of entry t of batch i + 1 and the Gaussian id of entry t of batch i + 2
     // in registers, so the dependent gathers overlap the replay.
-    auto batch_start = [&](int64_t be) { return (uint32_t)max((int64_t)range.x, be - kBlock); };
+    auto batch_start = [&](int64_t be) { return (uint32_t)max((int64_t)range.x, be - kBatch); };
     auto fetch_id = [&](int64_t be) -> uint32_t {
         const uint32_t bs = batch_start(be);
         return (be > (int64_t)range.x && (int64_t)threadIdx.x < be - (int64_t)bs) ? a.values[bs + threadIdx.x] : 0u;
@@ -236,10 +241,10 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
     };
     uint32_t id_cur = fetch_id(end);
     Attr at_cur = fetch_attr(end, id_cur);
-    uint32_t id_next = fetch_id((int64_t)end - kBlock);
+    uint32_t id_next = fetch_id((int64_t)end - kBatch);
 
-    for (int64_t bend = end; bend > (int64_t)range.x; bend -= kBlock) {
-        const uint32_t bstart = (uint32_t)max((int64_t)range.x, bend - kBlock);
+    for (int64_t bend = end; bend > (int64_t)range.x; bend -= kBatch) {
+        const uint32_t bstart = (uint32_t)max((int64_t)range.x, bend - kBatch);
         const int nb = (int)(bend - bstart);
         __syncthreads();                                   // previous batch fully flushed
         if ((int)threadIdx.x < nb) {
@@ -295,8 +300,8 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(BwdArgs ba)
         __syncthreads();
         // the next batches' loads, in flight during this one's replay
         id_cur = id_next;
-        at_cur = fetch_attr(bend - kBlock, id_cur);
-        id_next = fetch_id(bend - 2 * (int64_t)kBlock);
+        at_cur = fetch_attr(bend - kBatch, id_cur);
+        id_next = fetch_id(bend - 2 * (int64_t)kBatch);
 
         // wavefront's own range: skip entries past its last contributor
         const int wlimit = __builtin_amdgcn_readfirstlane(
