@@ -290,7 +290,9 @@ __device__ __forceinline__ float xor4_read(float v)
     return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (4 << 10)));
 }
 
-__device__ __forceinline__ void store_splats_oct(float *s, uint64_t e, uint32_t oct_in, float4 co, float4 mr,
+// grp: index of the group's first record (from the wavefront's base, not
+// from a lane's own index, which is clamped for lanes past the end)
+__device__ __forceinline__ void store_splats_oct(float *s, uint64_t grp, uint32_t oct_in, float4 co, float4 mr,
                                                  float bl)
 {
     const int l8 = __lane_id() & 7, p = l8 & 3;
@@ -316,7 +318,7 @@ __device__ __forceinline__ void store_splats_oct(float *s, uint64_t e, uint32_t 
         x[c] = xor4_read(c1 ? q[0][c] : q[1][c]);
         y[c] = xor4_read(c1 ? q[2][c] : q[3][c]);
     }
-    float4 *base = splat_rec(s, e - (uint64_t)l8);                      // record 0 of the group
+    float4 *base = splat_rec(s, grp);                                    // record 0 of the group
     float4 out[4];
     out[0] = c1 ? make_float4(x[0], x[1], x[2], x[3]) : make_float4(q[0][0], q[0][1], q[0][2], q[0][3]);
     out[1] = c1 ? make_float4(y[0], y[1], y[2], y[3]) : make_float4(q[2][0], q[2][1], q[2][2], q[2][3]);
@@ -392,7 +394,7 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
         } else {
             r = make_int4(0, 0, 0, 0);
         }
-        store_splats_oct(splats, (uint64_t)o, oct_in, co, mr, bl);
+        store_splats_oct(splats, (uint64_t)v * n + g0 + (__lane_id() & ~7u), oct_in, co, mr, bl);
         if (in) {
             depth[o] = dz;
             rect[o] = r;

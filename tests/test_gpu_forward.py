@@ -89,7 +89,8 @@ def _sync_np(t):
 # ---------------------------------------------------------------------------
 # projection
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("cfg,n,view", [(1, 10000, 0), (2, 20000, 0), (5, 20000, 2), (5, 20000, 7)])
+@pytest.mark.parametrize("cfg,n,view", [(1, 10000, 0), (2, 20000, 0), (5, 20000, 2), (5, 20000, 7),
+                                        (2, 10003, 0), (5, 5, 1)])
 def test_project_parity(cfg, n, view):
     sc = scenes.make_config(cfg, n=n)
     cam = sc.cameras[view]
@@ -112,6 +113,39 @@ def test_project_parity(cfg, n, view):
     assert np.all(np.abs(co - f32(rc)) <= 2 * ulp(rc) + 1e-30)
     rgb = _sync_np(pr.rgb).astype(np.float64)[vis]
     assert np.all(np.abs(rgb - f32(ref["rgb"][vis])) <= 2 * ulp(ref["rgb"][vis]) + 1e-7)
+
+
+@pytest.mark.parametrize("n", [1, 5, 8, 13, 64, 70, 1003])
+def test_project_writes_nothing_past_n(n):
+    """The records are stored by groups of eight lanes: with n not a multiple
+    of eight (or of the 64-lane wavefront) the last group is partial, and
+    nothing past the n-th record, depth or rectangle may be written.  Two
+    views through the batch entry point: view 0's tail borders view 1's
+    head."""
+    import ctypes as C
+    from paper_2606_16566_amd import _lib as L
+    sc = scenes.make_config(2, n=n)
+    cams = [sc.cameras[0], scenes.look_at_camera((0.5, 0, 0), (0, 0, 1), 320, 200)]
+    params = scene_tensors(sc)
+    pad = 9
+    dev = torch.device("cuda")
+    splats = torch.full((2 * n + pad, L.SPLAT_FLOATS), 7.25, device=dev)
+    depth = torch.full((2 * n + pad,), 7.25, device=dev)
+    rect = torch.full((2 * n + pad, 4), 7, dtype=torch.int32, device=dev)
+    p = lambda t: C.c_void_p(t.data_ptr())
+    L.check(L.lib().lgs_project_batch(L.camera_array(cams), 2, n, sc.sh_degree, *(p(t) for t in params), p(splats),
+                                      p(depth), p(rect), C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "lgs_project_batch")
+    got_s, got_d, got_r = _sync_np(splats), _sync_np(depth), _sync_np(rect)
+    assert np.all(got_s[2 * n:] == 7.25) and np.all(got_d[2 * n:] == 7.25) and np.all(got_r[2 * n:] == 7)
+    # every record of both views written (culled ones as zeros), each view
+    # equal to its single-view projection
+    assert not np.any(got_s[:2 * n] == 7.25) and not np.any(got_d[:2 * n] == 7.25)
+    for v in range(2):
+        one = R.project(cams[v], *params)
+        assert np.array_equal(got_s[v * n:(v + 1) * n], _sync_np(one.splats))
+        assert np.array_equal(got_d[v * n:(v + 1) * n], _sync_np(one.depth))
+        assert np.array_equal(got_r[v * n:(v + 1) * n], _sync_np(one.rect))
 
 
 # ---------------------------------------------------------------------------
@@ -193,7 +227,7 @@ def _plan_depths(case, n, rng):
 
 @pytest.mark.parametrize("case,n", [("equal", 1100000), ("one_bit", 1100000), ("span_24", 1100000),
                                     ("span_25", 1100000), ("span_31", 1100000), ("span_31", 4300000),
-                                    ("single_visible", 1100000), ("span_25", 20000)])
+                                    ("single_visible", 1100000), ("all_culled", 1100000), ("span_25", 20000)])
 def test_sort_depth_plans(case, n):
     """From 2^20 Gaussians the depth passes sort only the bits in which the
     visible depth keys differ: pair lists bitwise equal to the oracle's for
@@ -208,6 +242,10 @@ def test_sort_depth_plans(case, n):
         depth = np.full(n, 5.0, np.float32)
         rect[:] = 0
         rect[n // 2] = (3, 4, 9, 7)
+    elif case == "all_culled":
+        vis[:] = 0
+        depth = np.full(n, 5.0, np.float32)
+        rect[:] = 0
     else:
         depth = _plan_depths(case, n, rng)
     depth = np.where(vis > 0, depth, np.float32(np.inf)).astype(np.float32)
@@ -218,6 +256,9 @@ def test_sort_depth_plans(case, n):
     p = len(ids)
     b = R.Binner(capacity=p + 9).run(cam, R.Projected(None, to_dev(depth), to_dev(rect)))
     assert int(b.num_pairs.item()) == p and int(b.overflow.item()) == 0
+    if p == 0:
+        assert np.all(_sync_np(b.ranges) == 0)
+        return
     assert np.array_equal(_sync_np(b.tile_keys)[:p].astype(np.int64), np.repeat(np.arange(tx * ty), np.diff(off)))
     assert np.array_equal(_sync_np(b.values)[:p], ids)
 
