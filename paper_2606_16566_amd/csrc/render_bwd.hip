@@ -392,7 +392,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 5))) 
                 {
                     static_assert(kNG == 9, "wave_sums9 handles nine components");
                     const float tot = wave_sums9(g);
-                    if (wave_owner(lane) && tot != 0.f) atomicAdd(&s_g[wave_comp(lane)][k], tot);
+                    // (a zero total adds nothing; testing for it cost more than the add)
+                    if (wave_owner(lane)) atomicAdd(&s_g[wave_comp(lane)][k], tot);
                 }
             }
         }
