@@ -234,9 +234,9 @@ MEASURED_TRAFFIC = {
     "render_bwd_kernel": {
         "sources": ["include/localgs.h", "paper_2606_16566_amd/csrc/common.hpp",
                     "paper_2606_16566_amd/csrc/render_common.hpp", "paper_2606_16566_amd/csrc/render_bwd.hip"],
-        "sha256": "2199afa3f9e310a8e621c369b84682876081bfec95cc9ecdb4f5c4fb79b7ae30",
-        "read_bytes": 15091014530,
-        "write_bytes": 3725000800,
+        "sha256": "b683aeb8579518f09669b54f483e9d2bde7975ec89ea180dc780ebcf30a7942a",
+        "read_bytes": 15249092930,
+        "write_bytes": 3732327653,
         "profile": "profiles/train_clustered-10M-16views_hbm_counters.md",
     },
 }
