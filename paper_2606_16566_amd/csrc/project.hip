@@ -12,30 +12,33 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 __device__ __forceinline__ double sq(double x) { return x * x; }
 
+// (in the precision T of the evaluation: double, or float for the colour)
+template <typename T>
 struct ShConst {
-    double k0, k1, k2a, k2b, k2c, k3a, k3b, k3c, k3d, k3e;
+    T k0, k1, k2a, k2b, k2c, k3a, k3b, k3c, k3d, k3e;
 };
-__device__ __forceinline__ ShConst sh_consts()
+template <typename T>
+__device__ __forceinline__ ShConst<T> sh_consts()
 {
-    ShConst k;
-    k.k0 = 0.5 / sqrt(kPi);               // Y_0^0
-    k.k1 = sqrt(3.0 / (4.0 * kPi));       // degree 1
-    k.k2a = 0.5 * sqrt(15.0 / kPi);       // xy, yz, xz terms
-    k.k2b = 0.25 * sqrt(5.0 / kPi);       // 3z^2 - 1
-    k.k2c = 0.25 * sqrt(15.0 / kPi);      // x^2 - y^2
-    k.k3a = 0.25 * sqrt(35.0 / (2.0 * kPi));
-    k.k3b = 0.5 * sqrt(105.0 / kPi);
-    k.k3c = 0.25 * sqrt(21.0 / (2.0 * kPi));
-    k.k3d = 0.25 * sqrt(7.0 / kPi);
-    k.k3e = 0.25 * sqrt(105.0 / kPi);
+    ShConst<T> k;
+    k.k0 = (T)(0.5 / sqrt(kPi));               // Y_0^0
+    k.k1 = (T)sqrt(3.0 / (4.0 * kPi));         // degree 1
+    k.k2a = (T)(0.5 * sqrt(15.0 / kPi));       // xy, yz, xz terms
+    k.k2b = (T)(0.25 * sqrt(5.0 / kPi));       // 3z^2 - 1
+    k.k2c = (T)(0.25 * sqrt(15.0 / kPi));      // x^2 - y^2
+    k.k3a = (T)(0.25 * sqrt(35.0 / (2.0 * kPi)));
+    k.k3b = (T)(0.5 * sqrt(105.0 / kPi));
+    k.k3c = (T)(0.25 * sqrt(21.0 / (2.0 * kPi)));
+    k.k3d = (T)(0.25 * sqrt(7.0 / kPi));
+    k.k3e = (T)(0.25 * sqrt(105.0 / kPi));
     return k;
 }
 
 // SH basis in index order l*l + l + m (m = -l..l) at unit direction (x, y, z).
-template <int DEG>
-__device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y)
+template <int DEG, typename T>
+__device__ __forceinline__ void sh_eval(T x, T y, T z, T *Y)
 {
-    const ShConst k = sh_consts();
+    const ShConst<T> k = sh_consts<T>();
     Y[0] = k.k0;
     if (DEG >= 1) {
         Y[1] = -k.k1 * y; Y[2] = k.k1 * z; Y[3] = -k.k1 * x;
@@ -43,19 +46,19 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y)
     if (DEG >= 2) {
         Y[4] = k.k2a * x * y;
         Y[5] = -k.k2a * y * z;
-        Y[6] = k.k2b * (3.0 * z * z - 1.0);
+        Y[6] = k.k2b * ((T)3 * z * z - (T)1);
         Y[7] = -k.k2a * x * z;
         Y[8] = k.k2c * (x * x - y * y);
     }
     if (DEG >= 3) {
-        const double zz5 = 5.0 * z * z - 1.0;
-        Y[9] = -k.k3a * y * (3.0 * x * x - y * y);
+        const T zz5 = (T)5 * z * z - (T)1;
+        Y[9] = -k.k3a * y * ((T)3 * x * x - y * y);
         Y[10] = k.k3b * x * y * z;
         Y[11] = -k.k3c * y * zz5;
-        Y[12] = k.k3d * z * (5.0 * z * z - 3.0);
+        Y[12] = k.k3d * z * ((T)5 * z * z - (T)3);
         Y[13] = -k.k3c * x * zz5;
         Y[14] = k.k3e * z * (x * x - y * y);
-        Y[15] = -k.k3a * x * (x * x - 3.0 * y * y);
+        Y[15] = -k.k3a * x * (x * x - (T)3 * y * y);
     }
 }
 
@@ -63,14 +66,14 @@ __device__ __forceinline__ void sh_eval(double x, double y, double z, double *Y)
 // accumulated term by term so that no per-basis gradient table is held; the
 // weights come from a callable, evaluated where each is used (no table of
 // them either).
-template <int DEG, typename WF>
-__device__ __forceinline__ void sh_grad_dir(double x, double y, double z, WF &&wf, double *g)
+template <int DEG, typename T, typename WF>
+__device__ __forceinline__ void sh_grad_dir(T x, T y, T z, WF &&wf, T *g)
 {
-    double w[16];
+    T w[16];
 #pragma unroll
     for (int k = 1; k < (DEG + 1) * (DEG + 1); ++k) w[k] = wf(k);
-    const ShConst k = sh_consts();
-    double gx = 0.0, gy = 0.0, gz = 0.0;
+    const ShConst<T> k = sh_consts<T>();
+    T gx = 0, gy = 0, gz = 0;
     if (DEG >= 1) {
         gy -= k.k1 * w[1];
         gz += k.k1 * w[2];
@@ -79,18 +82,18 @@ __device__ __forceinline__ void sh_grad_dir(double x, double y, double z, WF &&w
     if (DEG >= 2) {
         gx += k.k2a * y * w[4]; gy += k.k2a * x * w[4];
         gy -= k.k2a * z * w[5]; gz -= k.k2a * y * w[5];
-        gz += 6.0 * k.k2b * z * w[6];
+        gz += (T)6 * k.k2b * z * w[6];
         gx -= k.k2a * z * w[7]; gz -= k.k2a * x * w[7];
-        gx += 2.0 * k.k2c * x * w[8]; gy -= 2.0 * k.k2c * y * w[8];
+        gx += (T)2 * k.k2c * x * w[8]; gy -= (T)2 * k.k2c * y * w[8];
     }
     if (DEG >= 3) {
-        const double zz5 = 5.0 * z * z - 1.0, d33 = 3.0 * x * x - 3.0 * y * y, xy6 = 6.0 * x * y;
+        const T zz5 = (T)5 * z * z - (T)1, d33 = (T)3 * x * x - (T)3 * y * y, xy6 = (T)6 * x * y;
         gx -= k.k3a * xy6 * w[9]; gy -= k.k3a * d33 * w[9];
         gx += k.k3b * y * z * w[10]; gy += k.k3b * x * z * w[10]; gz += k.k3b * x * y * w[10];
-        gy -= k.k3c * zz5 * w[11]; gz -= k.k3c * 10.0 * y * z * w[11];
-        gz += k.k3d * (15.0 * z * z - 3.0) * w[12];
-        gx -= k.k3c * zz5 * w[13]; gz -= k.k3c * 10.0 * x * z * w[13];
-        gx += 2.0 * k.k3e * x * z * w[14]; gy -= 2.0 * k.k3e * y * z * w[14]; gz += k.k3e * (x * x - y * y) * w[14];
+        gy -= k.k3c * zz5 * w[11]; gz -= k.k3c * (T)10 * y * z * w[11];
+        gz += k.k3d * ((T)15 * z * z - (T)3) * w[12];
+        gx -= k.k3c * zz5 * w[13]; gz -= k.k3c * (T)10 * x * z * w[13];
+        gx += (T)2 * k.k3e * x * z * w[14]; gy -= (T)2 * k.k3e * y * z * w[14]; gz += k.k3e * (x * x - y * y) * w[14];
         gx -= k.k3a * d33 * w[15]; gy += k.k3a * xy6 * w[15];
     }
     g[0] = gx; g[1] = gy; g[2] = gz;
@@ -99,7 +102,7 @@ __device__ __forceinline__ void sh_grad_dir(double x, double y, double z, WF &&w
 // Forward intermediates of one Gaussian, kept for the backward recompute.
 struct Proj {
     bool visible;
-    double m[3], s[3], qn[4], qlen, o;
+    double m[3], s[3], o;
     double t[3];
     double R[3][3];
     double TM[2][3];         // T M with M = R diag(s): Sigma2 = TM TM^T + low-pass
@@ -111,7 +114,6 @@ struct Proj {
     double det;
     double a, b, c;          // conic
     double mx, my;           // projected mean
-    double dir[3], dlen;     // unit view direction and |mean - campos|
     double tau;              // footprint level 2 ln(255 o)
 };
 
@@ -149,6 +151,15 @@ __device__ __forceinline__ GaussPre gauss_pre(const float *m3, const float *ls, 
     return g;
 }
 
+// rotation matrix of the unit quaternion (w, x, y, z)
+__device__ __forceinline__ void rotation(const double *qn, double (&R)[3][3])
+{
+    const double w = qn[0], x = qn[1], y = qn[2], z = qn[3];
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z); R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z); R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y); R[2][1] = 2.0 * (y * z + w * x); R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+}
+
 // Geometry of the projection (no colour) for one view.  Returns false if
 // culled before the footprint test.
 __device__ bool project_geometry(const Cam &cam, const float *m3, const GaussPre &G, Proj &P)
@@ -161,12 +172,7 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const GaussPre
         P.t[k] = fma((double)V[4 * k + 2], P.m[2], fma((double)V[4 * k + 1], P.m[1],
                  fma((double)V[4 * k + 0], P.m[0], (double)V[4 * k + 3])));
     if (!(P.t[2] > (double)cam.znear)) return false;
-    P.qlen = G.qlen;
-    const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-    P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
-    P.R[0][0] = 1.0 - 2.0 * (y * y + z * z); P.R[0][1] = 2.0 * (x * y - w * z); P.R[0][2] = 2.0 * (x * z + w * y);
-    P.R[1][0] = 2.0 * (x * y + w * z); P.R[1][1] = 1.0 - 2.0 * (x * x + z * z); P.R[1][2] = 2.0 * (y * z - w * x);
-    P.R[2][0] = 2.0 * (x * z - w * y); P.R[2][1] = 2.0 * (y * z + w * x); P.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    rotation(G.qn, P.R);
     for (int j = 0; j < 3; ++j) P.s[j] = G.s[j];
     const double fx = cam.fx, fy = cam.fy;
     const double limx = kGuard * (double)cam.tanx, limy = kGuard * (double)cam.tany;
@@ -196,16 +202,27 @@ __device__ bool project_geometry(const Cam &cam, const float *m3, const GaussPre
     P.my = fy * P.t[1] * rz + (double)cam.cy;
     P.o = G.o;
     P.tau = G.tau;
-    double d0 = P.m[0] - (double)cam.campos[0], d1 = P.m[1] - (double)cam.campos[1], d2 = P.m[2] - (double)cam.campos[2];
-    P.dlen = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    if (P.dlen > 0.0) {
-        const double il = 1.0 / P.dlen;
-        P.dir[0] = d0 * il; P.dir[1] = d1 * il; P.dir[2] = d2 * il;
-    } else {
-        P.dir[0] = 0.0; P.dir[1] = 0.0; P.dir[2] = 1.0;
-    }
     return true;
 }
+
+// Unit view direction (mean - camera centre) in single precision, for the SH
+// colour, and 1 / |mean - camera centre| (0 for a mean on the centre, whose
+// direction is taken as +z).  Each difference of two floats is exact to
+// within one rounding, so every component is within a few units in the last
+// place of its value.
+struct ViewDir {
+    float x, y, z, il;
+};
+__device__ __forceinline__ ViewDir view_dir(const Cam &cam, const float *m3)
+{
+    const float d0 = m3[0] - cam.campos[0], d1 = m3[1] - cam.campos[1], d2 = m3[2] - cam.campos[2];
+    const float s2 = d0 * d0 + d1 * d1 + d2 * d2;
+    ViewDir d;
+    d.il = s2 > 0.f ? rsqrtf(s2) : 0.f;
+    d.x = d0 * d.il; d.y = d1 * d.il; d.z = s2 > 0.f ? d2 * d.il : 1.f;
+    return d;
+}
+
 
 // Tile rectangle of the footprint; false if it covers no pixel centre.
 __device__ bool footprint(const Cam &cam, const Proj &P, int4 &rect)
@@ -379,17 +396,20 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
         float4 co = make_float4(0.f, 0.f, 0.f, 0.f), mr = co;
         float bl = 0.f, dz = INFINITY;
         if (vis) {
-            double Y[K];
-            sh_eval<DEG>(P.dir[0], P.dir[1], P.dir[2], Y);
-            double col[3] = {0.5, 0.5, 0.5};
+            // colour in single precision (a continuous function of the
+            // sum: its error bound is kColourTol's)
+            const ViewDir d = view_dir(cam, m3);
+            float Y[K];
+            sh_eval<DEG>(d.x, d.y, d.z, Y);
+            float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
             for (int k = 0; k < K; ++k) {
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) col[ch] += (double)shi[3 * k + ch] * Y[k];
+                for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(shi[3 * k + ch], Y[k], col[ch]);
             }
             co = make_float4((float)P.a, (float)P.b, (float)P.c, (float)P.o);
-            mr = make_float4((float)P.mx, (float)P.my, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0));
-            bl = (float)fmax(col[2], 0.0);
+            mr = make_float4((float)P.mx, (float)P.my, fmaxf(col[0], 0.f), fmaxf(col[1], 0.f));
+            bl = fmaxf(col[2], 0.f);
             dz = (float)P.t[2];
         } else {
             r = make_int4(0, 0, 0, 0);
@@ -402,10 +422,47 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     }
 }
 
-// Raw-parameter gradient of one Gaussian, summed over views.
+// Gradient of one Gaussian, summed over views: of the mean, of the opacity
+// logit, and of M = R diag(s) (the scales and the quaternion depend on the
+// view only through M, and linearly in dL/dM, so their chain is applied once
+// to the sum: rot_scale_grad).
 struct RawGrad {
-    double m[3], ls[3], q[4], logit;
+    double m[3], M[3][3], logit;
 };
+
+// dL/d log-scales and dL/d raw quaternion from dL/dM summed over views:
+// M = R diag(s) with s = exp(log-scales) and R the rotation of q / |q|.
+__device__ __forceinline__ void rot_scale_grad(const GaussPre &G, const double (&gM)[3][3], double *gls,
+                                               double *gqr)
+{
+    double R[3][3];
+    rotation(G.qn, R);
+    // dL/dR[a][b] = dL/dM[a][b] s[b], dL/ds[b] = sum_a dL/dM[a][b] R[a][b]
+    double gR[3][3], gs[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            gR[a][b] = gM[a][b] * G.s[b];
+            gs[b] += gM[a][b] * R[a][b];
+        }
+    for (int k = 0; k < 3; ++k) gls[k] = gs[k] * G.s[k];
+    // through the rotation matrix of the unit quaternion
+    const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    double gq[4];
+    gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0]
+                   + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    gq[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0]
+                   + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    gq[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1]
+                   + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    // normalisation q / |q|
+    const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+    const double iq = 1.0 / G.qlen;
+    gqr[0] = (gq[0] - w * dq) * iq;
+    gqr[1] = (gq[1] - x * dq) * iq;
+    gqr[2] = (gq[2] - y * dq) * iq;
+    gqr[3] = (gq[3] - z * dq) * iq;
+}
 
 // Adds one view's contribution.  m3/ls/qt/logit are the Gaussian's raw
 // parameters, shi its SH coefficients and dshi the slot accumulating
@@ -512,32 +569,9 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
         gm[k] += (double)V[0 * 4 + k] * gt[0] + (double)V[1 * 4 + k] * gt[1] + (double)V[2 * 4 + k] * gt[2];
     for (int k = 0; k < 3; ++k) acc.m[k] += gm[k];
 
-    // M = R diag(s): dL/dR[a][b] = dL/dM[a][b] s[b], dL/ds[b] = sum_a dL/dM[a][b] R[a][b]
-    double gR[3][3], gs[3] = {0.0, 0.0, 0.0};
+    // dL/dM = T^T dL/dTM, summed over views (rot_scale_grad applies the rest)
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            const double gM = P.T[0][a] * gTM[0][b] + P.T[1][a] * gTM[1][b];
-            gR[a][b] = gM * P.s[b];
-            gs[b] += gM * P.R[a][b];
-        }
-    for (int k = 0; k < 3; ++k) acc.ls[k] += gs[k] * P.s[k];
-    // rotation matrix of the unit quaternion
-    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    double gq[4];
-    gq[0] = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
-    gq[1] = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] + z * gR[2][0]
-                   + w * gR[2][1] - 2.0 * x * gR[2][2]);
-    gq[2] = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] - w * gR[2][0]
-                   + z * gR[2][1] - 2.0 * y * gR[2][2]);
-    gq[3] = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1]
-                   + y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
-    // normalisation q / |q|
-    const double dq = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
-    const double iq = 1.0 / P.qlen;
-    acc.q[0] += (gq[0] - w * dq) * iq;
-    acc.q[1] += (gq[1] - x * dq) * iq;
-    acc.q[2] += (gq[2] - y * dq) * iq;
-    acc.q[3] += (gq[3] - z * dq) * iq;
+        for (int b = 0; b < 3; ++b) acc.M[a][b] += P.T[0][a] * gTM[0][b] + P.T[1][a] * gTM[1][b];
 }
 
 
@@ -630,8 +664,10 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
             project_bwd_accum<DEG>(cb.cam[v], m3, G, shi, rv, make_float2(gv[4], gv[5]), gc3, gv[3], gr3, acc,
                                    dslot);
         }
-        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)acc.ls[k]; }
-        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)acc.q[k];
+        double gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+        if (G.ok) rot_scale_grad(G, acc.M, gls, gq);
+        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)gls[k]; }
+        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)gq[k];
         d_logits[i] = (float)acc.logit;
     }
     unstage_sh<K3>(d_sh, g0, cnt, s_dsh[wid]);

@@ -111,8 +111,13 @@ def test_project_parity(cfg, n, view):
     co = _sync_np(pr.conic_opacity).astype(np.float64)[vis]
     rc = np.concatenate([ref["conic"], ref["opacity"][:, None]], 1)[vis]
     assert np.all(np.abs(co - f32(rc)) <= 2 * ulp(rc) + 1e-30)
+    # the colour is evaluated in single precision: within 96 u sum_k |sh_k| + 8 u
+    # (u = 2^-24) of the exact value, the bound the kernel's sign test uses
     rgb = _sync_np(pr.rgb).astype(np.float64)[vis]
-    assert np.all(np.abs(rgb - f32(ref["rgb"][vis])) <= 2 * ulp(ref["rgb"][vis]) + 1e-7)
+    sh_abs = np.abs(sc.sh.reshape(n, -1, 3).astype(np.float64)).sum(1)[vis]
+    tol = 2 * ulp(ref["rgb"][vis]) + (96 * sh_abs + 8) * 2.0 ** -24
+    assert np.all(np.abs(rgb - f32(ref["rgb"][vis])) <= tol)
+    print(f"  colour error: worst {np.max(np.abs(rgb - ref['rgb'][vis]) / tol):.3f} of the bound", flush=True)
 
 
 @pytest.mark.parametrize("n", [1, 5, 8, 13, 64, 70, 1003])
