@@ -422,13 +422,14 @@ __global__ __launch_bounds__(256) void project_fwd_kernel(CamBatch cb, int64_t n
     }
 }
 
-// Gradient of one Gaussian, summed over views: of the mean, of the opacity
-// logit, and of M = R diag(s) (the scales and the quaternion depend on the
-// view only through M, and linearly in dL/dM, so their chain is applied once
-// to the sum: rot_scale_grad).
+// One view's gradient of a Gaussian: of the mean, of the opacity logit, and
+// of M = R diag(s) (the scales and the quaternion depend on the view only
+// through M, and linearly in dL/dM, so their chain is applied once to the sum
+// over views: rot_scale_grad).
 struct RawGrad {
     double m[3], M[3][3], logit;
 };
+constexpr int kRawGradD = 13;   // doubles in a RawGrad
 
 // dL/d log-scales and dL/d raw quaternion from dL/dM summed over views:
 // M = R diag(s) with s = exp(log-scales) and R the rotation of q / |q|.
@@ -464,24 +465,19 @@ __device__ __forceinline__ void rot_scale_grad(const GaussPre &G, const double (
     gqr[3] = (gq[3] - z * dq) * iq;
 }
 
-// Adds one view's contribution.  m3/ls/qt/logit are the Gaussian's raw
-// parameters, shi its SH coefficients and dshi the slot accumulating
-// dL/d sh; g* are this view's gradients of the projected attributes.
+// One view's contribution of a Gaussian whose projected attributes received
+// a gradient.  m3 is its mean, G its view-independent terms, shi its SH
+// coefficients and dshi[k * dstride] the LDS accumulators of dL/d sh (added
+// to atomically: several views of one Gaussian may be taken at once); g* are
+// this view's gradients of the projected attributes.  The SH gradient is
+// always added; out (the rest) only if the projection's geometry is valid,
+// which the return value says.
 template <int DEG>
-__device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m3, const GaussPre &G,
-                                                  const float *shi, const int4 r, const float2 g2,
-                                                  const float *g_con, float g_op, const float *g_col, RawGrad &acc,
-                                                  float *dshi)
+__device__ __forceinline__ bool project_bwd_view(const Cam &cam, const float *m3, const GaussPre &G,
+                                                 const float *shi, const float2 g2, const float *g_con, float g_op,
+                                                 const float *g_col, RawGrad &out, double *dshi, int dstride)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    // every term below is linear in the incoming gradients: a view that sends
-    // none (the Gaussian culled, or covered by nearer ones in every pixel it
-    // reaches) adds nothing, and whole wavefronts of neighbouring Gaussians
-    // skip it together
-    if (g2.x == 0.f && g2.y == 0.f && g_con[0] == 0.f && g_con[1] == 0.f && g_con[2] == 0.f && g_op == 0.f
-        && g_col[0] == 0.f && g_col[1] == 0.f && g_col[2] == 0.f)
-        return;
-    if (!((r.z > r.x) && (r.w > r.y))) return;
     // The colour's gradient first: it needs only the view direction, so its
     // basis and weights are dead before the projection's intermediates are
     // recomputed below (fewer registers live at once).
@@ -506,7 +502,7 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
         // of them in registers across the passes (a compiler barrier only)
         __asm__ volatile("" ::: "memory");
         for (int k = 0; k < K; ++k)
-            for (int ch = 0; ch < 3; ++ch) dshi[3 * k + ch] += (float)(gcol[ch] * Y[k]);
+            for (int ch = 0; ch < 3; ++ch) atomicAdd(&dshi[(3 * k + ch) * dstride], gcol[ch] * Y[k]);
         // dL/d dir = sum_k (sum_ch gcol_ch sh_k,ch) grad Y_k
         double gdir[3];
         sh_grad_dir<DEG>(dir[0], dir[1], dir[2], [&](int k) {
@@ -518,13 +514,13 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
         }
     }
     Proj P;
-    if (!project_geometry(cam, m3, G, P)) return;
+    if (!project_geometry(cam, m3, G, P)) return false;
     const double gmx = g2.x, gmy = g2.y;
     const double ga = g_con[0], gb = g_con[1], gc = g_con[2];
     const double go = g_op;
 
     // opacity = sigmoid(logit)
-    acc.logit += go * P.o * (1.0 - P.o);
+    out.logit = go * P.o * (1.0 - P.o);
 
     // conic (a, b, c) = (Y, -Z, X) / det  ->  Sigma2 entries X, Y, Z
     const double id = 1.0 / P.det, id2 = id * id;
@@ -567,110 +563,216 @@ __device__ __forceinline__ void project_bwd_accum(const Cam &cam, const float *m
     // t = W m + t_c
     for (int k = 0; k < 3; ++k)
         gm[k] += (double)V[0 * 4 + k] * gt[0] + (double)V[1 * 4 + k] * gt[1] + (double)V[2 * 4 + k] * gt[2];
-    for (int k = 0; k < 3; ++k) acc.m[k] += gm[k];
+    for (int k = 0; k < 3; ++k) out.m[k] = gm[k];
 
-    // dL/dM = T^T dL/dTM, summed over views (rot_scale_grad applies the rest)
+    // dL/dM = T^T dL/dTM (rot_scale_grad applies the rest to the sum)
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) acc.M[a][b] += P.T[0][a] * gTM[0][b] + P.T[1][a] * gTM[1][b];
+        for (int b = 0; b < 3; ++b) out.M[a][b] = P.T[0][a] * gTM[0][b] + P.T[1][a] * gTM[1][b];
+    return true;
 }
 
 
-// copy this wavefront's LDS slots back to HBM with 16-byte stores
+// Row stride (in doubles) of the coefficient-major LDS accumulators of the
+// SH gradient, [k][Gaussian]: 65, not 64, so that the transposing copy-out's
+// lanes (consecutive coefficients of one Gaussian) fall in different banks.
+constexpr int kDshStride = 65;
+
+// copy a wavefront's coefficient-major SH gradient [k][Gaussian] to HBM,
+// Gaussian-major, with 16-byte stores (the run of cnt * 3K floats starts
+// 16-byte aligned: the wavefront's first Gaussian is a multiple of 64)
 template <int K3>
-__device__ __forceinline__ void unstage_sh(float *__restrict__ dst_all, int64_t g0, int cnt, const float *s_sh)
+__device__ __forceinline__ void unstage_dsh(float *__restrict__ dst_all, int64_t g0, int cnt, const double *s_dsh)
 {
-    constexpr int P = sh_stride(K3);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float *dst = dst_all + g0 * K3;
-    const int total = cnt * K3;
-    const int nv = total >> 2;
+    auto at = [&](int e) { const int g = e / K3; return (float)s_dsh[(e - g * K3) * kDshStride + g]; };
+    const int total = cnt * K3, nv = total >> 2;
     float4 *dst4 = reinterpret_cast<float4 *>(dst);
-    if constexpr (P == K3) {
-        const float4 *src4 = reinterpret_cast<const float4 *>(s_sh);
-        for (int i = __lane_id(); i < nv; i += 64) dst4[i] = src4[i];
-    } else {
-        for (int i = __lane_id(); i < nv; i += 64) {
-            const int e = 4 * i, g = e / K3, k = e - g * K3;
-            const float *q = s_sh + g * P + k;
-            dst4[i] = make_float4(q[0], q[1], q[2], q[3]);
-        }
-    }
-    for (int i = (nv << 2) + __lane_id(); i < total; i += 64) dst[i] = s_sh[(i / K3) * P + i % K3];
+    for (int q = __lane_id(); q < nv; q += 64) dst4[q] = make_float4(at(4 * q), at(4 * q + 1), at(4 * q + 2), at(4 * q + 3));
+    for (int e = (nv << 2) + __lane_id(); e < total; e += 64) dst[e] = at(e);
 }
 
+// the value x of lane src (src4 = 4 src), for 32- and 64-bit values
+__device__ __forceinline__ float from_lane(float x, int src4)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(x)));
+}
+__device__ __forceinline__ double from_lane(double x, int src4)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src4, __double2loint(x));
+    const int hi = __builtin_amdgcn_ds_bpermute(src4, __double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// Backward of the projection for a batch of views.  A workgroup of two
+// wavefronts per 64 Gaussians (lane l of each holds Gaussian l's parameters).
+// A Gaussian receives a gradient in few of the views (in a training step of
+// 16 views over a dense scene, 17 % of the (Gaussian, view) pairs, 2.7 views
+// per Gaussian on average, while some lane of a wavefront has one in 84 % of
+// the wavefront-views), so the pairs are compacted before the expensive part:
+//  1. scan: wavefront w reads, for its half of the views, every Gaussian's
+//     gradient record and rectangle (all of them issued at once); the pairs
+//     with a nonzero record over a nonempty rectangle go to its LDS list,
+//     view by view;
+//  2. rounds: the two lists, concatenated, are taken 64 pairs at a time by
+//     the two wavefronts in turn; a lane takes one pair (the Gaussian's
+//     parameters from its lane, its SH row from LDS, the camera of the view)
+//     and adds its contribution to the Gaussian's LDS accumulators with
+//     double-precision LDS atomics (several views of one Gaussian may be
+//     taken at once; the single-precision LDS atomic add measured several
+//     times slower per instruction when most lanes take part);
+//  3. wavefront 0 turns each Gaussian's sums into the raw-parameter
+//     gradients, wavefront 1 copies the SH gradient out.
 template <int DEG>
 __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n, const float *__restrict__ means3d,
-                                                          const float *__restrict__ log_scales,
-                                                          const float *__restrict__ quats,
-                                                          const float *__restrict__ logits,
-                                                          const float *__restrict__ sh, const int4 *__restrict__ rect,
-                                                          float *__restrict__ g_splats, bool clear,
-                                                          float *__restrict__ d_means3d,
-                                                          float *__restrict__ d_log_scales, float *__restrict__ d_quats,
-                                                          float *__restrict__ d_logits, float *__restrict__ d_sh)
+                                                         const float *__restrict__ log_scales,
+                                                         const float *__restrict__ quats,
+                                                         const float *__restrict__ logits,
+                                                         const float *__restrict__ sh, const int4 *__restrict__ rect,
+                                                         float *__restrict__ g_splats, bool clear,
+                                                         float *__restrict__ d_means3d,
+                                                         float *__restrict__ d_log_scales, float *__restrict__ d_quats,
+                                                         float *__restrict__ d_logits, float *__restrict__ d_sh)
 {
     constexpr int K3 = 3 * (DEG + 1) * (DEG + 1);
     constexpr int P = sh_stride(K3);
-    __shared__ float s_sh[2][64 * P];
-    __shared__ float s_dsh[2][64 * P];
+    constexpr int kHalf = kMaxViews / 2;
+    __shared__ float s_sh[64 * P];
+    __shared__ double s_dsh[K3 * kDshStride];    // coefficient-major: [k][Gaussian]
+    __shared__ double s_acc[kRawGradD][64];
+    __shared__ uint16_t s_items[2][64 * kHalf];   // lane | view << 8, one list per wavefront
+    __shared__ int s_w[2];
+    const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + wid * 64;
-    if (g0 >= n) return;                                   // whole wavefront past the end
+    const int64_t g0 = (int64_t)blockIdx.x * 64;
     const int cnt = (int)min((int64_t)64, n - g0);
-    stage_sh<K3>(sh, g0, cnt, s_sh[wid]);
-    const int64_t i = g0 + __lane_id();
-    float *dslot = s_dsh[wid] + __lane_id() * P;
-    for (int k = 0; k < K3; ++k) dslot[k] = 0.f;
-    if (i < n) {
-        const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
-        const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
-        const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
-        const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
-        const float logit = logits[i];
-        const float *shi = s_sh[wid] + __lane_id() * P;
-        const GaussPre G = gauss_pre(m3, ls, qt, logit);
-        RawGrad acc = {};
-        // view v + 1's gradient record and rectangle are loaded while view v
-        // is accumulated
-        float gn[kGradF];
-        int4 rn;
-        auto fetch = [&](int v) {
-            const int64_t o = (int64_t)v * n + i;
+    if (wid == 0) {
+        stage_sh<K3>(sh, g0, cnt, s_sh);
+    } else {
+        for (int k = 0; k < K3; ++k) s_dsh[k * kDshStride + lane] = 0.0;
+        for (int c = 0; c < kRawGradD; ++c) s_acc[c][lane] = 0.0;
+    }
+    const bool in = lane < cnt;
+    const int64_t i = g0 + (in ? lane : 0);
+    const float m3[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
+    const float ls[3] = {log_scales[3 * i], log_scales[3 * i + 1], log_scales[3 * i + 2]};
+    const float4 q4 = reinterpret_cast<const float4 *>(quats)[i];
+    const float qt[4] = {q4.x, q4.y, q4.z, q4.w};
+    const GaussPre G = gauss_pre(m3, ls, qt, logits[i]);
+
+    // 1. scan: wavefront w takes views [w * h, min(V, (w + 1) * h)), h = ceil(V / 2)
+    const int h = (cb.V + 1) >> 1;
+    const int vbeg = wid * h, vend = min(cb.V, vbeg + h);
+    int W = 0;
+    {
+        float gv[kHalf][kGradF];
+        int4 rv[kHalf];
+#pragma unroll
+        for (int u = 0; u < kHalf; ++u) {
+            const int64_t o = (int64_t)min(vbeg + u, cb.V - 1) * n + i;
             const float *gr = g_splats + (uint64_t)o * kGradF;
 #pragma unroll
-            for (int c = 0; c < kGradF; ++c) gn[c] = gr[c];
-            rn = rect[o];
-        };
-        fetch(0);
-        for (int v = 0; v < cb.V; ++v) {
-            float gv[kGradF];
+            for (int c = 0; c < kGradF; ++c) gv[u][c] = gr[c];
+            rv[u] = rect[o];
+        }
 #pragma unroll
-            for (int c = 0; c < kGradF; ++c) gv[c] = gn[c];
-            const int4 rv = rn;
-            if (v + 1 < cb.V) fetch(v + 1);
+        for (int u = 0; u < kHalf; ++u) {
+            const int v = vbeg + u;
+            if (v >= vend) break;
+            // a record that is not listed (nonzero over an empty rectangle:
+            // nothing to add) is cleared here, a listed one when it is taken
             bool nz = false;
 #pragma unroll
-            for (int c = 0; c < kGradF; ++c) nz = nz || gv[c] != 0.f;
-            if (clear && nz) {
-                // read and cleared: the record is zero for the next backward
+            for (int c = 0; c < kGradF; ++c) nz = nz || gv[u][c] != 0.f;
+            nz = nz && in;
+            const bool act = nz && rv[u].z > rv[u].x && rv[u].w > rv[u].y;
+            if (clear && nz && !act) {
                 float *gr = g_splats + ((uint64_t)v * n + i) * kGradF;
+#pragma unroll
+                for (int c = 0; c < kGradF; ++c) gr[c] = 0.f;
+            }
+            const uint64_t b = __ballot(act);
+            const int pos = W + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+            if (act) s_items[wid][pos] = (uint16_t)(lane | (v << 8));
+            W += __popcll(b);
+        }
+    }
+    if (lane == 0) s_w[wid] = W;
+    __syncthreads();
+    const int W0 = s_w[0], Wt = W0 + s_w[1];
+    auto item = [&](int j) { return j < W0 ? (int)s_items[0][j] : (int)s_items[1][j - W0]; };
+
+    // 2. rounds of 64 listed pairs, taken alternately by the two wavefronts
+    float gn[kGradF];
+    auto fetch = [&](int j) {
+        if (j < Wt) {
+            const int it = item(j);
+            const float *gr = g_splats + ((uint64_t)(it >> 8) * n + (uint64_t)(g0 + (it & 63))) * kGradF;
+#pragma unroll
+            for (int c = 0; c < kGradF; ++c) gn[c] = gr[c];
+        }
+    };
+    fetch(wid * 64 + lane);
+    for (int r = wid * 64; r < Wt; r += 128) {
+        const int j = r + lane;
+        const bool has = j < Wt;
+        const int it = has ? item(j) : 0;
+        const int gl = it & 63, v = it >> 8;
+        float gv[kGradF];
+#pragma unroll
+        for (int c = 0; c < kGradF; ++c) gv[c] = gn[c];
+        fetch(j + 128);
+        // the Gaussian's mean and view-independent terms, from its lane
+        const int src4 = gl << 2;
+        const float m3o[3] = {from_lane(m3[0], src4), from_lane(m3[1], src4), from_lane(m3[2], src4)};
+        GaussPre Go;
+        Go.ok = __builtin_amdgcn_ds_bpermute(src4, G.ok ? 1 : 0) != 0;
+        for (int c = 0; c < 4; ++c) Go.qn[c] = from_lane(G.qn[c], src4);
+        for (int c = 0; c < 3; ++c) Go.s[c] = from_lane(G.s[c], src4);
+        Go.o = from_lane(G.o, src4);
+        Go.qlen = 0.0;                          // unused by the per-view terms
+        Go.tau = 0.0;
+        if (has) {
+            float *gr = g_splats + ((uint64_t)v * n + (uint64_t)(g0 + gl)) * kGradF;
+            if (clear) {
 #pragma unroll
                 for (int c = 0; c < kGradF; ++c) gr[c] = 0.f;
             }
             const float gc3[3] = {gv[0], gv[1], gv[2]};
             const float gr3[3] = {gv[6], gv[7], gv[8]};
-            project_bwd_accum<DEG>(cb.cam[v], m3, G, shi, rv, make_float2(gv[4], gv[5]), gc3, gv[3], gr3, acc,
-                                   dslot);
+            RawGrad vg;
+            if (project_bwd_view<DEG>(cb.cam[v], m3o, Go, s_sh + gl * P, make_float2(gv[4], gv[5]), gc3, gv[3], gr3,
+                                      vg, s_dsh + gl, kDshStride)) {
+                for (int c = 0; c < 3; ++c) atomicAdd(&s_acc[c][gl], vg.m[c]);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) atomicAdd(&s_acc[3 + 3 * a + b][gl], vg.M[a][b]);
+                atomicAdd(&s_acc[12][gl], vg.logit);
+            }
         }
-        double gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
-        if (G.ok) rot_scale_grad(G, acc.M, gls, gq);
-        for (int k = 0; k < 3; ++k) { d_means3d[3 * i + k] = (float)acc.m[k]; d_log_scales[3 * i + k] = (float)gls[k]; }
-        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)gq[k];
-        d_logits[i] = (float)acc.logit;
     }
-    unstage_sh<K3>(d_sh, g0, cnt, s_dsh[wid]);
+    __syncthreads();
+
+    // 3. wavefront 0: the sums through the scales and the rotation; 1: the SH gradient
+    if (wid == 0) {
+        if (in) {
+            double M[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) M[a][b] = s_acc[3 + 3 * a + b][lane];
+            double gls[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0};
+            if (G.ok) rot_scale_grad(G, M, gls, gq);
+            for (int k = 0; k < 3; ++k) {
+                d_means3d[3 * i + k] = (float)s_acc[k][lane];
+                d_log_scales[3 * i + k] = (float)gls[k];
+            }
+            for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = (float)gq[k];
+            d_logits[i] = (float)s_acc[12][lane];
+        }
+    } else {
+        unstage_dsh<K3>(d_sh, g0, cnt, s_dsh);
+    }
 }
 
 }  // namespace
@@ -750,7 +852,7 @@ extern "C" lgs_status lgs_project_backward_batch(const lgs_camera *cameras, int3
                     && ((uintptr_t)d_sh % 16 == 0) && ((uintptr_t)quats % 16 == 0),
                 "lgs_project_backward: rect/sh/d_sh/quats must be 16-byte and g_splats 4-byte aligned");
     hipStream_t s = as_stream(stream);
-    const dim3 grid(grid_for(n, 128)), block(128);
+    const dim3 grid(grid_for(n, 64)), block(128);
     auto *rc = reinterpret_cast<const int4 *>(rect);
 #define LGS_PB(D)                                                                                                   \
     hipLaunchKernelGGL(project_bwd_kernel<D>, grid, block, 0, s, cb, n, means3d, log_scales, quats, opacity_logits, \

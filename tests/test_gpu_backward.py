@@ -88,6 +88,60 @@ def test_project_backward_parity(cfg, n, view):
         assert_grad_close(_np(got[k]), want[k], k, tol=1e-5)
 
 
+@pytest.mark.parametrize("V,n,seed", [(16, 3001, 11), (5, 130, 12), (1, 777, 13), (16, 64, 14)])
+def test_project_backward_batch_sparse_views(V, n, seed):
+    """The batch backward of the projection lists, per 64 Gaussians, the
+    (Gaussian, view) pairs whose gradient record is nonzero over a nonempty
+    rectangle and takes them 64 at a time, several views of one Gaussian in
+    one round.  Against the oracle's single-view backward summed over the
+    views: sparse records (a Gaussian in no view, in some, or in nearly all),
+    nonzero records over empty rectangles (no contribution; cleared like the
+    others), n not a multiple of 64, and the records all zero afterwards."""
+    import ctypes as C
+    from paper_2606_16566_amd import _lib as L
+    from tests.test_gpu_batch import ring_cameras
+    sc = scenes.make_config(5, n=n)
+    cams = ring_cameras([(64 + 16 * (v % 5), 48 + 8 * (v % 3)) for v in range(V)])
+    rng = np.random.default_rng(seed)
+    # per Gaussian, the share of views with a gradient: none, some, most
+    share = rng.choice([0.0, 0.2, 0.6, 0.95], size=n, p=[0.3, 0.4, 0.2, 0.1])
+    rect = np.zeros((V, n, 4), np.int32)
+    rec = np.zeros((V, n, L.GRAD_FLOATS), np.float32)
+    want = {k: 0.0 for k in ("means3d", "log_scales", "quats", "opacity_logits", "sh")}
+    listed = 0
+    for v, cam in enumerate(cams):
+        pr = O.project(cam, sc.means3d, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh)
+        rect[v] = pr["rect"]
+        vis = pr["visible"] == 1
+        has = rng.uniform(size=n) < np.where(vis, share, 0.5)      # some over empty rectangles too
+        g = rng.standard_normal((n, L.GRAD_FLOATS)).astype(np.float32)
+        g[:, 0:3] *= 100.0                                          # conic gradients
+        g[~has] = 0.0
+        rec[v] = g
+        listed += int((has & vis).sum())
+        d = O.project_backward(cam, sc.means3d, sc.log_scales, sc.quats, sc.opacity_logits, sc.sh,
+                               g[:, 4:6], g[:, 0:3], g[:, 3], g[:, 6:9])
+        for k in want:
+            want[k] = want[k] + d[k]
+    print(f"V={V} n={n}: {listed} listed pairs of {V * n}", flush=True)
+    ps = scene_tensors(sc)
+    dev = torch.device("cuda")
+    r_dev = to_dev(rect.reshape(V * n, 4))
+    g_dev = to_dev(rec.reshape(V * n, L.GRAD_FLOATS))
+    out = dict(means3d=torch.empty((n, 3), device=dev), log_scales=torch.empty((n, 3), device=dev),
+               quats=torch.empty((n, 4), device=dev), opacity_logits=torch.empty(n, device=dev),
+               sh=torch.empty(tuple(sc.sh.shape), device=dev))
+    p = lambda t: C.c_void_p(t.data_ptr())
+    L.check(L.lib().lgs_project_backward_batch(L.camera_array(cams), V, n, sc.sh_degree, *(p(t) for t in ps),
+                                               p(r_dev), p(g_dev), p(out["means3d"]), p(out["log_scales"]),
+                                               p(out["quats"]), p(out["opacity_logits"]), p(out["sh"]),
+                                               L.PROJ_BWD_CLEAR, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+            "lgs_project_backward_batch")
+    for k in want:
+        assert_grad_close(_np(out[k]), want[k], k, tol=1e-5)
+    assert not bool(g_dev.any()), "gradient records left nonzero"
+
+
 def test_l1_loss_kernel():
     rng = np.random.default_rng(3)
     x = rng.uniform(size=(3, 77, 131)).astype(np.float32)
