@@ -88,19 +88,23 @@ def test_project_backward_parity(cfg, n, view):
         assert_grad_close(_np(got[k]), want[k], k, tol=1e-5)
 
 
-@pytest.mark.parametrize("V,n,seed", [(16, 3001, 11), (5, 130, 12), (1, 777, 13), (16, 64, 14)])
-def test_project_backward_batch_sparse_views(V, n, seed):
-    """The batch backward of the projection lists, per 64 Gaussians, the
+@pytest.mark.parametrize("V,n,seed,cfg", [(16, 3001, 11, 5), (9, 500, 15, 4), (8, 300, 16, 5), (5, 130, 12, 5),
+                                          (1, 777, 13, 4), (16, 64, 14, 2)])
+def test_project_backward_batch_sparse_views(V, n, seed, cfg):
+    """The batch backward of the projection: up to 8 views one lane per
+    Gaussian loops over them; beyond, it lists, per 64 Gaussians, the
     (Gaussian, view) pairs whose gradient record is nonzero over a nonempty
     rectangle and takes them 64 at a time, several views of one Gaussian in
-    one round.  Against the oracle's single-view backward summed over the
-    views: sparse records (a Gaussian in no view, in some, or in nearly all),
-    nonzero records over empty rectangles (no contribution; cleared like the
-    others), n not a multiple of 64, and the records all zero afterwards."""
+    one round (two lists of 5 and 4 views with 9).  Against the oracle's
+    single-view backward summed over the views, at SH degrees 3 and 0: sparse
+    records (a Gaussian in no view, in some, or in nearly all), nonzero
+    records over empty rectangles (no contribution; cleared like the others),
+    n not a multiple of 64, and the records all zero afterwards.  Tolerance
+    1e-5 (1e-4 for the SH gradient summed in single precision by the loop)."""
     import ctypes as C
     from paper_2606_16566_amd import _lib as L
     from tests.test_gpu_batch import ring_cameras
-    sc = scenes.make_config(5, n=n)
+    sc = scenes.make_config(cfg, n=n)
     cams = ring_cameras([(64 + 16 * (v % 5), 48 + 8 * (v % 3)) for v in range(V)])
     rng = np.random.default_rng(seed)
     # per Gaussian, the share of views with a gradient: none, some, most
@@ -138,7 +142,11 @@ def test_project_backward_batch_sparse_views(V, n, seed):
                                                L.PROJ_BWD_CLEAR, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
             "lgs_project_backward_batch")
     for k in want:
-        assert_grad_close(_np(out[k]), want[k], k, tol=1e-5)
+        # up to 8 views the SH gradient is summed over the views in single
+        # precision (its stored precision): each view adds a rounded product
+        # to a rounded sum, 1e-4; everything else (and every sum of the
+        # listed pairs) in double, 1e-5
+        assert_grad_close(_np(out[k]), want[k], k, tol=1e-4 if (k == "sh" and V <= 8) else 1e-5)
     assert not bool(g_dev.any()), "gradient records left nonzero"
 
 
