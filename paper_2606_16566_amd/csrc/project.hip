@@ -737,7 +737,7 @@ __device__ __forceinline__ double from_lane(double x, int src4)
 //     view by view;
 //  2. rounds: the two lists, concatenated, are taken 64 pairs at a time by
 //     the two wavefronts in turn; a lane takes one pair (the Gaussian's
-//     parameters from its lane, its SH row from LDS, the camera of the view)
+//     parameters from its lane, its SH row and its view's camera from LDS)
 //     and adds its contribution to the Gaussian's LDS accumulators with
 //     double-precision LDS atomics (several views of one Gaussian may be
 //     taken at once; the single-precision LDS atomic add measured several
@@ -763,8 +763,18 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
     __shared__ double s_acc[kRawGradD][64];
     __shared__ uint16_t s_items[2][64 * kHalf];   // lane | view << 8, one list per wavefront
     __shared__ int s_w[2];
+    __shared__ Cam s_cam[kMaxViews];            // the cameras, read per lane by the pair's view
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
+    {
+        // (from the kernel argument once per workgroup: a lane's own view in
+        // a round would otherwise be a vector load of it, waited for at once)
+        constexpr int kCamWords = (int)(sizeof(Cam) / 4);
+        static_assert(sizeof(Cam) % 4 == 0, "whole words");
+        const int *src = reinterpret_cast<const int *>(cb.cam);
+        int *dst = reinterpret_cast<int *>(s_cam);
+        for (int e = threadIdx.x; e < cb.V * kCamWords; e += blockDim.x) dst[e] = src[e];
+    }
     const int64_t g0 = (int64_t)blockIdx.x * 64;
     const int cnt = (int)min((int64_t)64, n - g0);
     if (wid == 0) {
@@ -863,7 +873,7 @@ __global__ __launch_bounds__(128) void project_bwd_kernel(CamBatch cb, int64_t n
             const float gc3[3] = {gv[0], gv[1], gv[2]};
             const float gr3[3] = {gv[6], gv[7], gv[8]};
             RawGrad vg;
-            if (project_bwd_view<DEG, double>(cb.cam[v], m3o, Go, s_sh + gl * P, make_float2(gv[4], gv[5]), gc3, gv[3], gr3,
+            if (project_bwd_view<DEG, double>(s_cam[v], m3o, Go, s_sh + gl * P, make_float2(gv[4], gv[5]), gc3, gv[3], gr3,
                                       vg, s_dsh + gl, kDshStride)) {
                 for (int c = 0; c < 3; ++c) atomicAdd(&s_acc[c][gl], vg.m[c]);
                 for (int a = 0; a < 3; ++a)
