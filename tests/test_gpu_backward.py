@@ -88,15 +88,16 @@ def test_project_backward_parity(cfg, n, view):
         assert_grad_close(_np(got[k]), want[k], k, tol=1e-5)
 
 
-@pytest.mark.parametrize("V,n,seed,cfg", [(16, 3001, 11, 5), (9, 500, 15, 4), (8, 300, 16, 5), (5, 130, 12, 5),
-                                          (1, 777, 13, 4), (16, 64, 14, 2)])
-def test_project_backward_batch_sparse_views(V, n, seed, cfg):
+@pytest.mark.parametrize("V,n,seed,cfg,deg", [(16, 3001, 11, 5, 3), (9, 500, 15, 4, 0), (8, 300, 16, 5, 3),
+                                              (5, 130, 12, 5, 3), (1, 777, 13, 4, 0), (16, 64, 14, 2, 3),
+                                              (10, 700, 17, 5, 1), (12, 400, 18, 5, 2)])
+def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg):
     """The batch backward of the projection: up to 8 views one lane per
     Gaussian loops over them; beyond, it lists, per 64 Gaussians, the
     (Gaussian, view) pairs whose gradient record is nonzero over a nonempty
     rectangle and takes them 64 at a time, several views of one Gaussian in
     one round (two lists of 5 and 4 views with 9).  Against the oracle's
-    single-view backward summed over the views, at SH degrees 3 and 0: sparse
+    single-view backward summed over the views, at SH degrees 0 to 3: sparse
     records (a Gaussian in no view, in some, or in nearly all), nonzero
     records over empty rectangles (no contribution; cleared like the others),
     n not a multiple of 64, and the records all zero afterwards.  Tolerance
@@ -105,6 +106,8 @@ def test_project_backward_batch_sparse_views(V, n, seed, cfg):
     from paper_2606_16566_amd import _lib as L
     from tests.test_gpu_batch import ring_cameras
     sc = scenes.make_config(cfg, n=n)
+    sc.sh = np.ascontiguousarray(sc.sh[:, :(deg + 1) ** 2, :])        # lower degrees: the leading coefficients
+    assert sc.sh_degree == deg
     cams = ring_cameras([(64 + 16 * (v % 5), 48 + 8 * (v % 3)) for v in range(V)])
     rng = np.random.default_rng(seed)
     # per Gaussian, the share of views with a gradient: none, some, most
