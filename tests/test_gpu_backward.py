@@ -88,10 +88,12 @@ def test_project_backward_parity(cfg, n, view):
         assert_grad_close(_np(got[k]), want[k], k, tol=1e-5)
 
 
-@pytest.mark.parametrize("V,n,seed,cfg,deg", [(16, 3001, 11, 5, 3), (9, 500, 15, 4, 0), (8, 300, 16, 5, 3),
-                                              (5, 130, 12, 5, 3), (1, 777, 13, 4, 0), (16, 64, 14, 2, 3),
-                                              (10, 700, 17, 5, 1), (12, 400, 18, 5, 2)])
-def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg):
+@pytest.mark.parametrize("V,n,seed,cfg,deg,clear", [(16, 3001, 11, 5, 3, True), (9, 500, 15, 4, 0, True),
+                                                    (8, 300, 16, 5, 3, True), (5, 130, 12, 5, 3, True),
+                                                    (1, 777, 13, 4, 0, True), (16, 64, 14, 2, 3, True),
+                                                    (10, 700, 17, 5, 1, True), (12, 400, 18, 5, 2, True),
+                                                    (11, 900, 19, 5, 3, False), (4, 900, 20, 5, 3, False)])
+def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg, clear):
     """The batch backward of the projection: up to 8 views one lane per
     Gaussian loops over them; beyond, it lists, per 64 Gaussians, the
     (Gaussian, view) pairs whose gradient record is nonzero over a nonempty
@@ -100,7 +102,8 @@ def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg):
     single-view backward summed over the views, at SH degrees 0 to 3: sparse
     records (a Gaussian in no view, in some, or in nearly all), nonzero
     records over empty rectangles (no contribution; cleared like the others),
-    n not a multiple of 64, and the records all zero afterwards.  Tolerance
+    n not a multiple of 64, and the records all zero afterwards (untouched
+    without the clear flag).  Tolerance
     1e-5 (1e-4 for the SH gradient summed in single precision by the loop)."""
     import ctypes as C
     from paper_2606_16566_amd import _lib as L
@@ -142,7 +145,8 @@ def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg):
     L.check(L.lib().lgs_project_backward_batch(L.camera_array(cams), V, n, sc.sh_degree, *(p(t) for t in ps),
                                                p(r_dev), p(g_dev), p(out["means3d"]), p(out["log_scales"]),
                                                p(out["quats"]), p(out["opacity_logits"]), p(out["sh"]),
-                                               L.PROJ_BWD_CLEAR, C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                                               L.PROJ_BWD_CLEAR if clear else 0,
+                                               C.c_void_p(torch.cuda.current_stream().cuda_stream)),
             "lgs_project_backward_batch")
     for k in want:
         # up to 8 views the SH gradient is summed over the views in single
@@ -150,7 +154,10 @@ def test_project_backward_batch_sparse_views(V, n, seed, cfg, deg):
         # to a rounded sum, 1e-4; everything else (and every sum of the
         # listed pairs) in double, 1e-5
         assert_grad_close(_np(out[k]), want[k], k, tol=1e-4 if (k == "sh" and V <= 8) else 1e-5)
-    assert not bool(g_dev.any()), "gradient records left nonzero"
+    if clear:
+        assert not bool(g_dev.any()), "gradient records left nonzero"
+    else:
+        assert np.array_equal(_np(g_dev), rec.reshape(V * n, L.GRAD_FLOATS).astype(np.float64)), "records changed"
 
 
 def test_l1_loss_kernel():
