@@ -89,12 +89,16 @@ def _sync_np(t):
 # ---------------------------------------------------------------------------
 # projection
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("cfg,n,view", [(1, 10000, 0), (2, 20000, 0), (5, 20000, 2), (5, 20000, 7),
-                                        (2, 10003, 0), (5, 5, 1)])
-def test_project_parity(cfg, n, view):
+@pytest.mark.parametrize("cfg,n,view,deg", [(1, 10000, 0, None), (2, 20000, 0, None), (5, 20000, 2, None),
+                                            (5, 20000, 7, None), (2, 10003, 0, None), (5, 5, 1, None),
+                                            (2, 8000, 0, 1), (5, 8000, 4, 2)])
+def test_project_parity(cfg, n, view, deg):
     sc = scenes.make_config(cfg, n=n)
+    if deg is not None:                  # a lower SH degree: the leading coefficients
+        sc.sh = np.ascontiguousarray(sc.sh[:, :(deg + 1) ** 2, :])
+        assert sc.sh_degree == deg
     cam = sc.cameras[view]
-    print(f"project cfg={cfg} n={n} view={view}", flush=True)
+    print(f"project cfg={cfg} n={n} view={view} sh degree {sc.sh_degree}", flush=True)
     pr = R.project(cam, *scene_tensors(sc))
     ref = O.project_scene(sc, view)
     vis = ref["visible"] == 1
